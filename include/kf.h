@@ -1,0 +1,206 @@
+/* kf.h -- C ABI of the fused BLAS-1/BLAS-2 sequence engine for MI355X (gfx950).
+ *
+ * Method: Filipovic, Madzin, Fousek, Matyska, "Optimizing CUDA Code By Kernel
+ * Fusion -- Application on BLAS" (arXiv 1305.1183). A caller records a
+ * *script* of elementary BLAS-1/BLAS-2 calls over declared vectors, matrices
+ * and scalars (Section 4.1, Listing 1), the library builds the data-dependency
+ * graph, enumerates the legal fusions (Section 3.2, Section 4.2), picks a plan
+ * and compiles each kernel of the plan from gfx950 building blocks (Section
+ * 4.3, Algorithms 1 and 2) at run time with hipRTC. The plan then runs on the
+ * caller's HIP stream.
+ *
+ * Conventions
+ *  - Every function returns kf_status; KF_OK is 0, errors are negative.
+ *    kf_last_error() gives a thread-local message for the last failure.
+ *    Out-parameters are written only on KF_OK. No C++ exception crosses the ABI.
+ *  - All data is FP32. Matrices are row-major: element (i, j) of an
+ *    rows x cols matrix with leading dimension ld lives at ptr[i*ld + j]; a
+ *    matrix buffer holds rows*ld floats. ld must be >= cols and a multiple of
+ *    4, base pointers 16-byte aligned.
+ *    Columns cols..ld-1 are padding and are never read into a result nor
+ *    written. Vectors are dense, 16-byte aligned, any length >= 1.
+ *  - Values are SSA (Listing 1): each call returns a fresh value; declared
+ *    values are inputs and are never written. Outputs must not alias inputs.
+ *  - Ownership: the caller owns all device memory (operands, outputs and the
+ *    workspace). The library owns host metadata and the loaded code objects.
+ *  - A plan runs on one stream at a time; distinct plans are independent.
+ */
+#ifndef KF_H
+#define KF_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kf_status;
+enum {
+    KF_OK = 0,
+    KF_ERR_ARG = -1,         /* null pointer, bad enum, bad handle          */
+    KF_ERR_SHAPE = -2,       /* operand shapes do not match the call        */
+    KF_ERR_DTYPE = -3,       /* operand kind (vector/matrix/scalar) wrong    */
+    KF_ERR_ALIGN = -4,       /* pointer or leading dimension misaligned     */
+    KF_ERR_ALIAS = -5,       /* an output buffer overlaps an input buffer   */
+    KF_ERR_STATE = -6,       /* SSA violation, script already compiled, ... */
+    KF_ERR_UNBOUND = -7,     /* kf_run with a value or workspace not bound  */
+    KF_ERR_WORKSPACE = -8,   /* workspace smaller than kf_plan_workspace_bytes */
+    KF_ERR_COMPILE = -9,     /* hipRTC failed; the log is in kf_last_error  */
+    KF_ERR_HIP = -10,        /* a HIP runtime call failed                   */
+    KF_ERR_NOMEM = -11,      /* host allocation failed                      */
+    KF_ERR_UNSUPPORTED = -12,/* legal request this build does not handle    */
+    KF_ERR_INTERNAL = -13
+};
+
+typedef int32_t kf_value;
+#define KF_NONE ((kf_value)-1)
+
+typedef struct kf_script kf_script;
+typedef struct kf_plan kf_plan;
+typedef struct kf_planset kf_planset;
+
+/* Thread-local description of the last error (never NULL). */
+const char* kf_last_error(void);
+/* Library version string, e.g. "kfuse 0.1 gfx950". */
+const char* kf_version(void);
+
+/* ---- script recording (Section 4.1, Listing 1) ------------------------- */
+kf_status kf_script_create(kf_script** out);
+void kf_script_destroy(kf_script* s);
+
+/* Declarations. A vector has n >= 1 FP32 entries; a matrix is rows x cols
+ * row-major with leading dimension ld (0 = cols rounded up to a multiple of 4).
+ * kf_const is a host FP32 scalar passed to the kernels by value (rebindable
+ * with kf_set_const); kf_scalar is an FP32 scalar in device memory. */
+kf_status kf_vector(kf_script* s, int64_t n, kf_value* out);
+kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_value* out);
+kf_status kf_const(kf_script* s, float v, kf_value* out);
+kf_status kf_scalar(kf_script* s, kf_value* out);
+/* Listing 1 `input` and `return`. Declared values must be marked input before
+ * they are used; any value may be marked output (results are written to the
+ * buffer bound to it). */
+kf_status kf_input(kf_script* s, kf_value v);
+kf_status kf_output(kf_script* s, kf_value v);
+
+/* Elementary calls (all out-of-place, Section 3.3 and Table 1). alpha and beta
+ * are scalar values (kf_const, kf_scalar or a kf_dot result).
+ *   kf_scal : y = alpha x                            (BLAS-1 map)
+ *   kf_axpy : z = alpha x + y                        (BLAS-1 map)
+ *   kf_dot  : r = x^T y          (device scalar)     (map + reduce)
+ *   kf_gemv : y = alpha A x + beta y0    (y0 may be KF_NONE; eq. (2))
+ *   kf_gemtv: y = alpha A^T x + beta y0  (A viewed as a list of columns)
+ *   kf_ger  : B = A + alpha u v^T        (rank-1 update; B gets ld of A's
+ *                                         cols rounded up to a multiple of 4) */
+kf_status kf_scal(kf_script* s, kf_value alpha, kf_value x, kf_value* y);
+kf_status kf_axpy(kf_script* s, kf_value alpha, kf_value x, kf_value y, kf_value* z);
+kf_status kf_dot(kf_script* s, kf_value x, kf_value y, kf_value* r);
+kf_status kf_gemv(kf_script* s, kf_value alpha, kf_value A, kf_value x, kf_value beta,
+                  kf_value y0, kf_value* y);
+kf_status kf_gemtv(kf_script* s, kf_value alpha, kf_value A, kf_value x, kf_value beta,
+                   kf_value y0, kf_value* y);
+kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value v,
+                 kf_value* B);
+
+/* Shape of a value: kind 0 vector (d0 = n), 1 matrix (d0 = rows, d1 = cols,
+ * d2 = ld), 2 const scalar, 3 device scalar. */
+kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* d0,
+                        int64_t* d1, int64_t* d2);
+kf_status kf_script_num_calls(const kf_script* s, int32_t* n);
+
+/* ---- compilation (Section 4.2: fusions, implementations, combinations) -- */
+enum {
+    KF_MODE_UNFUSED = 0,      /* one kernel per call                           */
+    KF_MODE_FUSED = 1,        /* the legal partition with fewest kernels       */
+    KF_MODE_ADDITIVE = 2,     /* best plan by the additive routine predictor   */
+    KF_MODE_LEARNED = 3,      /* best plan by the learned MLP cost model       */
+    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate on the GPU, keep fastest */
+    KF_MODE_PARTITION = 5     /* the partition given in opts.partition         */
+};
+enum {
+    KF_COMPILE_NO_LOAD = 1    /* stop after hipRTC (no GPU needed): build checks */
+};
+typedef struct kf_compile_opts {
+    int32_t mode;            /* KF_MODE_*                                         */
+    int32_t flags;           /* KF_COMPILE_*                                      */
+    /* Implementation parameters; 0 = library default for the shape.
+     * mat_k: float4 columns per lane (1, 2, 4); mat_waves: waves per workgroup
+     * (1..16); mat_group: rows per wave step (1, 2, 4, 8, 16); mat_rows: rows
+     * per workgroup (multiple of mat_waves*mat_group). vec_unroll: float4 per
+     * thread per step (1, 2, 4, 8); vec_threads: 64..1024; vec_grid: max
+     * workgroups (grid-stride beyond). */
+    int32_t mat_k, mat_waves, mat_group, mat_rows;
+    int32_t vec_unroll, vec_threads, vec_grid;
+    /* KF_MODE_PARTITION: partition[i] = kernel id of call i (calls numbered in
+     * recording order), ids 0..K-1. */
+    const int32_t* partition;
+    int32_t partition_len;
+    int32_t reserved[8];
+} kf_compile_opts;
+
+/* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
+void kf_compile_opts_init(kf_compile_opts* o);
+/* Compile a plan. The plan deep-copies what it needs from the script. */
+kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** out);
+void kf_plan_destroy(kf_plan* p);
+
+/* ---- plan-space enumeration (Section 4.2) ------------------------------- */
+/* Enumerate the legal partitions of the script's calls into kernels (rules of
+ * Section 3.2: same iteration space, no reduction result consumed in the
+ * kernel that computes it, convex and acyclic, fusions must share data),
+ * at most max_plans of them, fewest kernels first. */
+kf_status kf_enumerate(const kf_script* s, int32_t max_plans, kf_planset** out);
+void kf_planset_destroy(kf_planset* ps);
+kf_status kf_planset_count(const kf_planset* ps, int32_t* n);
+/* partition[call] = kernel id for plan i (len = number of calls). */
+kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, int32_t len);
+
+/* ---- bind and run --------------------------------------------------------- */
+/* Bytes of device workspace the plan needs: partial sums of reductions and
+ * intermediate values that a later kernel of the plan reads from HBM. */
+kf_status kf_plan_workspace_bytes(const kf_plan* p, size_t* bytes);
+/* Bind a device buffer to a vector, matrix or device-scalar value. Checks
+ * alignment and, for outputs, overlap with every bound input. */
+kf_status kf_bind(kf_plan* p, kf_value v, void* dev_ptr);
+kf_status kf_bind_workspace(kf_plan* p, void* dev_ptr, size_t bytes);
+/* Change a kf_const value without recompiling. */
+kf_status kf_set_const(kf_plan* p, kf_value v, float value);
+/* Launch every kernel of the plan on `stream` (a hipStream_t; NULL = the null
+ * stream). Asynchronous; allocates nothing and keeps no state on the device
+ * between runs, so repeated runs and graph replays need no preparation. A
+ * kernel whose reductions span several workgroups is two launches: the main
+ * pass writes partial sums to the workspace, a small second pass adds them
+ * in a fixed order (the final reduction "by extra kernel", Section 3.2.2). */
+kf_status kf_run(kf_plan* p, void* stream);
+/* Launch only kernel k of the plan (in plan order), e.g. to time one kernel.
+ * Its inputs must already hold valid data. */
+kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream);
+/* Time the plan: `warmup` untimed runs, then `reps` runs each bracketed by HIP
+ * events; returns the median in microseconds. Synchronises the stream. */
+kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps,
+                       float* median_us);
+
+/* ---- introspection -------------------------------------------------------- */
+/* JSON description (kernels, calls, parameters, grid, bytes). Writes at most
+ * cap bytes (NUL-terminated) and the needed size to *needed. */
+kf_status kf_plan_describe(const kf_plan* p, char* buf, size_t cap, size_t* needed);
+/* Algorithmic HBM bytes of one run: every operand counted once per kernel
+ * that reads or writes it in HBM (the paper's "really transferred" bytes,
+ * Section 5.2); workspace traffic is excluded. */
+kf_status kf_plan_bytes(const kf_plan* p, uint64_t* read, uint64_t* written);
+kf_status kf_plan_num_kernels(const kf_plan* p, int32_t* n);
+/* HIP source of kernel k of the plan (for inspection and tests). */
+kf_status kf_plan_source(const kf_plan* p, int32_t k, char* buf, size_t cap, size_t* needed);
+/* Launch geometry of kernel k: grid (workgroups) and block (threads). */
+kf_status kf_plan_kernel_geometry(const kf_plan* p, int32_t k, int32_t* grid, int32_t* block);
+
+/* ---- measurement helper -------------------------------------------------- */
+/* dst[0..bytes) = src[0..bytes) with a plain streaming kernel (128-bit
+ * non-temporal loads and stores) on `stream`; bytes and both pointers must be
+ * multiples of 16. Used to calibrate memory-traffic counters against a copy of
+ * known size. */
+kf_status kf_util_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KF_H */

@@ -1,0 +1,717 @@
+// api.cpp -- the C ABI: script recording, compilation, binding and launch.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <sstream>
+
+#include "kf_internal.h"
+
+namespace kf {
+
+static thread_local std::string g_err = "no error";
+
+kf_status set_error(kf_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+// Loaded kernels, by generated name (a hash of the kernel text). Modules stay
+// loaded for the life of the process so plans can share kernels.
+struct Registry {
+    std::mutex mu;
+    std::map<std::string, hipFunction_t> funcs;
+    std::map<std::string, std::string> code;     // name -> code object (no-load mode)
+    std::vector<hipModule_t> modules;
+};
+static Registry& registry() {
+    static Registry* r = new Registry();  // never destroyed: modules outlive static dtors
+    return *r;
+}
+
+}  // namespace kf
+
+using namespace kf;
+
+struct PlanKernel {
+    KernelCode code;
+    std::vector<hipFunction_t> fns;   // one per launch
+    size_t ws_off = 0;   // bytes from workspace base to this kernel's partial sums
+};
+
+struct kf_plan {
+    Script s;
+    std::vector<int> part;
+    std::vector<PlanKernel> ks;
+    std::vector<void*> bind;          // per value (caller buffers)
+    std::vector<float> consts;        // per value (kf_const)
+    std::vector<size_t> inter_off;    // per value: workspace offset of intermediates, or SIZE_MAX
+    std::vector<char> is_read, is_written;
+    void* ws = nullptr;
+    size_t ws_bound = 0;
+    size_t ws_need = 0;
+    bool loaded = false;
+    int mode = 0;
+};
+
+static const char* kVersion = "kfuse 0.1 gfx950";
+
+#define KF_TRY(...)                                                                   \
+    try {                                                                             \
+        __VA_ARGS__;                                                                  \
+    } catch (const std::bad_alloc&) {                                                 \
+        return set_error(KF_ERR_NOMEM, "host allocation failed");                     \
+    } catch (const std::exception& ex) {                                              \
+        return set_error(KF_ERR_INTERNAL, std::string("internal error: ") + ex.what()); \
+    } catch (...) {                                                                   \
+        return set_error(KF_ERR_INTERNAL, "internal error");                           \
+    }
+
+extern "C" {
+
+const char* kf_last_error(void) { return g_err.c_str(); }
+const char* kf_version(void) { return kVersion; }
+
+kf_status kf_script_create(kf_script** out) {
+    if (!out) return set_error(KF_ERR_ARG, "null out");
+    KF_TRY(*out = new kf_script());
+    return KF_OK;
+}
+
+void kf_script_destroy(kf_script* s) { delete s; }
+
+static bool valid_value(const kf_script* s, kf_value v) {
+    return s && v >= 0 && v < (kf_value)s->s.values.size();
+}
+
+static kf_status add_value(kf_script* s, const Value& v, kf_value* out) {
+    if (!s || !out) return set_error(KF_ERR_ARG, "null argument");
+    KF_TRY(s->s.values.push_back(v));
+    *out = (kf_value)s->s.values.size() - 1;
+    return KF_OK;
+}
+
+kf_status kf_vector(kf_script* s, int64_t n, kf_value* out) {
+    if (n < 1) return set_error(KF_ERR_SHAPE, "vector length must be >= 1");
+    Value v;
+    v.kind = VK::Vec;
+    v.n = n;
+    return add_value(s, v, out);
+}
+
+kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_value* out) {
+    if (rows < 1 || cols < 1) return set_error(KF_ERR_SHAPE, "matrix dimensions must be >= 1");
+    if (ld == 0) ld = (cols + 3) / 4 * 4;
+    if (ld < cols) return set_error(KF_ERR_SHAPE, "ld < cols");
+    if (ld % 4) return set_error(KF_ERR_ALIGN, "ld must be a multiple of 4 floats");
+    Value v;
+    v.kind = VK::Mat;
+    v.rows = rows;
+    v.cols = cols;
+    v.ld = ld;
+    return add_value(s, v, out);
+}
+
+kf_status kf_const(kf_script* s, float c, kf_value* out) {
+    Value v;
+    v.kind = VK::Const;
+    v.cval = c;
+    v.input = true;
+    return add_value(s, v, out);
+}
+
+kf_status kf_scalar(kf_script* s, kf_value* out) {
+    Value v;
+    v.kind = VK::DevScalar;
+    return add_value(s, v, out);
+}
+
+kf_status kf_input(kf_script* s, kf_value v) {
+    if (!valid_value(s, v)) return set_error(KF_ERR_ARG, "bad value handle");
+    Value& x = s->s.values[v];
+    if (x.producer >= 0) return set_error(KF_ERR_STATE, "a computed value cannot be an input");
+    x.input = true;
+    return KF_OK;
+}
+
+kf_status kf_output(kf_script* s, kf_value v) {
+    if (!valid_value(s, v)) return set_error(KF_ERR_ARG, "bad value handle");
+    Value& x = s->s.values[v];
+    if (x.producer < 0) return set_error(KF_ERR_STATE, "only computed values can be outputs");
+    x.output = true;
+    return KF_OK;
+}
+
+// Checks shared by the call recorders.
+static kf_status need(const kf_script* s, kf_value v, VK kind, const char* what) {
+    if (!valid_value(s, v)) return set_error(KF_ERR_ARG, std::string("bad handle for ") + what);
+    const Value& x = s->s.values[v];
+    bool ok = x.kind == kind || (kind == VK::Const && x.kind == VK::DevScalar);
+    if (!ok) return set_error(KF_ERR_DTYPE, std::string(what) + " has the wrong kind");
+    if (x.producer < 0 && !x.input)
+        return set_error(KF_ERR_STATE, std::string(what) + " is declared but not marked input");
+    return KF_OK;
+}
+
+static kf_status record(kf_script* s, const Call& c, const Value& outv, kf_value* out) {
+    if (!out) return set_error(KF_ERR_ARG, "null out");
+    KF_TRY({
+        Value v = outv;
+        v.producer = (int)s->s.calls.size();
+        s->s.values.push_back(v);
+        Call k = c;
+        k.out = (int)s->s.values.size() - 1;
+        s->s.calls.push_back(k);
+        int ci = (int)s->s.calls.size() - 1;
+        int ops[5] = {k.alpha, k.beta, k.in[0], k.in[1], k.in[2]};
+        for (int o : ops)
+            if (o >= 0) s->s.values[o].consumers.push_back(ci);
+        *out = k.out;
+    });
+    return KF_OK;
+}
+
+#define CHECK(e)                        \
+    do {                                \
+        kf_status st__ = (e);           \
+        if (st__ != KF_OK) return st__; \
+    } while (0)
+
+kf_status kf_scal(kf_script* s, kf_value alpha, kf_value x, kf_value* y) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    CHECK(need(s, alpha, VK::Const, "alpha"));
+    CHECK(need(s, x, VK::Vec, "x"));
+    Call c;
+    c.op = Op::Scal;
+    c.alpha = alpha;
+    c.in[0] = x;
+    Value o;
+    o.kind = VK::Vec;
+    o.n = s->s.values[x].n;
+    return record(s, c, o, y);
+}
+
+kf_status kf_axpy(kf_script* s, kf_value alpha, kf_value x, kf_value y, kf_value* z) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    CHECK(need(s, alpha, VK::Const, "alpha"));
+    CHECK(need(s, x, VK::Vec, "x"));
+    CHECK(need(s, y, VK::Vec, "y"));
+    if (s->s.values[x].n != s->s.values[y].n) return set_error(KF_ERR_SHAPE, "axpy: x and y lengths differ");
+    Call c;
+    c.op = Op::Axpy;
+    c.alpha = alpha;
+    c.in[0] = x;
+    c.in[1] = y;
+    Value o;
+    o.kind = VK::Vec;
+    o.n = s->s.values[x].n;
+    return record(s, c, o, z);
+}
+
+kf_status kf_dot(kf_script* s, kf_value x, kf_value y, kf_value* r) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    CHECK(need(s, x, VK::Vec, "x"));
+    CHECK(need(s, y, VK::Vec, "y"));
+    if (s->s.values[x].n != s->s.values[y].n) return set_error(KF_ERR_SHAPE, "dot: x and y lengths differ");
+    Call c;
+    c.op = Op::Dot;
+    c.in[0] = x;
+    c.in[1] = y;
+    Value o;
+    o.kind = VK::DevScalar;
+    return record(s, c, o, r);
+}
+
+static kf_status rec_gemv(kf_script* s, bool trans, kf_value alpha, kf_value A, kf_value x,
+                          kf_value beta, kf_value y0, kf_value* y) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    CHECK(need(s, alpha, VK::Const, "alpha"));
+    CHECK(need(s, A, VK::Mat, "A"));
+    CHECK(need(s, x, VK::Vec, "x"));
+    const Value& Av = s->s.values[A];
+    int64_t nin = trans ? Av.rows : Av.cols, nout = trans ? Av.cols : Av.rows;
+    if (s->s.values[x].n != nin) return set_error(KF_ERR_SHAPE, "gemv: x length does not match A");
+    if (y0 != KF_NONE) {
+        CHECK(need(s, y0, VK::Vec, "y0"));
+        if (s->s.values[y0].n != nout) return set_error(KF_ERR_SHAPE, "gemv: y0 length does not match A");
+        if (beta == KF_NONE) return set_error(KF_ERR_ARG, "gemv: y0 given without beta");
+        CHECK(need(s, beta, VK::Const, "beta"));
+    }
+    Call c;
+    c.op = trans ? Op::Gemtv : Op::Gemv;
+    c.alpha = alpha;
+    c.beta = y0 != KF_NONE ? beta : -1;
+    c.in[0] = A;
+    c.in[1] = x;
+    c.in[2] = y0 != KF_NONE ? y0 : -1;
+    Value o;
+    o.kind = VK::Vec;
+    o.n = nout;
+    return record(s, c, o, y);
+}
+
+kf_status kf_gemv(kf_script* s, kf_value alpha, kf_value A, kf_value x, kf_value beta,
+                  kf_value y0, kf_value* y) {
+    return rec_gemv(s, false, alpha, A, x, beta, y0, y);
+}
+
+kf_status kf_gemtv(kf_script* s, kf_value alpha, kf_value A, kf_value x, kf_value beta,
+                   kf_value y0, kf_value* y) {
+    return rec_gemv(s, true, alpha, A, x, beta, y0, y);
+}
+
+kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value v, kf_value* B) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    CHECK(need(s, alpha, VK::Const, "alpha"));
+    CHECK(need(s, A, VK::Mat, "A"));
+    CHECK(need(s, u, VK::Vec, "u"));
+    CHECK(need(s, v, VK::Vec, "v"));
+    const Value& Av = s->s.values[A];
+    if (s->s.values[u].n != Av.rows || s->s.values[v].n != Av.cols)
+        return set_error(KF_ERR_SHAPE, "ger: u/v lengths do not match A");
+    Call c;
+    c.op = Op::Ger;
+    c.alpha = alpha;
+    c.in[0] = A;
+    c.in[1] = u;
+    c.in[2] = v;
+    Value o;
+    o.kind = VK::Mat;
+    o.rows = Av.rows;
+    o.cols = Av.cols;
+    o.ld = (Av.cols + 3) / 4 * 4;
+    return record(s, c, o, B);
+}
+
+kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* d0, int64_t* d1,
+                        int64_t* d2) {
+    if (!valid_value(s, v)) return set_error(KF_ERR_ARG, "bad value handle");
+    const Value& x = s->s.values[v];
+    if (kind) *kind = (int32_t)x.kind;
+    if (d0) *d0 = x.kind == VK::Mat ? x.rows : x.n;
+    if (d1) *d1 = x.cols;
+    if (d2) *d2 = x.ld;
+    return KF_OK;
+}
+
+kf_status kf_script_num_calls(const kf_script* s, int32_t* n) {
+    if (!s || !n) return set_error(KF_ERR_ARG, "null argument");
+    *n = (int32_t)s->s.calls.size();
+    return KF_OK;
+}
+
+void kf_compile_opts_init(kf_compile_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->mode = KF_MODE_FUSED;
+}
+
+kf_status kf_enumerate(const kf_script* s, int32_t max_plans, kf_planset** out) {
+    if (!s || !out) return set_error(KF_ERR_ARG, "null argument");
+    if (s->s.calls.empty()) return set_error(KF_ERR_STATE, "script has no calls");
+    KF_TRY({
+        auto* ps = new kf_planset();
+        ps->parts = enumerate_partitions(s->s, max_plans);
+        *out = ps;
+    });
+    return KF_OK;
+}
+
+void kf_planset_destroy(kf_planset* ps) { delete ps; }
+
+kf_status kf_planset_count(const kf_planset* ps, int32_t* n) {
+    if (!ps || !n) return set_error(KF_ERR_ARG, "null argument");
+    *n = (int32_t)ps->parts.size();
+    return KF_OK;
+}
+
+kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, int32_t len) {
+    if (!ps || !partition) return set_error(KF_ERR_ARG, "null argument");
+    if (i < 0 || i >= (int32_t)ps->parts.size()) return set_error(KF_ERR_ARG, "plan index out of range");
+    if (len < (int32_t)ps->parts[i].size()) return set_error(KF_ERR_ARG, "partition buffer too small");
+    for (size_t c = 0; c < ps->parts[i].size(); ++c) partition[c] = ps->parts[i][c];
+    return KF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// compilation
+// ---------------------------------------------------------------------------
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static size_t value_bytes(const Value& v) {
+    switch (v.kind) {
+        case VK::Vec: return (size_t)v.n * 4;
+        case VK::Mat: return (size_t)v.rows * v.ld * 4;
+        case VK::DevScalar: return 4;
+        default: return 0;
+    }
+}
+
+static kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_compile_opts& o,
+                            kf_plan** out) {
+    const int ncall = (int)sc.calls.size();
+    if ((int)part.size() != ncall) return set_error(KF_ERR_ARG, "partition length != number of calls");
+    int nk = 0;
+    for (int k : part) {
+        if (k < 0) return set_error(KF_ERR_ARG, "negative kernel id in partition");
+        nk = std::max(nk, k + 1);
+    }
+    std::vector<std::vector<int>> members(nk);
+    for (int c = 0; c < ncall; ++c) members[part[c]].push_back(c);
+    for (int k = 0; k < nk; ++k) {
+        if (members[k].empty()) return set_error(KF_ERR_ARG, "partition kernel ids must be dense");
+        std::string why = block_illegal_reason(sc, members[k]);
+        if (members[k].size() > 1 && !why.empty())
+            return set_error(KF_ERR_UNSUPPORTED, "illegal fusion: " + why);
+    }
+    if (!partition_acyclic(sc, part, nk)) return set_error(KF_ERR_UNSUPPORTED, "illegal plan: kernels form a cycle");
+
+    auto* p = new kf_plan();
+    std::unique_ptr<kf_plan> guard(p);
+    p->s = sc;
+    p->part = part;
+    p->mode = o.mode;
+    const size_t nv = sc.values.size();
+    p->bind.assign(nv, nullptr);
+    p->consts.assign(nv, 0.f);
+    p->inter_off.assign(nv, SIZE_MAX);
+    p->is_read.assign(nv, 0);
+    p->is_written.assign(nv, 0);
+    for (size_t v = 0; v < nv; ++v)
+        if (sc.values[v].kind == VK::Const) p->consts[v] = sc.values[v].cval;
+
+    MatParams mp;
+    mp.k = o.mat_k;
+    mp.waves = o.mat_waves;
+    mp.group = o.mat_group;
+    mp.rows = o.mat_rows;
+    VecParams vp;
+    vp.unroll = o.vec_unroll;
+    vp.threads = o.vec_threads;
+    vp.grid = o.vec_grid;
+    if (mp.k && mp.k != 1 && mp.k != 2 && mp.k != 4) return set_error(KF_ERR_ARG, "mat_k must be 1, 2 or 4");
+    if (mp.waves && (mp.waves < 1 || mp.waves > 16)) return set_error(KF_ERR_ARG, "mat_waves must be 1..16");
+    if (mp.group && (mp.group & (mp.group - 1) || mp.group > 16)) return set_error(KF_ERR_ARG, "mat_group must be 1, 2, 4, 8 or 16");
+    if (vp.unroll && (vp.unroll < 1 || vp.unroll > 8)) return set_error(KF_ERR_ARG, "vec_unroll must be 1..8");
+    if (vp.threads && (vp.threads < 64 || vp.threads > 1024 || vp.threads % 64)) return set_error(KF_ERR_ARG, "vec_threads must be a multiple of 64 in 64..1024");
+    if (vp.grid < 0) return set_error(KF_ERR_ARG, "vec_grid must be >= 0");
+
+    auto order = kernels_in_order(sc, part);
+    for (auto& calls : order) {
+        PlanKernel pk;
+        Space sp = call_space(sc, calls[0]);
+        if (sp.mat) {
+            MatParams q = default_mat_params(sp.a, sp.b, mp);
+            if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_waves * mat_group");
+        }
+        pk.code = generate_kernel(sc, calls, part, mp, vp);
+        if (pk.code.lds_bytes > 64 * 1024)
+            return set_error(KF_ERR_ARG, "parameters need " + std::to_string(pk.code.lds_bytes) +
+                                             " bytes of LDS per workgroup (limit 65536)");
+        for (const Launch& l : pk.code.launches)
+            for (const KArg& a : l.args) {
+                if (a.kind == ArgKind::MatIn || a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn) p->is_read[a.value] = 1;
+                if (a.kind == ArgKind::MatOut || a.kind == ArgKind::VecOut || a.kind == ArgKind::DevScalarOut) p->is_written[a.value] = 1;
+            }
+        p->ks.push_back(std::move(pk));
+    }
+    // workspace: partial sums, then intermediates kept in HBM
+    size_t off = 0;
+    for (auto& k : p->ks) { k.ws_off = off; off = align_up(off + k.code.ws_floats * 4, 256); }
+    for (size_t v = 0; v < nv; ++v) {
+        const Value& x = sc.values[v];
+        if (x.producer >= 0 && !x.output && p->is_written[v]) {
+            p->inter_off[v] = off;
+            off = align_up(off + value_bytes(x), 256);
+        }
+    }
+    p->ws_need = off;
+
+    // compile (and load) the kernels not yet known
+    Registry& reg = registry();
+    std::lock_guard<std::mutex> lock(reg.mu);
+    const bool load = !(o.flags & KF_COMPILE_NO_LOAD);
+    std::vector<const KernelCode*> todo;
+    std::set<std::string> names;
+    for (auto& k : p->ks) {
+        bool have = load ? reg.funcs.count(k.code.name) : reg.code.count(k.code.name);
+        if (!have && names.insert(k.code.name).second) todo.push_back(&k.code);
+    }
+    if (!todo.empty()) {
+        std::string co, log;
+        if (!jit_compile(todo, &co, &log)) return set_error(KF_ERR_COMPILE, log);
+        if (load) {
+            hipModule_t mod = nullptr;
+            hipError_t e = hipModuleLoadData(&mod, co.data());
+            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+            reg.modules.push_back(mod);
+            for (const KernelCode* k : todo)
+                for (const Launch& l : k->launches) {
+                    hipFunction_t fn = nullptr;
+                    e = hipModuleGetFunction(&fn, mod, l.name.c_str());
+                    if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+                    reg.funcs[l.name] = fn;
+                }
+        } else {
+            for (const KernelCode* k : todo) reg.code[k->name] = "compiled";
+        }
+    }
+    if (load)
+        for (auto& k : p->ks)
+            for (const Launch& l : k.code.launches) k.fns.push_back(reg.funcs[l.name]);
+    p->loaded = load;
+    *out = guard.release();
+    return KF_OK;
+}
+
+extern "C" {
+
+kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** out) {
+    if (!s || !out) return set_error(KF_ERR_ARG, "null argument");
+    if (s->s.calls.empty()) return set_error(KF_ERR_STATE, "script has no calls");
+    kf_compile_opts o;
+    kf_compile_opts_init(&o);
+    if (opts) o = *opts;
+    std::vector<int> part;
+    KF_TRY({
+        switch (o.mode) {
+            case KF_MODE_UNFUSED: part = unfused_partition(s->s); break;
+            case KF_MODE_FUSED: part = fused_partition(s->s); break;
+            case KF_MODE_PARTITION:
+                if (!o.partition || o.partition_len != (int32_t)s->s.calls.size())
+                    return set_error(KF_ERR_ARG, "partition missing or of the wrong length");
+                part.assign(o.partition, o.partition + o.partition_len);
+                break;
+            case KF_MODE_ADDITIVE:
+            case KF_MODE_LEARNED:
+            case KF_MODE_EXHAUSTIVE:
+                return set_error(KF_ERR_UNSUPPORTED, "search modes are selected through kf_search");
+            default: return set_error(KF_ERR_ARG, "unknown mode");
+        }
+        return build_plan(s->s, part, o, out);
+    });
+    return KF_OK;
+}
+
+void kf_plan_destroy(kf_plan* p) { delete p; }
+
+kf_status kf_plan_workspace_bytes(const kf_plan* p, size_t* bytes) {
+    if (!p || !bytes) return set_error(KF_ERR_ARG, "null argument");
+    *bytes = p->ws_need;
+    return KF_OK;
+}
+
+static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+kf_status kf_bind(kf_plan* p, kf_value v, void* ptr) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (v < 0 || v >= (kf_value)p->s.values.size()) return set_error(KF_ERR_ARG, "bad value handle");
+    const Value& x = p->s.values[v];
+    if (x.kind == VK::Const) return set_error(KF_ERR_DTYPE, "constants are set with kf_set_const");
+    if (x.producer >= 0 && !x.output)
+        return set_error(KF_ERR_ARG, "intermediate values live in the plan workspace");
+    if (!ptr) return set_error(KF_ERR_ARG, "null device pointer");
+    size_t al = x.kind == VK::DevScalar ? 4 : 16;
+    if ((uintptr_t)ptr % al) return set_error(KF_ERR_ALIGN, "device pointer misaligned");
+    const size_t nb = value_bytes(x);
+    // an output must not overlap any other bound value
+    for (size_t w = 0; w < p->s.values.size(); ++w) {
+        if ((kf_value)w == v || !p->bind[w]) continue;
+        const Value& y = p->s.values[w];
+        bool vw = x.producer >= 0, ww = y.producer >= 0;
+        if ((vw || ww) && overlap(ptr, nb, p->bind[w], value_bytes(y)))
+            return set_error(KF_ERR_ALIAS, "an output buffer overlaps another operand");
+    }
+    p->bind[v] = ptr;
+    return KF_OK;
+}
+
+kf_status kf_bind_workspace(kf_plan* p, void* ptr, size_t bytes) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (bytes < p->ws_need) return set_error(KF_ERR_WORKSPACE, "workspace smaller than kf_plan_workspace_bytes");
+    if (p->ws_need && !ptr) return set_error(KF_ERR_ARG, "null workspace");
+    if ((uintptr_t)ptr % 256) return set_error(KF_ERR_ALIGN, "workspace must be 256-byte aligned");
+    p->ws = ptr;
+    p->ws_bound = bytes;
+    return KF_OK;
+}
+
+kf_status kf_set_const(kf_plan* p, kf_value v, float value) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (v < 0 || v >= (kf_value)p->s.values.size()) return set_error(KF_ERR_ARG, "bad value handle");
+    if (p->s.values[v].kind != VK::Const) return set_error(KF_ERR_DTYPE, "not a constant");
+    p->consts[v] = value;
+    return KF_OK;
+}
+
+static void* value_ptr(kf_plan* p, int v) {
+    if (p->inter_off[v] != SIZE_MAX) return (char*)p->ws + p->inter_off[v];
+    return p->bind[v];
+}
+
+static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream) {
+    for (size_t li = 0; li < k.code.launches.size(); ++li) {
+        const Launch& l = k.code.launches[li];
+        const size_t na = l.args.size();
+        uint64_t store[64];
+        void* ptrs[64];
+        if (na > 64) return set_error(KF_ERR_INTERNAL, "too many kernel arguments");
+        for (size_t i = 0; i < na; ++i) {
+            const KArg& a = l.args[i];
+            store[i] = 0;
+            switch (a.kind) {
+                case ArgKind::ConstScalar: {
+                    float f = p->consts[a.value];
+                    std::memcpy(&store[i], &f, 4);
+                    break;
+                }
+                case ArgKind::Workspace: store[i] = (uint64_t)(uintptr_t)((char*)p->ws + k.ws_off); break;
+                default: {
+                    void* q = value_ptr(p, a.value);
+                    if (!q) return set_error(KF_ERR_UNBOUND, "value " + std::to_string(a.value) + " is not bound");
+                    store[i] = (uint64_t)(uintptr_t)q;
+                }
+            }
+            ptrs[i] = &store[i];
+        }
+        hipError_t e = hipModuleLaunchKernel(k.fns[li], (unsigned)l.grid, 1, 1, (unsigned)l.block, 1, 1, 0,
+                                             stream, ptrs, nullptr);
+        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    }
+    return KF_OK;
+}
+
+static kf_status check_runnable(const kf_plan* p) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (!p->loaded) return set_error(KF_ERR_STATE, "plan compiled without loading");
+    if (p->ws_need && !p->ws) return set_error(KF_ERR_UNBOUND, "workspace not bound");
+    return KF_OK;
+}
+
+kf_status kf_run(kf_plan* p, void* stream) {
+    CHECK(check_runnable(p));
+    for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream));
+    return KF_OK;
+}
+
+kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream) {
+    CHECK(check_runnable(p));
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    return launch_kernel(p, p->ks[k], (hipStream_t)stream);
+}
+
+kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps, float* median_us) {
+    if (!p || !median_us || reps < 1 || warmup < 0) return set_error(KF_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    for (int i = 0; i < warmup; ++i) CHECK(kf_run(p, stream));
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return set_error(KF_ERR_HIP, "hipEventCreate");
+    kf_status st_out = KF_OK;
+    for (int i = 0; i < reps && st_out == KF_OK; ++i) {
+        if (hipEventRecord(ev[2 * i], st) != hipSuccess) { st_out = set_error(KF_ERR_HIP, "hipEventRecord"); break; }
+        st_out = kf_run(p, stream);
+        if (st_out == KF_OK && hipEventRecord(ev[2 * i + 1], st) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipEventRecord");
+    }
+    std::vector<float> t;
+    if (st_out == KF_OK) {
+        if (hipStreamSynchronize(st) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipStreamSynchronize");
+        for (int i = 0; i < reps && st_out == KF_OK; ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipEventElapsedTime");
+            t.push_back(ms * 1000.f);
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (st_out != KF_OK) return st_out;
+    std::sort(t.begin(), t.end());
+    *median_us = t.size() % 2 ? t[t.size() / 2] : 0.5f * (t[t.size() / 2 - 1] + t[t.size() / 2]);
+    return KF_OK;
+}
+
+kf_status kf_plan_bytes(const kf_plan* p, uint64_t* rd, uint64_t* wr) {
+    if (!p || !rd || !wr) return set_error(KF_ERR_ARG, "null argument");
+    uint64_t r = 0, w = 0;
+    for (auto& k : p->ks) { r += k.code.bytes_read; w += k.code.bytes_written; }
+    *rd = r;
+    *wr = w;
+    return KF_OK;
+}
+
+kf_status kf_plan_num_kernels(const kf_plan* p, int32_t* n) {
+    if (!p || !n) return set_error(KF_ERR_ARG, "null argument");
+    *n = (int32_t)p->ks.size();
+    return KF_OK;
+}
+
+static kf_status copy_out(const std::string& s, char* buf, size_t cap, size_t* needed) {
+    if (needed) *needed = s.size() + 1;
+    if (buf && cap) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return KF_OK;
+}
+
+kf_status kf_plan_source(const kf_plan* p, int32_t k, char* buf, size_t cap, size_t* needed) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    return copy_out(p->ks[k].code.source, buf, cap, needed);
+}
+
+kf_status kf_plan_kernel_geometry(const kf_plan* p, int32_t k, int32_t* grid, int32_t* block) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    if (grid) *grid = p->ks[k].code.launches[0].grid;
+    if (block) *block = p->ks[k].code.launches[0].block;
+    return KF_OK;
+}
+
+kf_status kf_plan_describe(const kf_plan* p, char* buf, size_t cap, size_t* needed) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    std::ostringstream o;
+    uint64_t r = 0, w = 0;
+    o << "{\"kernels\": [";
+    for (size_t i = 0; i < p->ks.size(); ++i) {
+        const KernelCode& k = p->ks[i].code;
+        o << (i ? ", " : "") << "{\"name\": \"" << k.name << "\", \"class\": \"" << (k.mat ? "blas2" : "blas1")
+          << "\", \"calls\": [";
+        for (size_t j = 0; j < k.calls.size(); ++j)
+            o << (j ? ", " : "") << "{\"index\": " << k.calls[j] << ", \"op\": \"" << op_name(p->s.calls[k.calls[j]].op) << "\"}";
+        o << "], \"launches\": [";
+        for (size_t j = 0; j < k.launches.size(); ++j)
+            o << (j ? ", " : "") << "{\"name\": \"" << k.launches[j].name << "\", \"grid\": " << k.launches[j].grid
+              << ", \"block\": " << k.launches[j].block << "}";
+        o << "], \"grid\": " << k.launches[0].grid << ", \"block\": " << k.launches[0].block
+          << ", \"params\": " << k.params_json << ", \"bytes_read\": " << k.bytes_read
+          << ", \"bytes_written\": " << k.bytes_written << ", \"workspace_floats\": " << k.ws_floats
+          << ", \"lds_bytes\": " << k.lds_bytes << "}";
+        r += k.bytes_read;
+        w += k.bytes_written;
+    }
+    o << "], \"partition\": [";
+    for (size_t i = 0; i < p->part.size(); ++i) o << (i ? ", " : "") << p->part[i];
+    o << "], \"bytes_read\": " << r << ", \"bytes_written\": " << w << ", \"workspace_bytes\": " << p->ws_need
+      << "}";
+    return copy_out(o.str(), buf, cap, needed);
+}
+
+kf_status kf_util_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || bytes % 16 || (uintptr_t)dst % 16 || (uintptr_t)src % 16)
+        return set_error(KF_ERR_ARG, "copy needs 16-byte aligned buffers and size");
+    hipError_t e = launch_copy(dst, src, bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(KF_ERR_HIP, hipGetErrorString(e));
+    return KF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,724 @@
+// codegen.cpp -- HIP source for one fused (or single-call) kernel of a plan.
+//
+// The generated kernel follows the schema of Algorithm 1: shared (LDS) data
+// first, then indices, invariant loads, cleared accumulators of reductions,
+// the serial loop over rows (or over vector chunks) calling the load, compute
+// and store routines of every call in script order (Algorithm 2), and last
+// the stores of the accumulated reductions. Values that stay on chip are
+// never stored or reloaded (Section 4.3: fusion removes the store of the
+// producer and the load of the consumer); a value goes to HBM only when it is
+// a script output or a later kernel reads it.
+//
+// BLAS-2 kernels (nesting depth 2) run on a 2D decomposition of the rows x
+// cols iteration space: a workgroup owns a strip of C = 256 k columns (k
+// float4 per lane, 64 lanes) and R rows; its W waves split the rows and walk
+// them G at a time. Row reductions (gemv) are finished by a transposing
+// cross-lane reduction per G rows; column reductions (gemtv) accumulate in
+// registers and are merged across waves through LDS at the end. When a
+// reduction spans several workgroups their partial sums go to the workspace
+// and a second, small launch adds them in a fixed order and applies the
+// alpha/beta epilogue (Section 3.2.2, final reduction "by extra kernel"):
+// the kernel boundary is the global barrier, so the main pass needs no
+// cross-XCD cache write-back per workgroup.
+//
+// BLAS-1 kernels (nesting depth 1) stream float4 chunks with a grid-stride
+// loop; dot products reduce per thread, per wave and per workgroup, and the
+// finishing launch adds the workgroup partials with a compensated sum.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <sstream>
+
+#include "kf_internal.h"
+
+namespace kf {
+
+static std::string F(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    int n = vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (n < (int)sizeof buf) return std::string(buf, n);
+    std::string s(n + 1, '\0');
+    va_start(ap, fmt);
+    vsnprintf(&s[0], n + 1, fmt, ap);
+    va_end(ap);
+    s.resize(n);
+    return s;
+}
+
+static uint64_t fnv1a(const std::string& s) {
+    uint64_t h = 1469598103934665603ULL;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+// Does value v, produced in kernel kid, have to be written to HBM (R6)?
+static bool must_store(const Script& s, const std::vector<int>& part, int kid, int v) {
+    const Value& val = s.values[v];
+    if (val.output) return true;
+    for (int d : val.consumers)
+        if (part[d] != kid) return true;
+    return false;
+}
+
+static bool produced_in(const Script& s, const std::vector<int>& part, int kid, int v) {
+    int p = s.values[v].producer;
+    return p >= 0 && part[p] == kid;
+}
+
+struct Emitter {
+    std::ostringstream o;
+    int ind = 1;
+    void l(const std::string& line) {
+        for (int i = 0; i < ind; ++i) o << "  ";
+        o << line << "\n";
+    }
+};
+
+// Scalar operand expression: kernel-local names sc<v>.
+static std::string scal_name(int v) { return F("sc%d", v); }
+
+static void add_scalar_args(const Script& s, int v, std::vector<KArg>* args, std::vector<int>* seen) {
+    if (v < 0) return;
+    if (std::find(seen->begin(), seen->end(), v) != seen->end()) return;
+    seen->push_back(v);
+    if (s.values[v].kind == VK::Const) args->push_back({ArgKind::ConstScalar, v});
+    else args->push_back({ArgKind::DevScalarIn, v});
+}
+
+void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vector<int>& part,
+                  uint64_t* rd, uint64_t* wr) {
+    const int kid = part[calls[0]];
+    std::set<int> reads, writes;
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        int ops[5] = {k.alpha, k.beta, k.in[0], k.in[1], k.in[2]};
+        for (int v : ops) {
+            if (v < 0) continue;
+            if (s.values[v].kind == VK::Const) continue;
+            if (!produced_in(s, part, kid, v)) reads.insert(v);
+        }
+        if (must_store(s, part, kid, k.out)) writes.insert(k.out);
+    }
+    auto bytes = [&](int v) -> uint64_t {
+        const Value& x = s.values[v];
+        switch (x.kind) {
+            case VK::Vec: return (uint64_t)x.n * 4;
+            case VK::Mat: return (uint64_t)x.rows * (uint64_t)x.cols * 4;
+            case VK::DevScalar: return 4;
+            default: return 0;
+        }
+    };
+    uint64_t r = 0, w = 0;
+    for (int v : reads) r += bytes(v);
+    for (int v : writes) w += bytes(v);
+    *rd = r;
+    *wr = w;
+}
+
+// ============================================================================
+// BLAS-2 kernels
+// ============================================================================
+static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
+                          const std::vector<int>& part, const MatParams& p) {
+    KernelCode kc;
+    kc.mat = true;
+    kc.calls = calls;
+    const int kid = part[calls[0]];
+    const Space sp = call_space(s, calls[0]);
+    const long M = (long)sp.a, N = (long)sp.b;
+    const int K = p.k, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
+    int LG = 0;
+    while ((1 << LG) < G) ++LG;
+    const long C = 256L * K;
+    const long S = (N + C - 1) / C, NB = (M + R - 1) / R;
+    const long NP = (N + 3) / 4 * 4;
+
+    // ---- classify operands
+    std::vector<int> mat_in, mat_out, colv, rowv, vec_in, vec_out, gemv_calls, gemtv_calls;
+    std::vector<int> scalars;
+    auto push_u = [](std::vector<int>& v, int x) {
+        if (std::find(v.begin(), v.end(), x) == v.end()) v.push_back(x);
+    };
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        int A = k.in[0];
+        if (!produced_in(s, part, kid, A)) push_u(mat_in, A);
+        if (k.op == Op::Ger) {
+            push_u(rowv, k.in[1]);
+            push_u(colv, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(mat_out, k.out);
+        } else if (k.op == Op::Gemv) {
+            push_u(colv, k.in[1]);
+            gemv_calls.push_back(c);
+            if (k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(vec_in, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
+        } else if (k.op == Op::Gemtv) {
+            push_u(rowv, k.in[1]);
+            gemtv_calls.push_back(c);
+            if (k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(vec_in, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
+        }
+    }
+    for (int v : colv) push_u(vec_in, v);
+    for (int v : rowv) push_u(vec_in, v);
+    const bool row_part = !gemv_calls.empty() && S > 1;
+    const bool col_part = !gemtv_calls.empty() && NB > 1;
+
+    // ---- workspace layout (floats) and tickets
+    std::map<int, size_t> ws_off;
+    size_t wsz = 0;
+    if (row_part)
+        for (int c : gemv_calls) { ws_off[c] = wsz; wsz += (size_t)S * M; wsz = (wsz + 3) / 4 * 4; }
+    if (col_part)
+        for (int c : gemtv_calls) { ws_off[c] = wsz; wsz += (size_t)NB * NP; }
+    kc.ws_floats = wsz;
+
+    // ---- arguments
+    std::vector<std::string> sig;
+    for (int v : mat_in) sig.push_back(F("const float* __restrict__ M%d", v));
+    for (int v : mat_out) sig.push_back(F("float* __restrict__ O%d", v));
+    for (int v : vec_in) sig.push_back(F("const float* __restrict__ V%d", v));
+    for (int v : vec_out) sig.push_back(F("float* __restrict__ Y%d", v));
+    std::vector<KArg> kc_scalar_args;
+    {
+        for (int c : calls) {
+            add_scalar_args(s, s.calls[c].alpha, &kc_scalar_args, &scalars);
+            if (s.calls[c].in[2] >= 0 && s.calls[c].op != Op::Ger)
+                add_scalar_args(s, s.calls[c].beta, &kc_scalar_args, &scalars);
+        }
+        for (auto& a : kc_scalar_args) {
+            if (a.kind == ArgKind::ConstScalar) sig.push_back(F("float P%d", a.value));
+            else sig.push_back(F("const float* __restrict__ P%d", a.value));
+        }
+    }
+    Launch mainl;
+    for (int v : mat_in) mainl.args.push_back({ArgKind::MatIn, v});
+    for (int v : mat_out) mainl.args.push_back({ArgKind::MatOut, v});
+    for (int v : vec_in) mainl.args.push_back({ArgKind::VecIn, v});
+    for (int v : vec_out) mainl.args.push_back({ArgKind::VecOut, v});
+    for (auto& a : kc_scalar_args) mainl.args.push_back(a);
+    mainl.args.push_back({ArgKind::Workspace, -1});
+    sig.push_back("float* __restrict__ ws");
+
+    // ---- body
+    Emitter e;
+    e.l(F("constexpr long M = %ldL, N = %ldL, C = %ldL, S = %ldL, NB = %ldL, NP = %ldL;", M, N, C, S, NB, NP));
+    e.l(F("constexpr int K = %d, W = %d, G = %d, LG = %d, R = %d, NT = %d;", K, W, G, LG, R, NT));
+    for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
+    e.l("const long sidx = blockIdx.x % S, rb = blockIdx.x / S;");
+    e.l("const long c0 = sidx * C, r0 = rb * R;");
+    e.l("const long r1 = (r0 + R < M) ? r0 + R : M;");
+    e.l("(void)ws;");
+    for (int v : scalars) {
+        if (s.values[v].kind == VK::Const) e.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
+        else e.l(F("const float %s = *P%d;", scal_name(v).c_str(), v));
+    }
+    e.l("long col[K];");
+    e.l("#pragma unroll");
+    e.l("for (int j = 0; j < K; ++j) col[j] = c0 + (long)(j * 64 + lane) * 4;");
+    // invariant column vectors (Algorithm 1, "load invariant data")
+    for (int v : colv) {
+        e.l(F("kf_f4 cv%d[K];", v));
+        e.l("#pragma unroll");
+        e.l(F("for (int j = 0; j < K; ++j) cv%d[j] = kf_ld4_tail(V%d, col[j], N);", v, v));
+    }
+    // row vectors staged in LDS; rows past the end read as zero
+    for (int v : rowv) {
+        e.l(F("__shared__ float rv%d[R];", v));
+        e.l(F("for (int i = tid; i < R; i += NT) rv%d[i] = (r0 + i < M) ? V%d[r0 + i] : 0.f;", v, v));
+    }
+    // cleared accumulators (Algorithm 1, "clear outputs of accumulated reductions")
+    for (int c : gemtv_calls) {
+        e.l(F("kf_f4 acc%d[K];", c));
+        e.l("#pragma unroll");
+        e.l(F("for (int j = 0; j < K; ++j) acc%d[j] = kf_zero4();", c));
+    }
+    e.l("__syncthreads();");
+
+    // Matrix value expression for matrix v at row gi.
+    auto mexpr = [&](int v) -> std::string {
+        if (produced_in(s, part, kid, v)) return F("m%d", v);
+        return F("L%d[gi]", v);
+    };
+    // Row epilogue for all gemv calls at `row`, sums in sum<c>.
+    auto row_epilogue = [&](const char* rowvar) {
+        for (int c : gemv_calls) {
+            const Call& k = s.calls[c];
+            std::string val = F("%s * sum%d", scal_name(k.alpha).c_str(), c);
+            if (k.in[2] >= 0) {
+                std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                     : F("V%d[%s]", k.in[2], rowvar);
+                val = F("__builtin_fmaf(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+            }
+            e.l(F("const float f%d = %s;", c, val.c_str()));
+            if (must_store(s, part, kid, k.out)) e.l(F("Y%d[%s] = f%d;", k.out, rowvar, c));
+            else e.l(F("(void)f%d;", c));
+        }
+    };
+
+    auto emit_loop = [&](bool edge) {
+        e.l("for (long g0 = r0 + (long)wave * G; g0 < r1; g0 += (long)W * G) {");
+        e.ind++;
+        // loads of every matrix read from HBM (load routines)
+        for (int v : mat_in) e.l(F("kf_f4 L%d[G][K];", v));
+        e.l("#pragma unroll");
+        e.l("for (int gi = 0; gi < G; ++gi) {");
+        e.ind++;
+        e.l("const long row = g0 + gi;");
+        for (int v : mat_in) {
+            e.l("#pragma unroll");
+            if (!edge)
+                e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = kf_ld4_nt(M%d + row * LD%d + col[j]);", v, v, v));
+            else
+                e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = (row < r1) ? kf_ldm_edge(M%d + row * LD%d, col[j], N) : kf_zero4();", v, v, v));
+        }
+        e.ind--;
+        e.l("}");
+        for (int c : gemv_calls) e.l(F("float rp%d[G];", c));
+        e.l("#pragma unroll");
+        e.l("for (int gi = 0; gi < G; ++gi) {");
+        e.ind++;
+        e.l("const long row = g0 + gi;");
+        e.l("const int rl = (int)(row - r0);");
+        e.l("(void)rl;");
+        // compute routines in script order
+        for (int c : calls) {
+            const Call& k = s.calls[c];
+            std::string Min = mexpr(k.in[0]);
+            if (k.op == Op::Ger) {
+                int o = k.out;
+                e.l(F("const float cu%d = %s * rv%d[rl];", c, scal_name(k.alpha).c_str(), k.in[1]));
+                e.l(F("kf_f4 m%d[K];", o));
+                e.l("#pragma unroll");
+                e.l(F("for (int j = 0; j < K; ++j) m%d[j] = kf_fma4s(cu%d, cv%d[j], %s[j]);", o, c, k.in[2], Min.c_str()));
+                if (must_store(s, part, kid, o)) {
+                    if (!edge) {
+                        e.l("#pragma unroll");
+                        e.l(F("for (int j = 0; j < K; ++j) kf_st4_nt(O%d + row * LD%d + col[j], m%d[j]);", o, o, o));
+                    } else {
+                        e.l("if (row < r1) {");
+                        e.l("#pragma unroll");
+                        e.l(F("  for (int j = 0; j < K; ++j) kf_stm_edge(O%d + row * LD%d, col[j], N, m%d[j]);", o, o, o));
+                        e.l("}");
+                    }
+                }
+            } else if (k.op == Op::Gemtv) {
+                e.l(F("const float xr%d = rv%d[rl];", c, k.in[1]));
+                e.l("#pragma unroll");
+                e.l(F("for (int j = 0; j < K; ++j) acc%d[j] = kf_fma4s(xr%d, %s[j], acc%d[j]);", c, c, Min.c_str(), c));
+            } else if (k.op == Op::Gemv) {
+                e.l(F("float t%d = 0.f;", c));
+                e.l("#pragma unroll");
+                e.l(F("for (int j = 0; j < K; ++j) t%d = kf_dot4(%s[j], cv%d[j], t%d);", c, Min.c_str(), k.in[1], c));
+                e.l(F("rp%d[gi] = t%d;", c, c));
+            }
+        }
+        e.ind--;
+        e.l("}");
+        // row reductions of this group
+        if (!gemv_calls.empty()) {
+            for (int c : gemv_calls) e.l(F("const float sum%d = kf_rows_reduce<LG>(rp%d);", c, c));
+            e.l("{");
+            e.ind++;
+            e.l("const long row = g0 + (lane >> (6 - LG));");
+            if (edge) e.l("if ((lane & ((64 >> LG) - 1)) == 0 && row < r1) {");
+            else e.l("if ((lane & ((64 >> LG) - 1)) == 0) {");
+            e.ind++;
+            if (!row_part) {
+                row_epilogue("row");
+            } else {
+                for (int c : gemv_calls) e.l(F("ws[%zuL + sidx * M + row] = sum%d;", ws_off[c], c));
+            }
+            e.ind--;
+            e.l("}");
+            e.ind--;
+            e.l("}");
+        }
+        e.ind--;
+        e.l("}");
+    };
+    e.l("const bool edge = (c0 + C > N) || (r0 + R > M);");
+    e.l("if (!edge) {");
+    e.ind++;
+    emit_loop(false);
+    e.ind--;
+    e.l("} else {");
+    e.ind++;
+    emit_loop(true);
+    e.ind--;
+    e.l("}");
+
+    // column reductions: merge the waves in wave order through LDS
+    if (!gemtv_calls.empty()) {
+        const int ngt = (int)gemtv_calls.size();
+        e.l(F("__shared__ kf_f4 kf_red[%d][W * (C / 4)];", ngt));
+        for (int i = 0; i < ngt; ++i) {
+            int c = gemtv_calls[i];
+            e.l("#pragma unroll");
+            e.l(F("for (int j = 0; j < K; ++j) kf_red[%d][wave * (C / 4) + j * 64 + lane] = acc%d[j];", i, c));
+        }
+        e.l("__syncthreads();");
+        e.l("for (int q = tid; q < C / 4; q += NT) {");
+        e.ind++;
+        e.l("const long cc = c0 + 4L * q;");
+        for (int i = 0; i < ngt; ++i) {
+            int c = gemtv_calls[i];
+            e.l(F("kf_f4 sum%d = kf_red[%d][q];", c, i));
+            e.l(F("for (int w = 1; w < W; ++w) sum%d += kf_red[%d][w * (C / 4) + q];", c, i));
+        }
+        if (!col_part) {
+            e.l("if (cc < N) {");
+            e.ind++;
+            for (int c : gemtv_calls) {
+                const Call& k = s.calls[c];
+                std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
+                if (k.in[2] >= 0) {
+                    std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                         : F("kf_ld4_tail(V%d, cc, N)", k.in[2]);
+                    val = F("kf_fma4s(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+                }
+                e.l(F("const kf_f4 f%d = %s;", c, val.c_str()));
+                if (must_store(s, part, kid, k.out)) e.l(F("kf_st4_tail(Y%d, cc, N, f%d);", k.out, c));
+                else e.l(F("(void)f%d;", c));
+            }
+            e.ind--;
+            e.l("}");
+        } else {
+            e.l("if (cc < N) {");
+            for (int c : gemtv_calls) e.l(F("  kf_st4(ws + %zuL + rb * NP + cc, sum%d);", ws_off[c], c));
+            e.l("}");
+        }
+        e.ind--;
+        e.l("}");
+    }
+    // ---- finishing launch: adds the partial sums in a fixed order, then the epilogue
+    Emitter f;
+    Launch finl;
+    std::vector<std::string> fsig;
+    if (row_part || col_part) {
+        std::vector<int> fin_in;
+        for (int c : calls) {
+            const Call& k = s.calls[c];
+            bool part_here = (k.op == Op::Gemv && row_part) || (k.op == Op::Gemtv && col_part);
+            if (part_here && k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(fin_in, k.in[2]);
+        }
+        std::vector<int> fin_out;
+        for (int v : vec_out) {
+            Op op = s.calls[s.values[v].producer].op;
+            if ((op == Op::Gemv && row_part) || (op == Op::Gemtv && col_part)) fin_out.push_back(v);
+        }
+        for (int v : fin_in) { finl.args.push_back({ArgKind::VecIn, v}); fsig.push_back(F("const float* __restrict__ V%d", v)); }
+        for (int v : fin_out) { finl.args.push_back({ArgKind::VecOut, v}); fsig.push_back(F("float* __restrict__ Y%d", v)); }
+        for (auto& a : kc_scalar_args) {
+            finl.args.push_back(a);
+            if (a.kind == ArgKind::ConstScalar) fsig.push_back(F("float P%d", a.value));
+            else fsig.push_back(F("const float* __restrict__ P%d", a.value));
+        }
+        finl.args.push_back({ArgKind::Workspace, -1});
+        fsig.push_back("const float* __restrict__ ws");
+        const long RBK = row_part ? (M + 255) / 256 : 0;
+        const long CBK = col_part ? (NP / 4 + 255) / 256 : 0;
+        f.l(F("constexpr long M = %ldL, N = %ldL, S = %ldL, NB = %ldL, NP = %ldL, RBK = %ldL;", M, N, S, NB, NP, RBK));
+        for (int v : scalars) {
+            if (s.values[v].kind == VK::Const) f.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
+            else f.l(F("const float %s = *P%d;", scal_name(v).c_str(), v));
+        }
+        if (row_part) {
+            f.l("if (blockIdx.x < RBK) {");
+            f.ind++;
+            f.l("const long row = (long)blockIdx.x * 256 + threadIdx.x;");
+            f.l("if (row < M) {");
+            f.ind++;
+            for (int c : gemv_calls) {
+                f.l(F("float sum%d = 0.f;", c));
+                f.l(F("for (long si = 0; si < S; ++si) sum%d += ws[%zuL + si * M + row];", c, ws_off[c]));
+            }
+            for (int c : gemv_calls) {
+                const Call& k = s.calls[c];
+                std::string val = F("%s * sum%d", scal_name(k.alpha).c_str(), c);
+                if (k.in[2] >= 0) {
+                    std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                         : F("V%d[row]", k.in[2]);
+                    val = F("__builtin_fmaf(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+                }
+                f.l(F("const float f%d = %s;", c, val.c_str()));
+                if (must_store(s, part, kid, k.out)) f.l(F("Y%d[row] = f%d;", k.out, c));
+                else f.l(F("(void)f%d;", c));
+            }
+            f.ind--;
+            f.l("}");
+            f.ind--;
+            f.l("}");
+        }
+        if (col_part) {
+            f.l("if (blockIdx.x >= RBK) {");
+            f.ind++;
+            f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 256 + threadIdx.x);");
+            f.l("if (cc < N) {");
+            f.ind++;
+            for (int c : gemtv_calls) {
+                f.l(F("kf_f4 sum%d = kf_zero4();", c));
+                f.l(F("for (long b = 0; b < NB; ++b) sum%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+            }
+            for (int c : gemtv_calls) {
+                const Call& k = s.calls[c];
+                std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
+                if (k.in[2] >= 0) {
+                    std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                         : F("kf_ld4_tail(V%d, cc, N)", k.in[2]);
+                    val = F("kf_fma4s(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+                }
+                f.l(F("const kf_f4 f%d = %s;", c, val.c_str()));
+                if (must_store(s, part, kid, k.out)) f.l(F("kf_st4_tail(Y%d, cc, N, f%d);", k.out, c));
+                else f.l(F("(void)f%d;", c));
+            }
+            f.ind--;
+            f.l("}");
+            f.ind--;
+            f.l("}");
+        }
+        finl.grid = (int)(RBK + CBK);
+        finl.block = 256;
+    }
+    // the main pass no longer stores outputs that the finishing launch writes
+    std::ostringstream head;
+    std::string sigs, fsigs;
+    for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
+    for (size_t i = 0; i < fsig.size(); ++i) fsigs += (i ? ",\n    " : "    ") + fsig[i];
+    std::string key = F("mat K%d W%d G%d R%d M%ld N%ld|", K, W, G, R, M, N) + sigs + e.o.str() + fsigs + f.o.str();
+    kc.name = F("kf_mat_%016llx", (unsigned long long)fnv1a(key));
+    head << "extern \"C\" __global__ void __launch_bounds__(" << NT << ") " << kc.name << "(\n"
+         << sigs << ") {\n" << e.o.str() << "}\n";
+    mainl.name = kc.name;
+    mainl.grid = (int)(S * NB);
+    mainl.block = NT;
+    kc.launches.push_back(mainl);
+    if (row_part || col_part) {
+        finl.name = kc.name + "_fin";
+        head << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n"
+             << fsigs << ") {\n" << f.o.str() << "}\n";
+        kc.launches.push_back(finl);
+    }
+    kc.source = head.str();
+    kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + gemtv_calls.size() * (size_t)W * (C / 4) * 16;
+    kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d, \"strips\": %ld, \"row_blocks\": %ld}",
+                       K, W, G, R, S, NB);
+    kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
+    return kc;
+}
+
+// ============================================================================
+// BLAS-1 kernels
+// ============================================================================
+static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
+                          const std::vector<int>& part, const VecParams& p) {
+    KernelCode kc;
+    kc.mat = false;
+    kc.calls = calls;
+    const int kid = part[calls[0]];
+    const Space sp = call_space(s, calls[0]);
+    const long N = (long)sp.a, N4 = N / 4, T = N % 4;
+    const int U = p.unroll, NT = p.threads, GRID = p.grid, NW = NT / 64;
+
+    std::vector<int> vec_in, vec_out, dots, scalars;
+    auto push_u = [](std::vector<int>& v, int x) {
+        if (std::find(v.begin(), v.end(), x) == v.end()) v.push_back(x);
+    };
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        for (int i = 0; i < 2; ++i)
+            if (k.in[i] >= 0 && !produced_in(s, part, kid, k.in[i])) push_u(vec_in, k.in[i]);
+        if (k.op == Op::Dot) {
+            dots.push_back(c);
+            if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
+        } else if (must_store(s, part, kid, k.out)) {
+            push_u(vec_out, k.out);
+        }
+    }
+    const int ndot = (int)dots.size();
+    const bool dot_part = GRID > 1 && ndot > 0;
+    kc.ws_floats = dot_part ? (size_t)ndot * GRID : 0;
+
+    std::vector<std::string> sig;
+    Launch mainl;
+    for (int v : vec_in) { mainl.args.push_back({ArgKind::VecIn, v}); sig.push_back(F("const float* __restrict__ V%d", v)); }
+    std::vector<int> dot_out;
+    for (int v : vec_out) {
+        bool sc = s.values[v].kind == VK::DevScalar;
+        if (sc && dot_part) { dot_out.push_back(v); continue; }
+        mainl.args.push_back({sc ? ArgKind::DevScalarOut : ArgKind::VecOut, v});
+        sig.push_back(F("float* __restrict__ Y%d", v));
+    }
+    {
+        std::vector<KArg> sargs;
+        for (int c : calls) add_scalar_args(s, s.calls[c].alpha, &sargs, &scalars);
+        for (auto& a : sargs) {
+            mainl.args.push_back(a);
+            if (a.kind == ArgKind::ConstScalar) sig.push_back(F("float P%d", a.value));
+            else sig.push_back(F("const float* __restrict__ P%d", a.value));
+        }
+    }
+    mainl.args.push_back({ArgKind::Workspace, -1});
+    sig.push_back("float* __restrict__ ws");
+
+    Emitter e;
+    e.l(F("constexpr long N = %ldL, N4 = %ldL, T = %ldL;", N, N4, T));
+    e.l(F("constexpr int U = %d, NT = %d, GRID = %d, NW = %d;", U, NT, GRID, NW));
+    e.l("constexpr long STEP = (long)NT * U;");
+    e.l("const int tid = threadIdx.x;");
+    e.l("__shared__ float kf_lds[NW];");
+    e.l("(void)kf_lds; (void)ws;");
+    for (int v : scalars) {
+        if (s.values[v].kind == VK::Const) e.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
+        else e.l(F("const float %s = *P%d;", scal_name(v).c_str(), v));
+    }
+    for (int c : dots) e.l(F("float dacc%d = 0.f;", c));
+
+    // compute routines on one float4 chunk held in x<v>
+    auto emit_compute = [&](const char* store_fmt_idx, bool tail) {
+        for (int c : calls) {
+            const Call& k = s.calls[c];
+            if (k.op == Op::Scal) {
+                e.l(F("const kf_f4 x%d = kf_mul4s(%s, x%d);", k.out, scal_name(k.alpha).c_str(), k.in[0]));
+            } else if (k.op == Op::Axpy) {
+                e.l(F("const kf_f4 x%d = kf_fma4s(%s, x%d, x%d);", k.out, scal_name(k.alpha).c_str(), k.in[0], k.in[1]));
+            } else if (k.op == Op::Dot) {
+                e.l(F("dacc%d = kf_dot4(x%d, x%d, dacc%d);", c, k.in[0], k.in[1], c));
+            }
+            if (k.op != Op::Dot && must_store(s, part, kid, k.out)) {
+                if (!tail) e.l(F("kf_st4_nt(Y%d + 4 * %s, x%d);", k.out, store_fmt_idx, k.out));
+                else e.l(F("Y%d[%s] = x%d.x;", k.out, store_fmt_idx, k.out));
+            }
+        }
+    };
+    auto emit_body = [&](bool guard) {
+        for (int v : vec_in) e.l(F("kf_f4 in%d[U];", v));
+        e.l("#pragma unroll");
+        e.l("for (int u = 0; u < U; ++u) {");
+        e.ind++;
+        e.l("const long i4 = b + (long)u * NT + tid;");
+        if (guard) e.l("if (i4 < N4) {");
+        for (int v : vec_in) e.l(F("  in%d[u] = kf_ld4_nt(V%d + 4 * i4);", v, v));
+        if (guard) e.l("}");
+        e.ind--;
+        e.l("}");
+        e.l("#pragma unroll");
+        e.l("for (int u = 0; u < U; ++u) {");
+        e.ind++;
+        e.l("const long i4 = b + (long)u * NT + tid;");
+        if (guard) {
+            e.l("if (i4 < N4) {");
+            e.ind++;
+        }
+        for (int v : vec_in) e.l(F("const kf_f4 x%d = in%d[u];", v, v));
+        emit_compute("i4", false);
+        if (guard) {
+            e.ind--;
+            e.l("}");
+        }
+        e.ind--;
+        e.l("}");
+    };
+    e.l("for (long b = (long)blockIdx.x * STEP; b < N4; b += (long)GRID * STEP) {");
+    e.ind++;
+    e.l("if (b + STEP <= N4) {");
+    e.ind++;
+    emit_body(false);
+    e.ind--;
+    e.l("} else {");
+    e.ind++;
+    emit_body(true);
+    e.ind--;
+    e.l("}");
+    e.ind--;
+    e.l("}");
+    if (T) {
+        e.l("if (blockIdx.x == 0 && tid < T) {");
+        e.ind++;
+        e.l("const long ix = 4 * N4 + tid;");
+        for (int v : vec_in) e.l(F("kf_f4 x%d = kf_zero4(); x%d.x = V%d[ix];", v, v, v));
+        emit_compute("ix", true);
+        e.ind--;
+        e.l("}");
+    }
+    // dot products: workgroup sums; the finishing launch adds them
+    for (int i = 0; i < ndot; ++i) {
+        int c = dots[i];
+        const Call& k = s.calls[c];
+        e.l(F("const float bs%d = kf_block_sum<NW>(dacc%d, kf_lds);", c, c));
+        if (!dot_part) {
+            if (must_store(s, part, kid, k.out)) e.l(F("if (tid == 0) *Y%d = bs%d;", k.out, c));
+        } else {
+            e.l(F("if (tid == 0) ws[%dL * GRID + blockIdx.x] = bs%d;", i, c));
+        }
+    }
+    Emitter f;
+    Launch finl;
+    std::vector<std::string> fsig;
+    if (dot_part) {
+        for (int v : dot_out) { finl.args.push_back({ArgKind::DevScalarOut, v}); fsig.push_back(F("float* __restrict__ Y%d", v)); }
+        finl.args.push_back({ArgKind::Workspace, -1});
+        fsig.push_back("const float* __restrict__ ws");
+        f.l(F("constexpr int GRID = %d;", GRID));
+        f.l("__shared__ float kf_lds[4];");
+        f.l("const int tid = threadIdx.x;");
+        for (int i = 0; i < ndot; ++i) {
+            int c = dots[i];
+            const Call& k = s.calls[c];
+            f.l("{");
+            f.ind++;
+            f.l("float s = 0.f, comp = 0.f;");
+            f.l(F("for (int g = tid; g < GRID; g += 256) { const float y = ws[%dL * GRID + g] - comp; const float t = s + y; comp = (t - s) - y; s = t; }", i));
+            f.l("const float tot = kf_block_sum<4>(s, kf_lds);");
+            if (must_store(s, part, kid, k.out)) f.l(F("if (tid == 0) *Y%d = tot;", k.out));
+            else f.l("(void)tot;");
+            f.ind--;
+            f.l("}");
+        }
+        finl.grid = 1;
+        finl.block = 256;
+    }
+
+    std::string sigs, fsigs;
+    for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
+    for (size_t i = 0; i < fsig.size(); ++i) fsigs += (i ? ",\n    " : "    ") + fsig[i];
+    std::string body = e.o.str();
+    std::string key = F("vec U%d NT%d G%d N%ld|", U, NT, GRID, N) + sigs + body + fsigs + f.o.str();
+    kc.name = F("kf_vec_%016llx", (unsigned long long)fnv1a(key));
+    std::ostringstream src;
+    src << "extern \"C\" __global__ void __launch_bounds__(" << NT << ") " << kc.name << "(\n"
+        << sigs << ") {\n" << body << "}\n";
+    mainl.name = kc.name;
+    mainl.grid = GRID;
+    mainl.block = NT;
+    kc.launches.push_back(mainl);
+    if (dot_part) {
+        finl.name = kc.name + "_fin";
+        src << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n"
+            << fsigs << ") {\n" << f.o.str() << "}\n";
+        kc.launches.push_back(finl);
+    }
+    kc.source = src.str();
+    kc.lds_bytes = 16 + (size_t)NW * 4;
+    kc.params_json = F("{\"unroll\": %d, \"threads\": %d, \"grid\": %d}", U, NT, GRID);
+    kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
+    return kc;
+}
+
+KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
+                           const std::vector<int>& part, const MatParams& mp,
+                           const VecParams& vp) {
+    Space sp = call_space(s, calls[0]);
+    if (sp.mat) return gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp));
+    return gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+}
+
+}  // namespace kf

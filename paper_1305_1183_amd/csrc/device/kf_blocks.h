@@ -1,0 +1,156 @@
+// kf_blocks.h -- gfx950 building blocks that the generated kernels compose.
+//
+// These are the "routines" of the paper's elementary functions (Section 4.3:
+// load, compute and store routines glued into one kernel), written for CDNA4:
+// 64-lane wavefronts, 128-bit global loads and stores, cross-lane exchanges
+// instead of shared-memory atomics, and a deterministic two-level reduction:
+// workgroups write partial sums, and a second launch adds them in a fixed
+// order (the "extra kernel" option of Section 3.2.2).
+//
+// This header is prepended verbatim to every run-time compiled source; it has
+// no includes of its own (hipRTC provides the HIP device runtime).
+
+typedef float kf_f4 __attribute__((ext_vector_type(4)));
+
+// ---- B1/B2: 128-bit loads and stores ----------------------------------------
+// Streamed matrix data is read once per plan, so it is loaded and stored with
+// the non-temporal hint; vectors use ordinary cached accesses.
+__device__ __forceinline__ kf_f4 kf_ld4_nt(const float* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const kf_f4*>(p));
+}
+__device__ __forceinline__ kf_f4 kf_ld4(const float* p) {
+    return *reinterpret_cast<const kf_f4*>(p);
+}
+__device__ __forceinline__ void kf_st4_nt(float* p, kf_f4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<kf_f4*>(p));
+}
+__device__ __forceinline__ void kf_st4(float* p, kf_f4 v) {
+    *reinterpret_cast<kf_f4*>(p) = v;
+}
+__device__ __forceinline__ kf_f4 kf_zero4() { kf_f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
+
+// Vector entries col..col+3, entries at index >= n read as zero (the vector
+// buffer holds exactly n floats, so nothing past n is touched).
+__device__ __forceinline__ kf_f4 kf_ld4_tail(const float* v, long col, long n) {
+    if (col + 4 <= n) return kf_ld4(v + col);
+    kf_f4 r = kf_zero4();
+    if (col + 0 < n) r.x = v[col + 0];
+    if (col + 1 < n) r.y = v[col + 1];
+    if (col + 2 < n) r.z = v[col + 2];
+    return r;
+}
+__device__ __forceinline__ void kf_st4_tail(float* v, long col, long n, kf_f4 x) {
+    if (col + 4 <= n) { kf_st4(v + col, x); return; }
+    if (col + 0 < n) v[col + 0] = x.x;
+    if (col + 1 < n) v[col + 1] = x.y;
+    if (col + 2 < n) v[col + 2] = x.z;
+}
+
+// Matrix row segment at the right edge: the row holds ld >= round_up(n, 4)
+// floats, so a float4 starting below n is inside the row; entries >= n are
+// padding and are replaced by zero with a select (padding may hold NaN).
+__device__ __forceinline__ kf_f4 kf_ldm_edge(const float* row, long col, long n) {
+    if (col >= n) return kf_zero4();
+    kf_f4 r = kf_ld4_nt(row + col);
+    if (col + 4 > n) {
+        r.y = (col + 1 < n) ? r.y : 0.f;
+        r.z = (col + 2 < n) ? r.z : 0.f;
+        r.w = 0.f;
+    }
+    return r;
+}
+__device__ __forceinline__ void kf_stm_edge(float* row, long col, long n, kf_f4 x) {
+    if (col >= n) return;
+    if (col + 4 <= n) { kf_st4_nt(row + col, x); return; }
+    row[col] = x.x;
+    if (col + 1 < n) row[col + 1] = x.y;
+    if (col + 2 < n) row[col + 2] = x.z;
+}
+
+// ---- B8: element-wise map arithmetic (explicit FMAs, no contraction) --------
+__device__ __forceinline__ kf_f4 kf_fma4s(float s, kf_f4 v, kf_f4 c) {
+    kf_f4 r;
+    r.x = __builtin_fmaf(s, v.x, c.x); r.y = __builtin_fmaf(s, v.y, c.y);
+    r.z = __builtin_fmaf(s, v.z, c.z); r.w = __builtin_fmaf(s, v.w, c.w);
+    return r;
+}
+__device__ __forceinline__ kf_f4 kf_fma4v(kf_f4 a, kf_f4 b, kf_f4 c) {
+    kf_f4 r;
+    r.x = __builtin_fmaf(a.x, b.x, c.x); r.y = __builtin_fmaf(a.y, b.y, c.y);
+    r.z = __builtin_fmaf(a.z, b.z, c.z); r.w = __builtin_fmaf(a.w, b.w, c.w);
+    return r;
+}
+__device__ __forceinline__ kf_f4 kf_mul4s(float s, kf_f4 v) {
+    kf_f4 r;
+    r.x = s * v.x; r.y = s * v.y; r.z = s * v.z; r.w = s * v.w;
+    return r;
+}
+// acc + a.b over the four components, in component order.
+__device__ __forceinline__ float kf_dot4(kf_f4 a, kf_f4 b, float acc) {
+    acc = __builtin_fmaf(a.x, b.x, acc);
+    acc = __builtin_fmaf(a.y, b.y, acc);
+    acc = __builtin_fmaf(a.z, b.z, acc);
+    acc = __builtin_fmaf(a.w, b.w, acc);
+    return acc;
+}
+
+// ---- B4: cross-lane reductions over the 64-lane wavefront --------------------
+__device__ __forceinline__ float kf_xor(float v, int mask) {
+    const int lane = __lane_id();
+    const int src = (lane ^ mask) << 2;
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v)));
+}
+// Butterfly: every lane ends with the sum of all 64 lanes (same value in all).
+__device__ __forceinline__ float kf_wave_sum(float v) {
+    v += kf_xor(v, 32);
+    v += kf_xor(v, 16);
+    v += kf_xor(v, 8);
+    v += kf_xor(v, 4);
+    v += kf_xor(v, 2);
+    v += kf_xor(v, 1);
+    return v;
+}
+// Transposing reduction of G = 2^LG row partials held by every lane. Stage t
+// exchanges half of the remaining values with the lane whose bit (5 - t)
+// differs, so after LG stages lane l holds one partial of row l >> (6 - LG);
+// a butterfly over the low 6 - LG bits then completes the sum. G rows cost
+// G - 1 + (6 - LG) exchanges instead of 6 G.
+template <int LG>
+__device__ __forceinline__ float kf_rows_reduce(float* v) {
+    const int lane = __lane_id();
+    constexpr int G = 1 << LG;
+#pragma unroll
+    for (int t = 0; t < LG; ++t) {
+        const int half = G >> (t + 1);
+        const int mask = 32 >> t;
+        const bool hi = (lane & mask) != 0;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            const float send = hi ? v[j] : v[j + half];
+            const float keep = hi ? v[j + half] : v[j];
+            v[j] = keep + kf_xor(send, mask);
+        }
+    }
+    float s = v[0];
+#pragma unroll
+    for (int mask = (32 >> LG); mask >= 1; mask >>= 1) s += kf_xor(s, mask);
+    return s;
+}
+
+// ---- B6: workgroup sum in wave order -----------------------------------------
+// Returns the workgroup total in thread 0 (other threads get an unspecified value).
+template <int NW>
+__device__ __forceinline__ float kf_block_sum(float v, float* lds) {
+    v = kf_wave_sum(v);
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    float s = 0.f;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s += lds[w];
+    }
+    return s;
+}

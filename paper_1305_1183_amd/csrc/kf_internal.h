@@ -1,0 +1,125 @@
+// kf_internal.h -- host-side data structures of the fused BLAS sequence engine.
+#pragma once
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/kf.h"
+
+namespace kf {
+
+// Kinds of values a script declares or produces (Listing 1 declarations).
+enum class VK : int { Vec = 0, Mat = 1, Const = 2, DevScalar = 3 };
+
+struct Value {
+    VK kind = VK::Vec;
+    int64_t n = 0;                 // vector length
+    int64_t rows = 0, cols = 0, ld = 0;
+    float cval = 0.f;              // kf_const value
+    int producer = -1;             // call index, -1 for declared values
+    bool input = false, output = false;
+    std::vector<int> consumers;    // call indices (one entry per use)
+};
+
+// Elementary calls (Section 3.3).
+enum class Op : int { Scal = 0, Axpy = 1, Dot = 2, Gemv = 3, Gemtv = 4, Ger = 5 };
+
+const char* op_name(Op op);
+
+struct Call {
+    Op op = Op::Scal;
+    int alpha = -1, beta = -1;     // scalar values (-1 = none)
+    int in[3] = {-1, -1, -1};      // operand values, see kf.h
+    int out = -1;
+};
+
+struct Script {
+    std::vector<Value> values;
+    std::vector<Call> calls;
+};
+
+// Iteration space of a call: BLAS-1 calls iterate over a vector of length n,
+// BLAS-2 calls over an rows x cols matrix (nesting depth 1 vs 2, Section 3.2).
+struct Space {
+    bool mat = false;
+    int64_t a = 0, b = 0;          // n (vec) or rows, cols (mat)
+    bool operator==(const Space& o) const { return mat == o.mat && a == o.a && b == o.b; }
+    bool operator<(const Space& o) const {
+        if (mat != o.mat) return mat < o.mat;
+        if (a != o.a) return a < o.a;
+        return b < o.b;
+    }
+};
+Space call_space(const Script& s, int c);
+bool is_reduction(Op op);
+
+// ---- legality and enumeration (plan.cpp) ----------------------------------
+// Reason a call set cannot be one kernel (empty = legal).
+std::string block_illegal_reason(const Script& s, const std::vector<int>& calls);
+bool partition_acyclic(const Script& s, const std::vector<int>& part, int nk);
+// Enumerate legal partitions; part[i] = kernel id of call i (ids numbered in
+// order of first call). Fewest kernels first, capped at max_plans.
+std::vector<std::vector<int>> enumerate_partitions(const Script& s, int max_plans);
+// The legal partition with the fewest kernels (ties: first enumerated).
+std::vector<int> fused_partition(const Script& s);
+std::vector<int> unfused_partition(const Script& s);
+// Kernel ids in a dependency-respecting order; calls of each kernel in
+// recording order (a topological order of the SSA script).
+std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vector<int>& part);
+
+// ---- implementation parameters ---------------------------------------------
+struct MatParams { int k = 0, waves = 0, group = 0, rows = 0; };
+struct VecParams { int unroll = 0, threads = 0, grid = 0; };
+MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req);
+VecParams default_vec_params(int64_t n, const VecParams& req);
+
+// ---- code generation (codegen.cpp) --------------------------------------------
+enum class ArgKind : int {
+    MatIn, MatOut, VecIn, VecOut, ConstScalar, DevScalarIn, DevScalarOut, Workspace
+};
+struct KArg { ArgKind kind; int value; };   // value id (or -1 for the workspace)
+
+// One HIP kernel launch: the main pass of a plan kernel, or the pass that
+// finishes its cross-workgroup reductions.
+struct Launch {
+    std::string name;              // extern "C" symbol
+    std::vector<KArg> args;        // launch argument order
+    int grid = 0, block = 0;
+};
+
+struct KernelCode {
+    std::string name;              // name of the main launch (unique per text)
+    std::string source;            // text of every launch (without the building blocks)
+    std::vector<Launch> launches;  // main pass, then the finishing pass if any
+    size_t ws_floats = 0;          // partial-sum floats this kernel needs
+    size_t lds_bytes = 0;          // static LDS per workgroup of the main pass
+    uint64_t bytes_read = 0, bytes_written = 0;
+    std::string params_json;
+    std::vector<int> calls;
+    bool mat = false;
+};
+KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
+                           const std::vector<int>& part, const MatParams& mp,
+                           const VecParams& vp);
+// Operand-level byte accounting of one kernel (reads, writes) in HBM.
+void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vector<int>& part,
+                  uint64_t* rd, uint64_t* wr);
+
+// ---- JIT (jit.cpp) ------------------------------------------------------------
+const std::string& blocks_source();
+// Compile the given kernels (one translation unit) to a code object for gfx950.
+// Returns false and fills log on failure.
+bool jit_compile(const std::vector<const KernelCode*>& ks, std::string* code_object,
+                 std::string* log);
+
+// ---- errors ---------------------------------------------------------------------
+kf_status set_error(kf_status st, const std::string& msg);
+
+}  // namespace kf
+
+// Opaque C handles.
+struct kf_script { kf::Script s; bool compiled_from = false; };
+struct kf_planset { std::vector<std::vector<int>> parts; };

@@ -16,6 +16,9 @@ regardless of the leading dimension, so padding never changes the values.
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 GAMMA = 0x9E3779B97F4A7C15
@@ -23,7 +26,7 @@ _K2 = 0xD1B54A32D192ED03
 _M1 = 0xBF58476D1CE4E5B9
 _M2 = 0x94D049BB133111EB
 _MASK = (1 << 64) - 1
-_CHUNK = 1 << 22
+_CHUNK = 1 << 17
 
 
 def stream_key(seed: int, tensor_id: int) -> int:
@@ -56,13 +59,28 @@ def raw_bits(seed: int, tensor_id: int, start: int, count: int) -> np.ndarray:
         return _mix64(key + idx * np.uint64(GAMMA))
 
 
+def _threads() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _fill_pm1(out: np.ndarray, seed: int, tensor_id: int, start: int) -> None:
+    # (h >> 40) - 2**23 is an integer in [-2**23, 2**23), exact in float32;
+    # scaling by 2**-23 is exact too, so the value equals (h >> 40) 2**-23 - 1.
+    bits = raw_bits(seed, tensor_id, start, out.size) >> np.uint64(40)
+    k = bits.astype(np.int64) - (1 << 23)
+    np.multiply(k.astype(np.float32), np.float32(2.0 ** -23), out=out)
+
+
 def uniform_pm1(seed: int, tensor_id: int, count: int, start: int = 0) -> np.ndarray:
     """float32 values uniform on [-1, 1) with 24 random bits each."""
     out = np.empty(count, dtype=np.float32)
-    for off in range(0, count, _CHUNK):
-        c = min(_CHUNK, count - off)
-        bits = raw_bits(seed, tensor_id, start + off, c) >> np.uint64(40)
-        out[off:off + c] = (bits.astype(np.float64) * 2.0 ** -23 - 1.0).astype(np.float32)
+    offs = list(range(0, count, _CHUNK))
+    if len(offs) <= 1:
+        if count:
+            _fill_pm1(out, seed, tensor_id, start)
+        return out
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(lambda o: _fill_pm1(out[o:o + _CHUNK], seed, tensor_id, start + o), offs))
     return out
 
 
@@ -89,11 +107,19 @@ def matrix(seed: int, tensor_id: int, rows: int, cols: int, ld: int | None = Non
     a = np.empty((rows, ld), dtype=np.float32)
     if ld > cols:
         a[:, cols:] = pad_value
+    if ld == cols:
+        a.reshape(-1)[:] = uniform_pm1(seed, tensor_id, rows * cols)
+        return a
     rows_per_chunk = max(1, _CHUNK // max(cols, 1))
-    for r0 in range(0, rows, rows_per_chunk):
+
+    def fill(r0):
         r1 = min(rows, r0 + rows_per_chunk)
-        a[r0:r1, :cols] = uniform_pm1(seed, tensor_id, (r1 - r0) * cols,
-                                      start=r0 * cols).reshape(r1 - r0, cols)
+        tmp = np.empty((r1 - r0) * cols, dtype=np.float32)
+        _fill_pm1(tmp, seed, tensor_id, r0 * cols)
+        a[r0:r1, :cols] = tmp.reshape(r1 - r0, cols)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(fill, range(0, rows, rows_per_chunk)))
     return a
 
 

@@ -1,0 +1,324 @@
+"""Thin ctypes binding of the ``kf.h`` C ABI (argument marshalling only).
+
+Every function keeps the C name and raises :class:`KFError` on a negative
+status. Device buffers are passed as integer addresses (``tensor.data_ptr()``)
+and streams as ``hipStream_t`` integers (``torch.cuda.current_stream().cuda_stream``).
+
+PyTorch's wheel ships its own HIP runtime with the same soname as the system
+one; it is imported before the library is loaded so that the process holds a
+single HIP runtime.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (load order: one HIP runtime per process)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkf.so")
+
+KF_OK = 0
+ERRORS = {
+    -1: "KF_ERR_ARG", -2: "KF_ERR_SHAPE", -3: "KF_ERR_DTYPE", -4: "KF_ERR_ALIGN",
+    -5: "KF_ERR_ALIAS", -6: "KF_ERR_STATE", -7: "KF_ERR_UNBOUND", -8: "KF_ERR_WORKSPACE",
+    -9: "KF_ERR_COMPILE", -10: "KF_ERR_HIP", -11: "KF_ERR_NOMEM", -12: "KF_ERR_UNSUPPORTED",
+    -13: "KF_ERR_INTERNAL",
+}
+KF_NONE = -1
+MODES = {"unfused": 0, "fused": 1, "additive": 2, "learned": 3, "exhaustive": 4, "partition": 5}
+KF_COMPILE_NO_LOAD = 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_sz = ctypes.c_size_t
+_f32 = ctypes.c_float
+_P = ctypes.POINTER
+
+
+class KFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (ERRORS.get(status, str(status)), message))
+        self.status = status
+        self.name = ERRORS.get(status, str(status))
+
+
+class kf_compile_opts(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("flags", _i32),
+                ("mat_k", _i32), ("mat_waves", _i32), ("mat_group", _i32), ("mat_rows", _i32),
+                ("vec_unroll", _i32), ("vec_threads", _i32), ("vec_grid", _i32),
+                ("partition", _P(_i32)), ("partition_len", _i32),
+                ("reserved", _i32 * 8)]
+
+
+_SIGS = {
+    "kf_last_error": ([], ctypes.c_char_p),
+    "kf_version": ([], ctypes.c_char_p),
+    "kf_script_create": ([_P(_vp)], _i32),
+    "kf_script_destroy": ([_vp], None),
+    "kf_vector": ([_vp, _i64, _P(_i32)], _i32),
+    "kf_matrix": ([_vp, _i64, _i64, _i64, _P(_i32)], _i32),
+    "kf_const": ([_vp, _f32, _P(_i32)], _i32),
+    "kf_scalar": ([_vp, _P(_i32)], _i32),
+    "kf_input": ([_vp, _i32], _i32),
+    "kf_output": ([_vp, _i32], _i32),
+    "kf_scal": ([_vp, _i32, _i32, _P(_i32)], _i32),
+    "kf_axpy": ([_vp, _i32, _i32, _i32, _P(_i32)], _i32),
+    "kf_dot": ([_vp, _i32, _i32, _P(_i32)], _i32),
+    "kf_gemv": ([_vp, _i32, _i32, _i32, _i32, _i32, _P(_i32)], _i32),
+    "kf_gemtv": ([_vp, _i32, _i32, _i32, _i32, _i32, _P(_i32)], _i32),
+    "kf_ger": ([_vp, _i32, _i32, _i32, _i32, _P(_i32)], _i32),
+    "kf_value_info": ([_vp, _i32, _P(_i32), _P(_i64), _P(_i64), _P(_i64)], _i32),
+    "kf_script_num_calls": ([_vp, _P(_i32)], _i32),
+    "kf_compile_opts_init": ([_P(kf_compile_opts)], None),
+    "kf_compile": ([_vp, _P(kf_compile_opts), _P(_vp)], _i32),
+    "kf_plan_destroy": ([_vp], None),
+    "kf_enumerate": ([_vp, _i32, _P(_vp)], _i32),
+    "kf_planset_destroy": ([_vp], None),
+    "kf_planset_count": ([_vp, _P(_i32)], _i32),
+    "kf_planset_get": ([_vp, _i32, _P(_i32), _i32], _i32),
+    "kf_plan_workspace_bytes": ([_vp, _P(_sz)], _i32),
+    "kf_bind": ([_vp, _i32, _vp], _i32),
+    "kf_bind_workspace": ([_vp, _vp, _sz], _i32),
+    "kf_set_const": ([_vp, _i32, _f32], _i32),
+    "kf_run": ([_vp, _vp], _i32),
+    "kf_run_kernel": ([_vp, _i32, _vp], _i32),
+    "kf_time_plan": ([_vp, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_plan_describe": ([_vp, ctypes.c_char_p, _sz, _P(_sz)], _i32),
+    "kf_plan_bytes": ([_vp, _P(_u64), _P(_u64)], _i32),
+    "kf_plan_num_kernels": ([_vp, _P(_i32)], _i32),
+    "kf_plan_source": ([_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)], _i32),
+    "kf_plan_kernel_geometry": ([_vp, _i32, _P(_i32), _P(_i32)], _i32),
+    "kf_util_copy": ([_vp, _vp, _sz, _vp], _i32),
+}
+EXPORTED = sorted(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libkf.so; raise if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkf.so is not built; run paper_1305_1183_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _chk(st: int) -> None:
+    if st != KF_OK:
+        raise KFError(st, lib().kf_last_error().decode())
+
+
+def kf_last_error() -> str:
+    return lib().kf_last_error().decode()
+
+
+def kf_version() -> str:
+    return lib().kf_version().decode()
+
+
+# ---- script recording --------------------------------------------------------
+def kf_script_create():
+    h = _vp()
+    _chk(lib().kf_script_create(ctypes.byref(h)))
+    return h
+
+
+def kf_script_destroy(s) -> None:
+    lib().kf_script_destroy(s)
+
+
+def _new(fn, *args) -> int:
+    out = _i32()
+    _chk(fn(*args, ctypes.byref(out)))
+    return out.value
+
+
+def kf_vector(s, n: int) -> int:
+    return _new(lib().kf_vector, s, n)
+
+
+def kf_matrix(s, rows: int, cols: int, ld: int = 0) -> int:
+    return _new(lib().kf_matrix, s, rows, cols, ld)
+
+
+def kf_const(s, v: float) -> int:
+    return _new(lib().kf_const, s, v)
+
+
+def kf_scalar(s) -> int:
+    return _new(lib().kf_scalar, s)
+
+
+def kf_input(s, v: int) -> None:
+    _chk(lib().kf_input(s, v))
+
+
+def kf_output(s, v: int) -> None:
+    _chk(lib().kf_output(s, v))
+
+
+def kf_scal(s, alpha: int, x: int) -> int:
+    return _new(lib().kf_scal, s, alpha, x)
+
+
+def kf_axpy(s, alpha: int, x: int, y: int) -> int:
+    return _new(lib().kf_axpy, s, alpha, x, y)
+
+
+def kf_dot(s, x: int, y: int) -> int:
+    return _new(lib().kf_dot, s, x, y)
+
+
+def kf_gemv(s, alpha: int, A: int, x: int, beta: int = KF_NONE, y0: int = KF_NONE) -> int:
+    return _new(lib().kf_gemv, s, alpha, A, x, beta, y0)
+
+
+def kf_gemtv(s, alpha: int, A: int, x: int, beta: int = KF_NONE, y0: int = KF_NONE) -> int:
+    return _new(lib().kf_gemtv, s, alpha, A, x, beta, y0)
+
+
+def kf_ger(s, alpha: int, A: int, u: int, v: int) -> int:
+    return _new(lib().kf_ger, s, alpha, A, u, v)
+
+
+def kf_value_info(s, v: int):
+    k, d0, d1, d2 = _i32(), _i64(), _i64(), _i64()
+    _chk(lib().kf_value_info(s, v, ctypes.byref(k), ctypes.byref(d0), ctypes.byref(d1),
+                             ctypes.byref(d2)))
+    return k.value, d0.value, d1.value, d2.value
+
+
+def kf_script_num_calls(s) -> int:
+    n = _i32()
+    _chk(lib().kf_script_num_calls(s, ctypes.byref(n)))
+    return n.value
+
+
+# ---- compile / enumerate --------------------------------------------------------
+def kf_compile_opts_init(mode="fused", flags=0, partition=None, **params) -> kf_compile_opts:
+    o = kf_compile_opts()
+    lib().kf_compile_opts_init(ctypes.byref(o))
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.flags = flags
+    for k, v in params.items():
+        if not hasattr(o, k):
+            raise TypeError("unknown compile option %s" % k)
+        setattr(o, k, int(v))
+    if partition is not None:
+        arr = (_i32 * len(partition))(*partition)
+        o.partition = ctypes.cast(arr, _P(_i32))
+        o.partition_len = len(partition)
+        o._keep = arr  # keep the array alive with the struct
+    return o
+
+
+def kf_compile(s, opts=None, **kw):
+    if opts is None:
+        opts = kf_compile_opts_init(**kw)
+    h = _vp()
+    _chk(lib().kf_compile(s, ctypes.byref(opts), ctypes.byref(h)))
+    return h
+
+
+def kf_plan_destroy(p) -> None:
+    lib().kf_plan_destroy(p)
+
+
+def kf_enumerate(s, max_plans: int = 0) -> list:
+    """All legal partitions (list of lists: kernel id per call)."""
+    h = _vp()
+    _chk(lib().kf_enumerate(s, max_plans, ctypes.byref(h)))
+    try:
+        n = _i32()
+        _chk(lib().kf_planset_count(h, ctypes.byref(n)))
+        nc = kf_script_num_calls(s)
+        out = []
+        buf = (_i32 * max(nc, 1))()
+        for i in range(n.value):
+            _chk(lib().kf_planset_get(h, i, buf, nc))
+            out.append(list(buf[:nc]))
+        return out
+    finally:
+        lib().kf_planset_destroy(h)
+
+
+# ---- bind / run ------------------------------------------------------------------
+def kf_plan_workspace_bytes(p) -> int:
+    n = _sz()
+    _chk(lib().kf_plan_workspace_bytes(p, ctypes.byref(n)))
+    return n.value
+
+
+def kf_bind(p, v: int, dev_ptr: int) -> None:
+    _chk(lib().kf_bind(p, v, _vp(dev_ptr)))
+
+
+def kf_bind_workspace(p, dev_ptr: int, nbytes: int) -> None:
+    _chk(lib().kf_bind_workspace(p, _vp(dev_ptr), nbytes))
+
+
+def kf_set_const(p, v: int, value: float) -> None:
+    _chk(lib().kf_set_const(p, v, value))
+
+
+def kf_run(p, stream: int = 0) -> None:
+    _chk(lib().kf_run(p, _vp(stream)))
+
+
+def kf_run_kernel(p, k: int, stream: int = 0) -> None:
+    _chk(lib().kf_run_kernel(p, k, _vp(stream)))
+
+
+def kf_time_plan(p, stream: int = 0, warmup: int = 3, reps: int = 20) -> float:
+    t = _f32()
+    _chk(lib().kf_time_plan(p, _vp(stream), warmup, reps, ctypes.byref(t)))
+    return t.value
+
+
+def _text(fn, *args) -> str:
+    need = _sz()
+    _chk(fn(*args, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _chk(fn(*args, buf, need.value, ctypes.byref(need)))
+    return buf.value.decode()
+
+
+def kf_plan_describe(p) -> str:
+    return _text(lib().kf_plan_describe, p)
+
+
+def kf_plan_source(p, k: int) -> str:
+    return _text(lib().kf_plan_source, p, k)
+
+
+def kf_plan_bytes(p):
+    r, w = _u64(), _u64()
+    _chk(lib().kf_plan_bytes(p, ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
+def kf_plan_num_kernels(p) -> int:
+    n = _i32()
+    _chk(lib().kf_plan_num_kernels(p, ctypes.byref(n)))
+    return n.value
+
+
+def kf_plan_kernel_geometry(p, k: int):
+    g, b = _i32(), _i32()
+    _chk(lib().kf_plan_kernel_geometry(p, k, ctypes.byref(g), ctypes.byref(b)))
+    return g.value, b.value
+
+
+def kf_util_copy(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
+    _chk(lib().kf_util_copy(_vp(dst), _vp(src), nbytes, _vp(stream)))

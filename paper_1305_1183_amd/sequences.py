@@ -1,0 +1,221 @@
+"""Scripts of the paper's Table 1 sequences, recorded through the C ABI.
+
+Each builder records the sequence as elementary calls (the paper prints the
+script only for BiCGK, Listing 1; the others use the same vocabulary):
+
+* AXPYDOT  z = axpy(-alpha, v, w); r = dot(z, u)            outputs z, r
+* WAXPBY   t = scal(beta, y); w = axpy(alpha, x, t)          output w
+* BiCGK    q = gemv(1, A, p); s = gemtv(1, A, r)             outputs q, s
+* ATAX     t = gemv(1, A, x); y = gemtv(1, A, t)             output y
+* GESUMMV  t = gemv(alpha, A, x); y = gemv(beta, B, x, 1, t) output y
+* GEMVER   B1 = ger(1, A, u1, v1); B = ger(1, B1, u2, v2);
+           x = gemtv(beta, B, y, 1, z); w = gemv(alpha, B, x) outputs B, x, w
+
+A :class:`Sequence` keeps the script and the value handles by name;
+:meth:`Sequence.compile` returns a :class:`Program` that binds torch tensors
+and launches the plan on the current stream.
+"""
+from __future__ import annotations
+
+import json
+from dataclasses import dataclass, field
+
+import torch
+
+from . import kf
+
+
+@dataclass
+class Sequence:
+    name: str
+    script: object
+    values: dict = field(default_factory=dict)      # name -> kf_value
+    inputs: list = field(default_factory=list)       # names of vectors/matrices to bind
+    outputs: list = field(default_factory=list)      # names of results
+    consts: dict = field(default_factory=dict)       # name -> (kf_value, float)
+    shapes: dict = field(default_factory=dict)       # name -> tuple
+
+    def __del__(self):
+        try:
+            if self.script is not None:
+                kf.kf_script_destroy(self.script)
+        except Exception:
+            pass
+
+    def compile(self, mode="fused", **opts) -> "Program":
+        plan = kf.kf_compile(self.script, mode=mode, **opts)
+        return Program(self, plan)
+
+
+class Program:
+    """A compiled plan plus the device buffers bound to it."""
+
+    def __init__(self, seq: Sequence, plan):
+        self.seq = seq
+        self.plan = plan
+        self.tensors = {}
+        self.workspace = None
+
+    def __del__(self):
+        try:
+            kf.kf_plan_destroy(self.plan)
+        except Exception:
+            pass
+
+    @property
+    def num_kernels(self) -> int:
+        return kf.kf_plan_num_kernels(self.plan)
+
+    def describe(self) -> dict:
+        return json.loads(kf.kf_plan_describe(self.plan))
+
+    def bytes(self):
+        return kf.kf_plan_bytes(self.plan)
+
+    def bind(self, device="cuda", **tensors):
+        """Bind input tensors by name; allocate outputs and the workspace."""
+        for name in self.seq.inputs:
+            t = tensors[name]
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous float32 tensor" % name)
+            self.tensors[name] = t
+            kf.kf_bind(self.plan, self.seq.values[name], t.data_ptr())
+        for name in self.seq.outputs:
+            if name in tensors:
+                t = tensors[name]
+            else:
+                t = torch.empty(self.seq.shapes[name], dtype=torch.float32, device=device)
+            self.tensors[name] = t
+            kf.kf_bind(self.plan, self.seq.values[name], t.data_ptr())
+        nb = kf.kf_plan_workspace_bytes(self.plan)
+        self.workspace = torch.empty(max(nb, 256) // 4 + 64, dtype=torch.float32, device=device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        kf.kf_bind_workspace(self.plan, aligned, nb)
+        return self
+
+    def set_const(self, name: str, value: float) -> None:
+        kf.kf_set_const(self.plan, self.seq.consts[name][0], value)
+
+    def run(self, stream=None) -> dict:
+        st = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        kf.kf_run(self.plan, st)
+        return {n: self.tensors[n] for n in self.seq.outputs}
+
+    def time(self, warmup=3, reps=20) -> float:
+        return kf.kf_time_plan(self.plan, torch.cuda.current_stream().cuda_stream, warmup, reps)
+
+
+def _seq(name):
+    return Sequence(name=name, script=kf.kf_script_create())
+
+
+def _vec(q, name, n):
+    v = kf.kf_vector(q.script, n)
+    kf.kf_input(q.script, v)
+    q.values[name] = v
+    q.inputs.append(name)
+    q.shapes[name] = (n,)
+    return v
+
+
+def _mat(q, name, rows, cols, ld=0):
+    v = kf.kf_matrix(q.script, rows, cols, ld)
+    kf.kf_input(q.script, v)
+    ld = kf.kf_value_info(q.script, v)[3]
+    q.values[name] = v
+    q.inputs.append(name)
+    q.shapes[name] = (rows, ld)
+    return v
+
+
+def _const(q, name, value):
+    v = kf.kf_const(q.script, float(value))
+    q.consts[name] = (v, float(value))
+    return v
+
+
+def _out(q, name, v):
+    kf.kf_output(q.script, v)
+    q.values[name] = v
+    q.outputs.append(name)
+    kind, d0, d1, d2 = kf.kf_value_info(q.script, v)
+    q.shapes[name] = {0: (d0,), 1: (d0, d2), 3: (1,)}[kind]
+    return v
+
+
+def axpydot(n: int, alpha: float) -> Sequence:
+    q = _seq("axpydot")
+    w, v, u = _vec(q, "w", n), _vec(q, "v", n), _vec(q, "u", n)
+    na = _const(q, "neg_alpha", -alpha)
+    z = kf.kf_axpy(q.script, na, v, w)
+    r = kf.kf_dot(q.script, z, u)
+    _out(q, "z", z)
+    _out(q, "r", r)
+    return q
+
+
+def waxpby(n: int, alpha: float, beta: float) -> Sequence:
+    q = _seq("waxpby")
+    x, y = _vec(q, "x", n), _vec(q, "y", n)
+    a, b = _const(q, "alpha", alpha), _const(q, "beta", beta)
+    t = kf.kf_scal(q.script, b, y)
+    w = kf.kf_axpy(q.script, a, x, t)
+    _out(q, "w", w)
+    return q
+
+
+def bicgk(m: int, n: int, ld: int = 0) -> Sequence:
+    q = _seq("bicgk")
+    A = _mat(q, "A", m, n, ld)
+    p, r = _vec(q, "p", n), _vec(q, "r", m)
+    one = _const(q, "one", 1.0)
+    qq = kf.kf_gemv(q.script, one, A, p)
+    ss = kf.kf_gemtv(q.script, one, A, r)
+    _out(q, "q", qq)
+    _out(q, "s", ss)
+    return q
+
+
+def atax(m: int, n: int, ld: int = 0) -> Sequence:
+    q = _seq("atax")
+    A = _mat(q, "A", m, n, ld)
+    x = _vec(q, "x", n)
+    one = _const(q, "one", 1.0)
+    t = kf.kf_gemv(q.script, one, A, x)
+    y = kf.kf_gemtv(q.script, one, A, t)
+    _out(q, "y", y)
+    return q
+
+
+def gesummv(m: int, n: int, alpha: float, beta: float, lda: int = 0, ldb: int = 0) -> Sequence:
+    q = _seq("gesummv")
+    A = _mat(q, "A", m, n, lda)
+    B = _mat(q, "B", m, n, ldb)
+    x = _vec(q, "x", n)
+    a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
+    t = kf.kf_gemv(q.script, a, A, x)
+    y = kf.kf_gemv(q.script, b, B, x, one, t)
+    _out(q, "y", y)
+    return q
+
+
+def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
+    q = _seq("gemver")
+    A = _mat(q, "A", m, n, ld)
+    u1, v1 = _vec(q, "u1", m), _vec(q, "v1", n)
+    u2, v2 = _vec(q, "u2", m), _vec(q, "v2", n)
+    y, z = _vec(q, "y", m), _vec(q, "z", n)
+    a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
+    B1 = kf.kf_ger(q.script, one, A, u1, v1)
+    B = kf.kf_ger(q.script, one, B1, u2, v2)
+    x = kf.kf_gemtv(q.script, b, B, y, one, z)
+    w = kf.kf_gemv(q.script, a, B, x)
+    _out(q, "B", B)
+    _out(q, "x", x)
+    _out(q, "w", w)
+    return q
+
+
+BUILDERS = {"axpydot": axpydot, "waxpby": waxpby, "bicgk": bicgk, "atax": atax,
+            "gesummv": gesummv, "gemver": gemver}

@@ -1,0 +1,79 @@
+"""Seeded synthetic workloads of the Table 1 sequences.
+
+Sizes and distributions: the paper states none, so the single-instance suite
+uses n = 16384 (A is 16384 x 16384 row-major FP32, 1 GiB) and 2**26-entry
+vectors, all entries uniform on [-1, 1) and scalars uniform on [0.5, 2]; the
+small parity case is BiCGK at n = 1024. Tensor ids follow the order in which
+the sequence declares its operands; the seed is ``1000 * suite + index``.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import inputs as I
+
+# operand declaration order of each sequence (tensor ids 0, 1, 2, ...)
+OPERANDS = {
+    "axpydot": ["w", "v", "u"],
+    "waxpby": ["x", "y"],
+    "bicgk": ["A", "p", "r"],
+    "atax": ["A", "x"],
+    "gesummv": ["A", "B", "x"],
+    "gemver": ["A", "u1", "v1", "u2", "v2", "y", "z"],
+}
+SCALARS = {"axpydot": ["alpha"], "waxpby": ["alpha", "beta"], "bicgk": [], "atax": [],
+           "gesummv": ["alpha", "beta"], "gemver": ["alpha", "beta"]}
+MATRIX = {"A", "B"}
+ORDER = ["axpydot", "waxpby", "bicgk", "atax", "gesummv", "gemver"]
+SEQ_INDEX = {name: i for i, name in enumerate(ORDER)}
+
+SUITE_N = 16384
+SUITE_VEC = 1 << 26
+
+
+def seed_for(suite: int, name: str) -> int:
+    return 1000 * suite + SEQ_INDEX[name]
+
+
+def vector_length(name: str, which: str, m: int, n: int) -> int:
+    """Length of vector operand `which` for an m x n matrix (BLAS-2) or n (BLAS-1)."""
+    if name in ("axpydot", "waxpby"):
+        return n
+    row_indexed = {"bicgk": {"r"}, "atax": set(), "gesummv": set(),
+                   "gemver": {"u1", "u2", "y"}}[name]
+    return m if which in row_indexed else n
+
+
+def make(name: str, m: int, n: int, seed: int, ld: int | None = None, pad_value=np.nan):
+    """Operands (float32 numpy) and scalars (python floats) of one instance."""
+    arrays = {}
+    for tid, op in enumerate(OPERANDS[name]):
+        if op in MATRIX:
+            arrays[op] = I.matrix(seed, tid, m, n, ld=ld if ld else I.padded_ld(n),
+                                  pad_value=pad_value)
+        else:
+            arrays[op] = I.vector(seed, tid, vector_length(name, op, m, n))
+    scal = {}
+    for j, sname in enumerate(SCALARS[name]):
+        scal[sname] = I.scalar_uniform(seed, 100 + j, 0.5, 2.0)
+    return arrays, scal
+
+
+def reduction_length(name: str, m: int, n: int) -> int:
+    """Longest reduction feeding an output (sets the accuracy tolerance)."""
+    if name in ("axpydot", "waxpby"):
+        return n
+    return max(m, n)
+
+
+def tolerance(name: str, m: int, n: int) -> float:
+    """Relative L2 error bound 1e-5 * log2(n) against the FP64 oracle."""
+    return 1e-5 * max(1.0, float(np.log2(reduction_length(name, m, n))))
+
+
+def rel_l2(got, ref) -> float:
+    got = np.asarray(got, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    den = float(np.linalg.norm(ref))
+    num = float(np.linalg.norm(got - ref))
+    return num / den if den > 0 else num
