@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Benchmark: the single-instance FP32 suite of Table 1 sequences on one MI355X.
+
+One step runs the fused plan of every sequence once -- AXPYDOT and WAXPBY on
+2**26-entry vectors, BiCGK, ATAX, GESUMMV and GEMVER on 16384 x 16384 row-major
+matrices -- over inputs already resident in HBM. `value` is the algorithmic
+bytes of the six fused plans (each operand counted once per kernel that moves
+it through HBM, as in the paper's bandwidth figures) divided by the time of a
+step. Per-sequence fused and unfused times give the speedup of fusion.
+
+Prints one JSON line. `--gpus` above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "fused-sequence GB/s (% of HBM peak) & speedup vs unfused, FP32 GEMVER/BiCGK"
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", default="", help="comma-separated subset of sequences (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-unfused", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB streaming copy (memory-counter calibration)")
+    ap.add_argument("--tune", action="store_true",
+                    help="grid-search the implementation parameters of every sequence and print them")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline():
+    """The FP64 oracle (plain C, one thread) on the suite's shapes, bounded by
+    the full shapes: BLAS-2 sequences on all `rows` of the 16384 rows, BLAS-1
+    sequences on 2**26 entries. GB/s over the same FP32 algorithmic bytes as
+    the fused GPU plan of the sampled shapes."""
+    from paper_1305_1183_amd import kf
+    from paper_1305_1183_amd import sequences as S
+    from paper_1305_1183_amd import workloads as WL
+    from tests import seqcheck as SC  # the oracle: CPU-baseline leg only
+
+    n, rows, vec = WL.SUITE_N, WL.SUITE_N, 1 << 26
+    total_bytes, total_s = 0, 0.0
+    for name in WL.ORDER:
+        m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (rows, n)
+        arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
+        q = S.by_name(name, m, nn, scal)
+        p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+        r, w = kf.kf_plan_bytes(p)
+        kf.kf_plan_destroy(p)
+        t0 = time.perf_counter()
+        SC.oracle_outputs(name, arrays, scal, nn)
+        dt = time.perf_counter() - t0
+        total_bytes += r + w
+        total_s += dt
+        log("cpu oracle %-8s %.2f s" % (name, dt))
+    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 oracle, one thread: BiCGK/ATAX/GESUMMV/GEMVER on %d x %d (row sample), "
+                      "AXPYDOT/WAXPBY on 2^26 entries; %.1f s total" % (rows, n, total_s)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1305_1183_amd import kf
+    from paper_1305_1183_amd import sequences as S
+    from paper_1305_1183_amd import workloads as WL
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    kf.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    st = stream.cuda_stream
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_(-1, 1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            kf.kf_util_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, st)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "launches": 5}))
+        return
+
+    names = [s for s in args.only.split(",") if s] or list(WL.ORDER)
+    n, vec = WL.SUITE_N, WL.SUITE_VEC
+    if args.tune:
+        from paper_1305_1183_amd import autotune
+        for name in names:
+            m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (n, n)
+            arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
+            q = S.by_name(name, m, nn, scal)
+            devin = {k: torch.from_numpy(v).to(dev) for k, v in arrays.items()}
+            for mode in ("fused", "unfused"):
+                best, res = autotune.tune(q, devin, mode=mode)
+                res.sort(key=lambda r: r[1])
+                print(json.dumps({"seq": name, "mode": mode, "best": best,
+                                  "top": [[p, round(t, 2)] for p, t in res[:6]],
+                                  "worst": [res[-1][0], round(res[-1][1], 2)]}), flush=True)
+            del devin
+            torch.cuda.empty_cache()
+        return
+    progs = {}
+    t0 = time.time()
+    for name in names:
+        m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (n, n)
+        arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
+        q = S.by_name(name, m, nn, scal)
+        devin = {k: torch.from_numpy(v).to(dev) for k, v in arrays.items()}
+        del arrays
+        fused = q.compile(mode="fused", **WL.tuned_params(name, m, nn, "fused")).bind(device=dev, **devin)
+        unfused = None if args.no_unfused else q.compile(
+            mode="unfused", **WL.tuned_params(name, m, nn, "unfused")).bind(device=dev, **devin)
+        progs[name] = (q, fused, unfused, devin)
+        log("prepared %s (%.1f s)" % (name, time.time() - t0))
+
+    # launch table of the fused step: every HIP launch of every plan kernel
+    kernels = []
+    for name in names:
+        d = progs[name][1].describe()
+        for k, kd in enumerate(d["kernels"]):
+            for l, ld in enumerate(kd["launches"]):
+                kernels.append({"seq": name, "k": k, "l": l, "name": ld["name"],
+                                "bytes": ld["bytes_read"] + ld["bytes_written"],
+                                "calls": [c["op"] for c in kd["calls"]], "params": kd["params"]})
+    plans = [progs[k["seq"]][1].plan for k in kernels]
+
+    def step(events=None):
+        for i, kd in enumerate(kernels):
+            if events is not None:
+                events[i][0].record(stream)
+            kf.kf_run_launch(plans[i], kd["k"], kd["l"], st)
+            if events is not None:
+                events[i][1].record(stream)
+
+    # warm-up steps; the first one also times every launch to find the dominant one
+    probe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in kernels]
+    for w in range(max(1, args.warmup)):
+        step(probe if w == 0 else None)
+    torch.cuda.synchronize()
+    avg_k = np.array([a.elapsed_time(b) for a, b in probe]) * 1e3  # us, one warm-up step
+    dom = int(np.argmax(avg_k))
+    dk = kernels[dom]
+
+    def timed_step(ev):
+        # every launch of the step, with HIP events on the stream around the dominant one only
+        for i, kd in enumerate(kernels):
+            if i == dom:
+                ev[0].record(stream)
+            kf.kf_run_launch(plans[i], kd["k"], kd["l"], st)
+            if i == dom:
+                ev[1].record(stream)
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        timed_step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    dom_us = float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e3
+    step_bytes = sum(k["bytes"] for k in kernels)
+    ms_per_step = wall * 1e3 / args.steps
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = dk["bytes"] / (dom_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": WL.traffic_from_profiles(os.path.join(ROOT, "profiles"), dk["name"]),
+                "kernel": "%s kernel %d launch %d (%s) %s" % (dk["seq"], dk["k"], dk["l"], "+".join(dk["calls"]), dk["name"]),
+                "avg_us": round(dom_us, 2), "bytes_per_launch": dk["bytes"],
+                "timing": "HIP events on the launch stream around this launch, mean over the timed steps"}
+
+    seqs = {}
+    for name in names:
+        q, fused, unfused, _ = progs[name]
+        r, w = fused.bytes()
+        tf = fused.time(3, 20)
+        entry = {"fused_us": round(tf, 2), "fused_bytes": r + w,
+                 "fused_gbps": round((r + w) / tf / 1e3, 1),
+                 "fused_pct_peak": round((r + w) / tf / 1e3 / HBM_PEAK_GBPS * 100, 1),
+                 "kernels": fused.num_kernels}
+        if unfused is not None:
+            ru, wu = unfused.bytes()
+            tu = unfused.time(3, 20)
+            entry.update({"unfused_us": round(tu, 2), "unfused_bytes": ru + wu,
+                          "unfused_gbps": round((ru + wu) / tu / 1e3, 1),
+                          "speedup": round(tu / tf, 3), "unfused_kernels": unfused.num_kernels})
+        seqs[name] = entry
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "single-instance FP32 suite: " + ", ".join(names) +
+                      " (A %d x %d row-major, vectors 2^26, uniform[-1,1), fused plans)" % (n, n),
+                      "n": n, "vector_length": vec, "sequences": names},
+           "pct_peak": round(value / HBM_PEAK_GBPS * 100, 2),
+           "roofline": roofline,
+           "sequences": seqs,
+           "launches_us_warmup_probe": {"%s/%d/%d %s" % (k["seq"], k["k"], k["l"], k["name"]): round(float(a), 2)
+                                        for k, a in zip(kernels, avg_k)}}
+    if not args.no_cpu_baseline and not args.only:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

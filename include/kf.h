@@ -174,6 +174,10 @@ kf_status kf_run(kf_plan* p, void* stream);
 /* Launch only kernel k of the plan (in plan order), e.g. to time one kernel.
  * Its inputs must already hold valid data. */
 kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream);
+/* Number of HIP launches of kernel k (1, or 2 with a finishing pass), and
+ * launch l of kernel k alone (main pass l = 0, finishing pass l = 1). */
+kf_status kf_plan_num_launches(const kf_plan* p, int32_t k, int32_t* n);
+kf_status kf_run_launch(kf_plan* p, int32_t k, int32_t l, void* stream);
 /* Time the plan: `warmup` untimed runs, then `reps` runs each bracketed by HIP
  * events; returns the median in microseconds. Synchronises the stream. */
 kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps,

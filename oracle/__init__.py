@@ -237,3 +237,52 @@ def gemtv_cols(A, x, idx, cols=None):
     out, op = _out(ik.size)
     lib().kfo_gemtv_cols(Ak.shape[0], n, Ak.shape[1], Ap, xp, ik.ctypes.data_as(_I), ik.size, op)
     return out
+
+
+# ---- selected outputs at full size -------------------------------------------
+# The compositions below evaluate the same definitions on a subset of rows or
+# on column panels, so that full-size results can be checked without holding
+# an n x n double matrix. Every element is computed by the routines above with
+# the same arithmetic as the full definition.
+def _mat_panel(A, cols):
+    """float64 copy of A[:, cols] (A float32 storage)."""
+    return np.ascontiguousarray(A[:, cols], dtype=np.float64)
+
+
+def bicgk_sampled(A, p, r, rows, cols_idx, cols=None):
+    n = int(cols) if cols is not None else A.shape[1]
+    q = gemv_rows(A, p.astype(np.float64), rows, cols=n)
+    s = gemtv_cols(A, r.astype(np.float64), cols_idx, cols=n)
+    return q, s
+
+
+def atax_sampled(A, x, cols_idx, cols=None):
+    n = int(cols) if cols is not None else A.shape[1]
+    t = gemv_rows(A, x.astype(np.float64), np.arange(A.shape[0]), cols=n)
+    return gemtv_cols(A, t, cols_idx, cols=n)
+
+
+def gesummv_sampled(alpha, A, beta, B, x, rows, cols=None):
+    n = int(cols) if cols is not None else A.shape[1]
+    xd = x.astype(np.float64)
+    Ar = np.ascontiguousarray(A[rows, :n], dtype=np.float64)
+    Br = np.ascontiguousarray(B[rows, :n], dtype=np.float64)
+    t = gemv(alpha, Ar, xd)
+    return gemv(beta, Br, xd, 1.0, t)
+
+
+def gemver_sampled(alpha, beta, A, u1, v1, u2, v2, y, z, rows, cols=None, panel=512):
+    """B on the given rows, the whole x, and w on the given rows."""
+    n = int(cols) if cols is not None else A.shape[1]
+    f = lambda a: np.asarray(a, dtype=np.float64)
+    u1d, v1d, u2d, v2d, yd, zd = f(u1), f(v1), f(u2), f(v2), f(y), f(z)
+    # x = beta B^T y + z, one column panel of B at a time
+    x = np.empty(n, dtype=np.float64)
+    for c0 in range(0, n, panel):
+        c = np.arange(c0, min(n, c0 + panel))
+        Bp = ger(1.0, ger(1.0, _mat_panel(A, c), u1d, v1d[c]), u2d, v2d[c])
+        x[c] = gemtv(beta, Bp, yd, 1.0, zd[c])
+    Ar = np.ascontiguousarray(A[rows, :n], dtype=np.float64)
+    Br = ger(1.0, ger(1.0, Ar, u1d[rows], v1d), u2d[rows], v2d)
+    w = gemv(alpha, Br, x)
+    return Br, x, w

@@ -558,8 +558,10 @@ static void* value_ptr(kf_plan* p, int v) {
     return p->bind[v];
 }
 
-static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream) {
-    for (size_t li = 0; li < k.code.launches.size(); ++li) {
+static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, int first = 0,
+                               int last = -1) {
+    if (last < 0) last = (int)k.code.launches.size();
+    for (size_t li = (size_t)first; li < (size_t)last; ++li) {
         const Launch& l = k.code.launches[li];
         const size_t na = l.args.size();
         uint64_t store[64];
@@ -601,6 +603,20 @@ kf_status kf_run(kf_plan* p, void* stream) {
     CHECK(check_runnable(p));
     for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream));
     return KF_OK;
+}
+
+kf_status kf_plan_num_launches(const kf_plan* p, int32_t k, int32_t* n) {
+    if (!p || !n) return set_error(KF_ERR_ARG, "null argument");
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    *n = (int32_t)p->ks[k].code.launches.size();
+    return KF_OK;
+}
+
+kf_status kf_run_launch(kf_plan* p, int32_t k, int32_t l, void* stream) {
+    CHECK(check_runnable(p));
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    if (l < 0 || l >= (int32_t)p->ks[k].code.launches.size()) return set_error(KF_ERR_ARG, "launch index out of range");
+    return launch_kernel(p, p->ks[k], (hipStream_t)stream, l, l + 1);
 }
 
 kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream) {
@@ -691,7 +707,8 @@ kf_status kf_plan_describe(const kf_plan* p, char* buf, size_t cap, size_t* need
         o << "], \"launches\": [";
         for (size_t j = 0; j < k.launches.size(); ++j)
             o << (j ? ", " : "") << "{\"name\": \"" << k.launches[j].name << "\", \"grid\": " << k.launches[j].grid
-              << ", \"block\": " << k.launches[j].block << "}";
+              << ", \"block\": " << k.launches[j].block << ", \"bytes_read\": " << k.launches[j].bytes_read
+              << ", \"bytes_written\": " << k.launches[j].bytes_written << "}";
         o << "], \"grid\": " << k.launches[0].grid << ", \"block\": " << k.launches[0].block
           << ", \"params\": " << k.params_json << ", \"bytes_read\": " << k.bytes_read
           << ", \"bytes_written\": " << k.bytes_written << ", \"workspace_floats\": " << k.ws_floats

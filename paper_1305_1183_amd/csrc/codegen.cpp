@@ -425,7 +425,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         finl.args.push_back({ArgKind::Workspace, -1});
         fsig.push_back("const float* __restrict__ ws");
         const long RBK = row_part ? (M + 255) / 256 : 0;
-        const long CBK = col_part ? (NP / 4 + 255) / 256 : 0;
+        const long CBK = col_part ? (NP / 4 + 63) / 64 : 0;
         f.l(F("constexpr long M = %ldL, N = %ldL, S = %ldL, NB = %ldL, NP = %ldL, RBK = %ldL;", M, N, S, NB, NP, RBK));
         for (int v : scalars) {
             if (s.values[v].kind == VK::Const) f.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
@@ -459,14 +459,25 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.l("}");
         }
         if (col_part) {
+            // 64 float4 columns per workgroup; the 4 waves split the row blocks
+            // (wave w adds blocks w, w + 4, ...) and are merged in wave order.
             f.l("if (blockIdx.x >= RBK) {");
             f.ind++;
-            f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 256 + threadIdx.x);");
-            f.l("if (cc < N) {");
+            f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
+            f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 64 + lane);");
+            f.l(F("__shared__ kf_f4 kf_fr[%d][4][64];", (int)gemtv_calls.size()));
+            for (size_t i = 0; i < gemtv_calls.size(); ++i) {
+                int c = gemtv_calls[i];
+                f.l(F("kf_f4 part%d = kf_zero4();", c));
+                f.l(F("if (cc < N) for (long b = wave; b < NB; b += 4) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+                f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
+            }
+            f.l("__syncthreads();");
+            f.l("if (wave == 0 && cc < N) {");
             f.ind++;
-            for (int c : gemtv_calls) {
-                f.l(F("kf_f4 sum%d = kf_zero4();", c));
-                f.l(F("for (long b = 0; b < NB; ++b) sum%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+            for (size_t i = 0; i < gemtv_calls.size(); ++i) {
+                int c = gemtv_calls[i];
+                f.l(F("const kf_f4 sum%d = ((kf_fr[%zu][0][lane] + kf_fr[%zu][1][lane]) + kf_fr[%zu][2][lane]) + kf_fr[%zu][3][lane];", c, i, i, i, i));
             }
             for (int c : gemtv_calls) {
                 const Call& k = s.calls[c];
@@ -713,12 +724,31 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
     return kc;
 }
 
+// Operand bytes one launch moves through HBM (workspace partials excluded).
+static void launch_bytes(const Script& s, Launch* l) {
+    l->bytes_read = l->bytes_written = 0;
+    for (const KArg& a : l->args) {
+        if (a.value < 0) continue;
+        const Value& x = s.values[a.value];
+        uint64_t b = x.kind == VK::Vec ? (uint64_t)x.n * 4
+                   : x.kind == VK::Mat ? (uint64_t)x.rows * (uint64_t)x.cols * 4
+                   : x.kind == VK::DevScalar ? 4 : 0;
+        switch (a.kind) {
+            case ArgKind::MatIn: case ArgKind::VecIn: case ArgKind::DevScalarIn: l->bytes_read += b; break;
+            case ArgKind::MatOut: case ArgKind::VecOut: case ArgKind::DevScalarOut: l->bytes_written += b; break;
+            default: break;
+        }
+    }
+}
+
 KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
                            const std::vector<int>& part, const MatParams& mp,
                            const VecParams& vp) {
     Space sp = call_space(s, calls[0]);
-    if (sp.mat) return gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp));
-    return gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+    KernelCode kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp))
+                           : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+    for (Launch& l : kc.launches) launch_bytes(s, &l);
+    return kc;
 }
 
 }  // namespace kf

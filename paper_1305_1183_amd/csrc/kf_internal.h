@@ -88,6 +88,7 @@ struct Launch {
     std::string name;              // extern "C" symbol
     std::vector<KArg> args;        // launch argument order
     int grid = 0, block = 0;
+    uint64_t bytes_read = 0, bytes_written = 0;   // algorithmic HBM bytes of this launch
 };
 
 struct KernelCode {

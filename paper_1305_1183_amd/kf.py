@@ -85,6 +85,8 @@ _SIGS = {
     "kf_set_const": ([_vp, _i32, _f32], _i32),
     "kf_run": ([_vp, _vp], _i32),
     "kf_run_kernel": ([_vp, _i32, _vp], _i32),
+    "kf_plan_num_launches": ([_vp, _i32, _P(_i32)], _i32),
+    "kf_run_launch": ([_vp, _i32, _i32, _vp], _i32),
     "kf_time_plan": ([_vp, _vp, _i32, _i32, _P(_f32)], _i32),
     "kf_plan_describe": ([_vp, ctypes.c_char_p, _sz, _P(_sz)], _i32),
     "kf_plan_bytes": ([_vp, _P(_u64), _P(_u64)], _i32),
@@ -278,6 +280,16 @@ def kf_run(p, stream: int = 0) -> None:
 
 def kf_run_kernel(p, k: int, stream: int = 0) -> None:
     _chk(lib().kf_run_kernel(p, k, _vp(stream)))
+
+
+def kf_plan_num_launches(p, k: int) -> int:
+    n = _i32()
+    _chk(lib().kf_plan_num_launches(p, k, ctypes.byref(n)))
+    return n.value
+
+
+def kf_run_launch(p, k: int, l: int, stream: int = 0) -> None:
+    _chk(lib().kf_run_launch(p, k, l, _vp(stream)))
 
 
 def kf_time_plan(p, stream: int = 0, warmup: int = 3, reps: int = 20) -> float:

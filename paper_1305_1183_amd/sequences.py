@@ -219,3 +219,20 @@ def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
 
 BUILDERS = {"axpydot": axpydot, "waxpby": waxpby, "bicgk": bicgk, "atax": atax,
             "gesummv": gesummv, "gemver": gemver}
+
+
+def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0) -> Sequence:
+    """Sequence `name` on an m x n matrix (BLAS-2) or n-entry vectors (BLAS-1)."""
+    if name == "axpydot":
+        return axpydot(n, scal["alpha"])
+    if name == "waxpby":
+        return waxpby(n, scal["alpha"], scal["beta"])
+    if name == "bicgk":
+        return bicgk(m, n, ld)
+    if name == "atax":
+        return atax(m, n, ld)
+    if name == "gesummv":
+        return gesummv(m, n, scal["alpha"], scal["beta"], ld, ld)
+    if name == "gemver":
+        return gemver(m, n, scal["alpha"], scal["beta"], ld)
+    raise KeyError(name)

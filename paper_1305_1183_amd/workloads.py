@@ -77,3 +77,43 @@ def rel_l2(got, ref) -> float:
     den = float(np.linalg.norm(ref))
     num = float(np.linalg.norm(got - ref))
     return num / den if den > 0 else num
+
+
+# Implementation parameters the benchmark uses for the suite at n = 16384 and
+# 2**26-entry vectors, per plan kind, as chosen by the autotuner
+# (``python bench.py --tune``: median of 10 runs per grid point on MI355X).
+_M2 = dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024)
+_M1 = dict(mat_k=1, mat_waves=4, mat_group=4, mat_rows=1024)
+TUNED = {
+    ("bicgk", "fused"): _M2, ("bicgk", "unfused"): _M1,
+    ("atax", "fused"): _M2, ("atax", "unfused"): dict(mat_k=1, mat_waves=2, mat_group=8, mat_rows=1024),
+    ("gesummv", "fused"): _M2, ("gesummv", "unfused"): _M1,
+    ("gemver", "fused"): _M2, ("gemver", "unfused"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=1024),
+    ("axpydot", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=2048),
+    ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=1024),
+    ("waxpby", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
+    ("waxpby", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
+}
+
+
+def tuned_params(name: str, m: int, n: int, mode: str = "fused") -> dict:
+    """Tuned parameters for the suite shapes; library defaults elsewhere."""
+    suite = (m, n) == ((SUITE_VEC, SUITE_VEC) if name in ("axpydot", "waxpby") else (SUITE_N, SUITE_N))
+    return dict(TUNED.get((name, mode), {})) if suite else {}
+
+
+def traffic_from_profiles(profile_dir: str, kernel_name: str):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the same counters of
+    a streaming copy of known size), or None when the summary does not cover
+    this exact kernel text (the name is a hash of it)."""
+    import json
+    import os
+    path = os.path.join(profile_dir, "pmc_summary.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    k = d.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return int(round(k["fetch_bytes_scaled"] + k["write_bytes_scaled"]))

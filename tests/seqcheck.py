@@ -11,19 +11,7 @@ from paper_1305_1183_amd import workloads as WL
 
 
 def build_sequence(name, m, n, scal, ld=0):
-    if name == "axpydot":
-        return S.axpydot(n, scal["alpha"])
-    if name == "waxpby":
-        return S.waxpby(n, scal["alpha"], scal["beta"])
-    if name == "bicgk":
-        return S.bicgk(m, n, ld)
-    if name == "atax":
-        return S.atax(m, n, ld)
-    if name == "gesummv":
-        return S.gesummv(m, n, scal["alpha"], scal["beta"], ld, ld)
-    if name == "gemver":
-        return S.gemver(m, n, scal["alpha"], scal["beta"], ld)
-    raise KeyError(name)
+    return S.by_name(name, m, n, scal, ld)
 
 
 def oracle_outputs(name, arrays, scal, n):

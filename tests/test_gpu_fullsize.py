@@ -1,0 +1,113 @@
+"""Parity at the benchmark's full sizes and launch configuration.
+
+A is 16384 x 16384 (1 GiB) and vectors have 2**26 entries, built with the
+benchmark's seeds and compiled with the benchmark's parameters. BLAS-1 outputs
+are compared whole; BLAS-2 outputs on sampled rows and columns that the oracle
+computes one by one (GEMVER's x is computed whole, panel by panel)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1305_1183_amd import inputs as I
+from paper_1305_1183_amd import sequences as S
+from paper_1305_1183_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+N = WL.SUITE_N
+V = WL.SUITE_VEC
+
+
+def run(name, m, n, mode="fused"):
+    arrays, scal = WL.make(name, m, n, seed=WL.seed_for(2, name))
+    q = S.by_name(name, m, n, scal)
+    prog = q.compile(mode=mode, **WL.tuned_params(name, m, n, mode))
+    dev = {k: torch.from_numpy(v).cuda() for k, v in arrays.items()}
+    prog.bind(**dev)
+    outs = prog.run()
+    torch.cuda.synchronize()
+    host = {k: v.cpu().numpy() for k, v in outs.items()}
+    del dev, prog
+    torch.cuda.empty_cache()
+    return arrays, scal, host
+
+
+def sample(n, k, seed):
+    idx = np.unique(np.concatenate([[0, n - 1], I.small_ints(seed, 0, k, 0, n - 1).astype(np.int64)]))
+    return idx
+
+
+def ok(name, got, ref, m, n):
+    err = WL.rel_l2(got, ref)
+    tol = WL.tolerance(name, m, n)
+    assert np.all(np.isfinite(got)) and err <= tol, (name, err, tol)
+    return err
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+@pytest.mark.parametrize("name", ["axpydot", "waxpby"])
+def test_blas1_full(name, mode):
+    print("case", name, V, mode, flush=True)
+    arrays, scal, h = run(name, V, V, mode)
+    if name == "axpydot":
+        z, r = oracle.axpydot(scal["alpha"], arrays["w"], arrays["v"], arrays["u"])
+        ok(name, h["z"], z, V, V)
+        ok(name, h["r"], np.array([r]), V, V)
+    else:
+        ok(name, h["w"], oracle.waxpby(scal["alpha"], arrays["x"], scal["beta"], arrays["y"]), V, V)
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_bicgk_full(mode):
+    print("case bicgk", N, mode, flush=True)
+    arrays, scal, h = run("bicgk", N, N, mode)
+    rows, cols = sample(N, 96, 1), sample(N, 96, 2)
+    q, s = oracle.bicgk_sampled(arrays["A"], arrays["p"], arrays["r"], rows, cols)
+    ok("bicgk", h["q"][rows], q, N, N)
+    ok("bicgk", h["s"][cols], s, N, N)
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_atax_full(mode):
+    print("case atax", N, mode, flush=True)
+    arrays, scal, h = run("atax", N, N, mode)
+    cols = sample(N, 96, 3)
+    ok("atax", h["y"][cols], oracle.atax_sampled(arrays["A"], arrays["x"], cols), N, N)
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_gesummv_full(mode):
+    print("case gesummv", N, mode, flush=True)
+    arrays, scal, h = run("gesummv", N, N, mode)
+    rows = sample(N, 96, 4)
+    ref = oracle.gesummv_sampled(scal["alpha"], arrays["A"], scal["beta"], arrays["B"], arrays["x"], rows)
+    ok("gesummv", h["y"][rows], ref, N, N)
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_gemver_full(mode):
+    print("case gemver", N, mode, flush=True)
+    arrays, scal, h = run("gemver", N, N, mode)
+    rows = sample(N, 48, 5)
+    a = arrays
+    Br, x, w = oracle.gemver_sampled(scal["alpha"], scal["beta"], a["A"], a["u1"], a["v1"], a["u2"],
+                                     a["v2"], a["y"], a["z"], rows)
+    ok("gemver", h["B"][rows, :N], Br, N, N)
+    ok("gemver", h["x"], x, N, N)
+    ok("gemver", h["w"][rows], w, N, N)
+
+
+def test_bicgk_config1():
+    """BiCGK at n = 1024, fused and unfused, whole outputs."""
+    n = 1024
+    for mode in ("fused", "unfused"):
+        arrays, scal = WL.make("bicgk", n, n, seed=WL.seed_for(1, "bicgk"))
+        q = S.by_name("bicgk", n, n, scal)
+        prog = q.compile(mode=mode)
+        prog.bind(**{k: torch.from_numpy(v).cuda() for k, v in arrays.items()})
+        outs = prog.run()
+        torch.cuda.synchronize()
+        qr, sr = oracle.bicgk(arrays["A"], arrays["p"], arrays["r"], cols=n)
+        ok("bicgk", outs["q"].cpu().numpy(), qr, n, n)
+        ok("bicgk", outs["s"].cpu().numpy(), sr, n, n)

@@ -220,8 +220,34 @@ def pin_bruteforce_fraction(O):
         assert abs(float(sum(terms)) - s[j]) <= bound
 
 
+
+
+def pin_sampled_sequences(O):
+    """The sampled/panelled compositions equal the whole-output definitions."""
+    m, n = 37, 45
+    A = I.matrix(12, 0, m, n, ld=48)
+    B = I.matrix(12, 1, m, n, ld=48)
+    v = {k: I.vector(12, 2 + i, m if k in ("u1", "u2", "y", "r") else n)
+         for i, k in enumerate(["u1", "v1", "u2", "v2", "y", "z", "p", "r", "x"])}
+    rows, cols = np.array([0, 3, m - 1]), np.array([1, 7, n - 1])
+    q, s = O.bicgk(A, v["p"], v["r"], cols=n)
+    qs, ss = O.bicgk_sampled(A, v["p"], v["r"], rows, cols, cols=n)
+    np.testing.assert_allclose(qs, q[rows], rtol=1e-14)
+    np.testing.assert_allclose(ss, s[cols], rtol=1e-14)
+    y = O.atax(A, v["x"], cols=n)
+    np.testing.assert_allclose(O.atax_sampled(A, v["x"], cols, cols=n), y[cols], rtol=1e-13)
+    y = O.gesummv(1.25, A, 0.5, B, v["x"], cols=n)
+    np.testing.assert_allclose(O.gesummv_sampled(1.25, A, 0.5, B, v["x"], rows, cols=n), y[rows], rtol=1e-14)
+    Bf, x, w = O.gemver(1.5, 0.75, A, v["u1"], v["v1"], v["u2"], v["v2"], v["y"], v["z"], cols=n)
+    Br, xs, ws = O.gemver_sampled(1.5, 0.75, A, v["u1"], v["v1"], v["u2"], v["v2"], v["y"], v["z"],
+                                  rows, cols=n, panel=8)
+    np.testing.assert_array_equal(Br, Bf[rows])
+    np.testing.assert_allclose(xs, x, rtol=1e-14)
+    np.testing.assert_allclose(ws, w[rows], rtol=1e-13)
+
+
 ALL_PINS = [pin_elementary, pin_library, pin_axpydot, pin_waxpby, pin_bicgk, pin_atax,
-            pin_gesummv, pin_gemver, pin_sampled, pin_bruteforce_fraction]
+            pin_gesummv, pin_gemver, pin_sampled, pin_bruteforce_fraction, pin_sampled_sequences]
 
 
 @pytest.mark.parametrize("pin", ALL_PINS, ids=[p.__name__ for p in ALL_PINS])
