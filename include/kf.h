@@ -111,14 +111,20 @@ kf_status kf_script_num_calls(const kf_script* s, int32_t* n);
 enum {
     KF_MODE_UNFUSED = 0,      /* one kernel per call                           */
     KF_MODE_FUSED = 1,        /* the legal partition with fewest kernels       */
-    KF_MODE_ADDITIVE = 2,     /* best plan by the additive routine predictor   */
-    KF_MODE_LEARNED = 3,      /* best plan by the learned MLP cost model       */
-    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate on the GPU, keep fastest */
+    KF_MODE_ADDITIVE = 2,     /* best candidate by the additive routine predictor */
+    KF_MODE_LEARNED = 3,      /* best candidate by the learned cost model: needs
+                                 device buffers, ranked with kf_candidates +
+                                 kf_planset_features + kf_mlp_forward          */
+    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate: needs bound buffers,
+                                 kf_candidates + kf_time_plan                  */
     KF_MODE_PARTITION = 5     /* the partition given in opts.partition         */
 };
 enum {
-    KF_COMPILE_NO_LOAD = 1    /* stop after hipRTC (no GPU needed): build checks */
+    KF_COMPILE_NO_LOAD = 1,       /* stop after hipRTC (no GPU needed): build checks */
+    KF_COMPILE_CODEGEN_ONLY = 2   /* generate code but do not compile: features, bytes,
+                                     additive predictions (kf_run is refused) */
 };
+struct kf_routine_entry;
 typedef struct kf_compile_opts {
     int32_t mode;            /* KF_MODE_*                                         */
     int32_t flags;           /* KF_COMPILE_*                                      */
@@ -134,7 +140,14 @@ typedef struct kf_compile_opts {
      * recording order), ids 0..K-1. */
     const int32_t* partition;
     int32_t partition_len;
-    int32_t reserved[8];
+    /* KF_MODE_ADDITIVE: the routine table, the number of partitions considered
+     * (0 = 64) and the implementation-parameter points to cross them with
+     * (NULL = every environment present in the table). */
+    const struct kf_routine_entry* table;
+    int32_t table_len;
+    int32_t max_partitions;
+    const struct kf_compile_opts* grid;
+    int32_t grid_len;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
@@ -153,6 +166,26 @@ void kf_planset_destroy(kf_planset* ps);
 kf_status kf_planset_count(const kf_planset* ps, int32_t* n);
 /* partition[call] = kernel id for plan i (len = number of calls). */
 kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, int32_t len);
+
+/* Candidate plans (Section 4.2, "combinations of fusion implementations"):
+ * the first max_partitions legal partitions crossed with the implementation
+ * parameter points grid[0..grid_len) (mode and partition fields ignored; only
+ * the fields of the kernel classes present matter, and candidates whose
+ * kernels would be identical are listed once). */
+kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_compile_opts* grid,
+                        int32_t grid_len, kf_planset** out);
+/* Parameters of candidate i (mode = KF_MODE_PARTITION, partition pointing into
+ * the planset, valid while it lives). */
+kf_status kf_planset_params(const kf_planset* ps, int32_t i, kf_compile_opts* out);
+/* Compile candidate i with `flags` (KF_COMPILE_*). */
+kf_status kf_planset_compile(const kf_planset* ps, int32_t i, int32_t flags, kf_plan** out);
+/* Compile the kernels of candidates idx[0..n) as one hipRTC unit into the
+ * KF_CACHE_DIR disk cache (no GPU needed); later kf_planset_compile calls in
+ * any process find them there. */
+kf_status kf_planset_precompile(const kf_planset* ps, const int32_t* idx, int32_t n);
+/* Additive predictions (us) of every candidate (no compilation). */
+kf_status kf_planset_predict_additive(const kf_planset* ps, const kf_routine_entry* table,
+                                      int32_t table_len, float* pred_us);
 
 /* ---- bind and run --------------------------------------------------------- */
 /* Bytes of device workspace the plan needs: partial sums of reductions and
@@ -196,6 +229,106 @@ kf_status kf_plan_num_kernels(const kf_plan* p, int32_t* n);
 kf_status kf_plan_source(const kf_plan* p, int32_t k, char* buf, size_t cap, size_t* needed);
 /* Launch geometry of kernel k: grid (workgroups) and block (threads). */
 kf_status kf_plan_kernel_geometry(const kf_plan* p, int32_t k, int32_t* grid, int32_t* block);
+
+/* ---- plan ranking (Section 4.2: performance prediction) ------------------- */
+/* Routines of the additive predictor. The paper benchmarks each routine of an
+ * elementary function (loads, compute, stores) in a simulated fusion
+ * environment and predicts a fusion as max(sum of transfer times, sum of
+ * compute times). Here a routine is timed alone by a probe kernel with the
+ * workgroup geometry and serial iterations of a real kernel:
+ *   LOAD_MAT / STORE_MAT     stream a matrix from / to HBM (per element),
+ *   COMPUTE_GEMV/GEMTV/GER   the call's arithmetic on on-chip (LDS) tiles,
+ *   LOAD_VEC / STORE_VEC     stream a vector (per entry),
+ *   COMPUTE_SCAL/AXPY/DOT    the call's arithmetic on register data,
+ *   FINISH                   one finishing launch (per launch).            */
+enum {
+    KF_ROUTINE_LOAD_MAT = 0, KF_ROUTINE_STORE_MAT = 1, KF_ROUTINE_COMPUTE_GEMV = 2,
+    KF_ROUTINE_COMPUTE_GEMTV = 3, KF_ROUTINE_COMPUTE_GER = 4, KF_ROUTINE_LOAD_VEC = 5,
+    KF_ROUTINE_STORE_VEC = 6, KF_ROUTINE_COMPUTE_SCAL = 7, KF_ROUTINE_COMPUTE_AXPY = 8,
+    KF_ROUTINE_COMPUTE_DOT = 9, KF_ROUTINE_FINISH = 10, KF_NUM_ROUTINES = 11
+};
+/* One entry of the routine table: the environment (BLAS-2: mat_k, mat_waves,
+ * mat_group, mat_rows; BLAS-1: vec_unroll, vec_threads, vec_grid, 0) and the
+ * time per unit in microseconds (per matrix element, per vector entry, or per
+ * launch for FINISH). */
+typedef struct kf_routine_entry {
+    int32_t cls;          /* 0 = BLAS-1, 1 = BLAS-2 */
+    int32_t env[4];
+    int32_t routine;      /* KF_ROUTINE_* */
+    float us_per_unit;
+} kf_routine_entry;
+/* Time routine `routine` alone on a rows x cols matrix (BLAS-2 routines; ld =
+ * cols, a multiple of 4) or on a rows-entry vector (BLAS-1 routines; cols
+ * ignored) with the implementation parameters of `params` (mode ignored).
+ * `buf` is a device buffer of at least rows*cols*4 + 65536 bytes (vector:
+ * rows*4 + 65536); its contents are overwritten. Median of `reps` runs.
+ * KF_ROUTINE_FINISH is not a probe (time a finishing launch instead). */
+kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols,
+                          const kf_compile_opts* params, void* buf, size_t buf_bytes,
+                          void* stream, int32_t warmup, int32_t reps, float* median_us);
+/* Additive prediction of a plan: for each kernel, max(t_t, t_c) with t_t the
+ * sum of its transfer routines (every matrix and vector it moves through HBM)
+ * and t_c the sum of its compute routines (one per call), plus one FINISH per
+ * finishing launch; summed over kernels. Entries are matched on class and
+ * environment; KF_ERR_UNSUPPORTED if a needed entry is missing. */
+kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n,
+                              float* us);
+
+/* Features of every kernel of a plan for the learned cost model: `rows` x
+ * KF_FEATURE_DIM floats, row k for plan kernel k (in plan order). Features:
+ *  0 BLAS-2 flag; 1 log2 rows (or n); 2 log2 cols; 3 log2 bytes read;
+ *  4 log2 bytes written; 5 log2 bytes saved against one kernel per call;
+ *  6..11 number of scal, axpy, dot, gemv, gemtv, ger calls; 12/13 matrices
+ *  loaded/stored; 14/15 vectors (and device scalars) loaded/stored; 16 k;
+ *  17 waves; 18 log2 group; 19 log2 rows per workgroup; 20 vec unroll;
+ *  21 vec threads/256; 22 log2 vec grid; 23 log2 workgroups of the main
+ *  launch; 24 log2 threads per workgroup; 25 launches; 26 log2 workspace
+ *  floats; 27 LDS bytes/4096; 28 calls; 29 chained y0; 30 log2 elements of
+ *  the iteration space; 31 written share of the bytes.
+ * *nk receives the number of kernels; KF_ERR_ARG if rows < *nk. */
+#define KF_FEATURE_DIM 32
+kf_status kf_plan_features(const kf_plan* p, float* out, int32_t rows, int32_t* nk);
+
+/* ---- learned cost model ---------------------------------------------------- */
+/* A multilayer perceptron in_dim -> hidden (x layers, ReLU) -> 1 that maps the
+ * (normalised) features of one plan kernel to its log run time. Parameters,
+ * gradients, Adam moments, inputs and the workspace are caller-owned device
+ * buffers of FP32; layer l's weights are a row-major in x out matrix at
+ * w_off (kf_mlp_layout) followed by its out biases at b_off. Every product runs
+ * on the GPU (16x16x4 FP32 matrix-core instructions); results are
+ * bit-reproducible. The stream argument is a hipStream_t. */
+typedef struct kf_mlp kf_mlp;
+kf_status kf_mlp_create(int32_t in_dim, int32_t hidden, int32_t layers, kf_mlp** out);
+void kf_mlp_destroy(kf_mlp* m);
+kf_status kf_mlp_param_count(const kf_mlp* m, int64_t* n);
+kf_status kf_mlp_layout(const kf_mlp* m, int32_t layer, int64_t* w_off, int64_t* b_off,
+                        int64_t* rows, int64_t* cols);
+/* He-uniform weights (SplitMix64 stream from `seed`), zero biases, written to
+ * a host array of kf_mlp_param_count floats. */
+kf_status kf_mlp_init_params(const kf_mlp* m, uint64_t seed, float* host_params);
+kf_status kf_mlp_workspace_bytes(const kf_mlp* m, int32_t batch, size_t* bytes);
+/* pred[0..n) = network(X) for X of n x in_dim (row-major). */
+kf_status kf_mlp_forward(const kf_mlp* m, const float* params, const float* X, int32_t n,
+                         float* pred, void* ws, size_t ws_bytes, void* stream);
+/* Mean squared error of network(X) against y[0..n) into *loss (device float),
+ * and its gradient with respect to every parameter into grads (overwritten). */
+kf_status kf_mlp_loss_grad(const kf_mlp* m, const float* params, const float* X, const float* y,
+                           int32_t n, float* grads, float* loss, void* ws, size_t ws_bytes,
+                           void* stream);
+/* One Adam step (Kingma and Ba) with bias correction for step `step` >= 1. */
+kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float* mstate,
+                      float* vstate, int32_t step, float lr, float beta1, float beta2, float eps,
+                      void* stream);
+
+/* ---- run-time compilation cache ------------------------------------------ */
+/* Each plan kernel is compiled by hipRTC for gfx950 once per process (keyed
+ * by a hash of its text); if the environment variable KF_CACHE_DIR names a
+ * directory, code objects are also read from and written to it, so several
+ * processes can share compilations. kf_jit_release unloads every loaded
+ * module: all plans must have been destroyed before. kf_jit_stats reports the
+ * number of loaded modules and of kernels compiled in this process. */
+kf_status kf_jit_release(void);
+kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
 
 /* ---- measurement helper -------------------------------------------------- */
 /* dst[0..bytes) = src[0..bytes) with a plain streaming kernel (128-bit

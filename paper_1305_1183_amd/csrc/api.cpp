@@ -23,8 +23,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
 // loaded for the life of the process so plans can share kernels.
 struct Registry {
     std::mutex mu;
-    std::map<std::string, hipFunction_t> funcs;
-    std::map<std::string, std::string> code;     // name -> code object (no-load mode)
+    std::map<std::string, hipFunction_t> funcs;  // launch name -> loaded function
+    std::set<std::string> compiled;               // kernel names compiled in this process
     std::vector<hipModule_t> modules;
 };
 static Registry& registry() {
@@ -32,30 +32,37 @@ static Registry& registry() {
     return *r;
 }
 
+// Compile (through the caches) and load one kernel; fills fns with one
+// function per launch.
+kf_status load_kernel(const KernelCode& kc, std::vector<void*>* fns) {
+    Registry& reg = registry();
+    std::lock_guard<std::mutex> lock(reg.mu);
+    bool have = true;
+    for (const Launch& l : kc.launches)
+        if (!reg.funcs.count(l.name)) have = false;
+    if (!have) {
+        std::string co, log;
+        if (!jit_compile_one(kc, &co, &log)) return set_error(KF_ERR_COMPILE, log);
+        reg.compiled.insert(kc.name);
+        hipModule_t mod = nullptr;
+        hipError_t e = hipModuleLoadData(&mod, co.data());
+        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+        reg.modules.push_back(mod);
+        for (const Launch& l : kc.launches) {
+            hipFunction_t fn = nullptr;
+            e = hipModuleGetFunction(&fn, mod, l.name.c_str());
+            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+            reg.funcs[l.name] = fn;
+        }
+    }
+    fns->clear();
+    for (const Launch& l : kc.launches) fns->push_back((void*)reg.funcs[l.name]);
+    return KF_OK;
+}
+
 }  // namespace kf
 
 using namespace kf;
-
-struct PlanKernel {
-    KernelCode code;
-    std::vector<hipFunction_t> fns;   // one per launch
-    size_t ws_off = 0;   // bytes from workspace base to this kernel's partial sums
-};
-
-struct kf_plan {
-    Script s;
-    std::vector<int> part;
-    std::vector<PlanKernel> ks;
-    std::vector<void*> bind;          // per value (caller buffers)
-    std::vector<float> consts;        // per value (kf_const)
-    std::vector<size_t> inter_off;    // per value: workspace offset of intermediates, or SIZE_MAX
-    std::vector<char> is_read, is_written;
-    void* ws = nullptr;
-    size_t ws_bound = 0;
-    size_t ws_need = 0;
-    bool loaded = false;
-    int mode = 0;
-};
 
 static const char* kVersion = "kfuse 0.1 gfx950";
 
@@ -352,7 +359,7 @@ static size_t value_bytes(const Value& v) {
     }
 }
 
-static kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_compile_opts& o,
+kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_compile_opts& o,
                             kf_plan** out) {
     const int ncall = (int)sc.calls.size();
     if ((int)part.size() != ncall) return set_error(KF_ERR_ARG, "partition length != number of calls");
@@ -377,6 +384,8 @@ static kf_status build_plan(const Script& sc, const std::vector<int>& part, cons
     p->part = part;
     p->mode = o.mode;
     const size_t nv = sc.values.size();
+    p->mp.k = o.mat_k; p->mp.waves = o.mat_waves; p->mp.group = o.mat_group; p->mp.rows = o.mat_rows;
+    p->vp.unroll = o.vec_unroll; p->vp.threads = o.vec_threads; p->vp.grid = o.vec_grid;
     p->bind.assign(nv, nullptr);
     p->consts.assign(nv, 0.f);
     p->inter_off.assign(nv, SIZE_MAX);
@@ -432,42 +441,43 @@ static kf_status build_plan(const Script& sc, const std::vector<int>& part, cons
     }
     p->ws_need = off;
 
+    if (o.flags & KF_COMPILE_CODEGEN_ONLY) {   // plan structure only: features, bytes, predictions
+        p->loaded = false;
+        *out = guard.release();
+        return KF_OK;
+    }
     // compile (and load) the kernels not yet known
     Registry& reg = registry();
     std::lock_guard<std::mutex> lock(reg.mu);
     const bool load = !(o.flags & KF_COMPILE_NO_LOAD);
-    std::vector<const KernelCode*> todo;
-    std::set<std::string> names;
     for (auto& k : p->ks) {
-        bool have = load ? reg.funcs.count(k.code.name) : reg.code.count(k.code.name);
-        if (!have && names.insert(k.code.name).second) todo.push_back(&k.code);
-    }
-    if (!todo.empty()) {
+        const std::string& nm = k.code.name;
+        bool have = load ? reg.funcs.count(nm) > 0 : (reg.compiled.count(nm) > 0 || reg.funcs.count(nm) > 0);
+        if (have) continue;
         std::string co, log;
-        if (!jit_compile(todo, &co, &log)) return set_error(KF_ERR_COMPILE, log);
-        if (load) {
-            hipModule_t mod = nullptr;
-            hipError_t e = hipModuleLoadData(&mod, co.data());
-            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
-            reg.modules.push_back(mod);
-            for (const KernelCode* k : todo)
-                for (const Launch& l : k->launches) {
-                    hipFunction_t fn = nullptr;
-                    e = hipModuleGetFunction(&fn, mod, l.name.c_str());
-                    if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
-                    reg.funcs[l.name] = fn;
-                }
-        } else {
-            for (const KernelCode* k : todo) reg.code[k->name] = "compiled";
+        if (!jit_compile_one(k.code, &co, &log)) return set_error(KF_ERR_COMPILE, log);
+        reg.compiled.insert(nm);
+        if (!load) continue;
+        hipModule_t mod = nullptr;
+        hipError_t e = hipModuleLoadData(&mod, co.data());
+        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+        reg.modules.push_back(mod);
+        for (const Launch& l : k.code.launches) {
+            hipFunction_t fn = nullptr;
+            e = hipModuleGetFunction(&fn, mod, l.name.c_str());
+            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+            reg.funcs[l.name] = fn;
         }
     }
     if (load)
         for (auto& k : p->ks)
-            for (const Launch& l : k.code.launches) k.fns.push_back(reg.funcs[l.name]);
+            for (const Launch& l : k.code.launches) k.fns.push_back((void*)reg.funcs[l.name]);
     p->loaded = load;
     *out = guard.release();
     return KF_OK;
 }
+
+kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
 
 extern "C" {
 
@@ -488,9 +498,12 @@ kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** 
                 part.assign(o.partition, o.partition + o.partition_len);
                 break;
             case KF_MODE_ADDITIVE:
+                return compile_additive(s, o, out);
             case KF_MODE_LEARNED:
             case KF_MODE_EXHAUSTIVE:
-                return set_error(KF_ERR_UNSUPPORTED, "search modes are selected through kf_search");
+                return set_error(KF_ERR_UNSUPPORTED,
+                                 "learned and exhaustive ranking need device buffers: use kf_candidates, "
+                                 "kf_planset_features / kf_time_plan and compile the chosen candidate");
             default: return set_error(KF_ERR_ARG, "unknown mode");
         }
         return build_plan(s->s, part, o, out);
@@ -585,7 +598,7 @@ static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, in
             }
             ptrs[i] = &store[i];
         }
-        hipError_t e = hipModuleLaunchKernel(k.fns[li], (unsigned)l.grid, 1, 1, (unsigned)l.block, 1, 1, 0,
+        hipError_t e = hipModuleLaunchKernel((hipFunction_t)k.fns[li], (unsigned)l.grid, 1, 1, (unsigned)l.block, 1, 1, 0,
                                              stream, ptrs, nullptr);
         if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     }
@@ -721,6 +734,24 @@ kf_status kf_plan_describe(const kf_plan* p, char* buf, size_t cap, size_t* need
     o << "], \"bytes_read\": " << r << ", \"bytes_written\": " << w << ", \"workspace_bytes\": " << p->ws_need
       << "}";
     return copy_out(o.str(), buf, cap, needed);
+}
+
+kf_status kf_jit_release(void) {
+    Registry& reg = registry();
+    std::lock_guard<std::mutex> lock(reg.mu);
+    for (hipModule_t m : reg.modules) (void)hipModuleUnload(m);
+    reg.modules.clear();
+    reg.funcs.clear();
+    reg.compiled.clear();
+    return KF_OK;
+}
+
+kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled) {
+    Registry& reg = registry();
+    std::lock_guard<std::mutex> lock(reg.mu);
+    if (modules) *modules = (int64_t)reg.modules.size();
+    if (kernels_compiled) *kernels_compiled = (int64_t)reg.compiled.size();
+    return KF_OK;
 }
 
 kf_status kf_util_copy(void* dst, const void* src, size_t bytes, void* stream) {

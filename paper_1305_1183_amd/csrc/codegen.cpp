@@ -752,3 +752,197 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
 }
 
 }  // namespace kf
+
+namespace kf {
+
+// ============================================================================
+// Routine probes: one routine alone, in the workgroup geometry and serial
+// iterations of a real kernel (Section 4.2: routine times are benchmarked in a
+// simulated fusion environment and summed to predict a fusion).
+// ============================================================================
+KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatParams& mp0,
+                          const VecParams& vp0) {
+    KernelCode kc;
+    Emitter e;
+    std::vector<std::string> sig = {"const float* __restrict__ src", "float* __restrict__ dst",
+                                    "float* __restrict__ sink"};
+    const bool mat = routine <= KF_ROUTINE_COMPUTE_GER;
+    std::string tag;
+    if (mat) {
+        MatParams p = default_mat_params(rows, cols, mp0);
+        const long M = (long)rows, N = (long)cols;
+        const int K = p.k, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
+        int LG = 0;
+        while ((1 << LG) < G) ++LG;
+        const long C = 256L * K, S = (N + C - 1) / C, NB = (M + R - 1) / R;
+        e.l(F("constexpr long M = %ldL, N = %ldL, C = %ldL, S = %ldL, LD = %ldL;", M, N, C, S, N));
+        e.l(F("constexpr int K = %d, W = %d, G = %d, LG = %d, R = %d, NT = %d;", K, W, G, LG, R, NT));
+        e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
+        e.l("const long sidx = blockIdx.x % S, rb = blockIdx.x / S;");
+        e.l("const long c0 = sidx * C, r0 = rb * R, r1 = (r0 + R < M) ? r0 + R : M;");
+        e.l("(void)src; (void)dst; (void)sidx;");
+        e.l("long col[K]; kf_f4 cv[K]; kf_f4 acc[K];");
+        e.l("for (int j = 0; j < K; ++j) { col[j] = c0 + (long)(j * 64 + lane) * 4; cv[j] = kf_zero4() + (float)(lane + j); acc[j] = kf_zero4(); }");
+        e.l("__shared__ kf_f4 tile[8 * K * 64];");
+        e.l("for (int i = tid; i < 8 * K * 64; i += NT) tile[i] = kf_zero4() + 1e-3f * (float)i;");
+        e.l("__syncthreads();");
+        e.l("float s = 0.f;");
+        e.l("for (long g0 = r0 + (long)wave * G; g0 < r1; g0 += (long)W * G) {");
+        e.ind++;
+        switch (routine) {
+            case KF_ROUTINE_LOAD_MAT:
+                e.l("kf_f4 L[G][K];");
+                e.l("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < K; ++j) L[gi][j] = kf_ld4_nt(src + (g0 + gi) * LD + col[j]);");
+                e.l("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < K; ++j) acc[j] += L[gi][j];");
+                tag = "load_mat";
+                break;
+            case KF_ROUTINE_STORE_MAT:
+                e.l("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < K; ++j) kf_st4_nt(dst + (g0 + gi) * LD + col[j], cv[j]);");
+                tag = "store_mat";
+                break;
+            case KF_ROUTINE_COMPUTE_GEMV:
+                e.l("float rp[G];");
+                e.l("for (int gi = 0; gi < G; ++gi) { float t = 0.f; for (int j = 0; j < K; ++j) t = kf_dot4(tile[(((g0 + gi) & 7) * K + j) * 64 + lane], cv[j], t); rp[gi] = t; }");
+                e.l("s += kf_rows_reduce<LG>(rp);");
+                tag = "gemv";
+                break;
+            case KF_ROUTINE_COMPUTE_GEMTV:
+                e.l("for (int gi = 0; gi < G; ++gi) { const float xr = 1e-7f * (float)(g0 + gi); for (int j = 0; j < K; ++j) acc[j] = kf_fma4s(xr, tile[(((g0 + gi) & 7) * K + j) * 64 + lane], acc[j]); }");
+                tag = "gemtv";
+                break;
+            case KF_ROUTINE_COMPUTE_GER:
+                e.l("for (int gi = 0; gi < G; ++gi) { const float cu = 1e-7f * (float)(g0 + gi); for (int j = 0; j < K; ++j) acc[j] += kf_fma4s(cu, cv[j], tile[(((g0 + gi) & 7) * K + j) * 64 + lane]); }");
+                tag = "ger";
+                break;
+        }
+        e.ind--;
+        e.l("}");
+        e.l("for (int j = 0; j < K; ++j) s += (acc[j].x + acc[j].y) + (acc[j].z + acc[j].w);");
+        e.l("if (s == 1234.5678f) sink[tid] = s;");
+        std::string key = F("probe %s K%d W%d G%d R%d M%ld N%ld", tag.c_str(), K, W, G, R, M, N) + e.o.str();
+        kc.name = F("kf_probe_%016llx", (unsigned long long)fnv1a(key));
+        Launch l;
+        l.name = kc.name;
+        l.grid = (int)(S * NB);
+        l.block = NT;
+        kc.launches.push_back(l);
+        kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d}", K, W, G, R);
+        kc.mat = true;
+    } else {
+        VecParams p = default_vec_params(rows, vp0);
+        const long N = (long)rows, N4 = N / 4;
+        const int U = p.unroll, NT = p.threads, GRID = p.grid;
+        e.l(F("constexpr long N4 = %ldL; constexpr int U = %d, NT = %d, GRID = %d;", N4, U, NT, GRID));
+        e.l("constexpr long STEP = (long)NT * U;");
+        e.l("const int tid = threadIdx.x; (void)src; (void)dst;");
+        e.l("kf_f4 acc = kf_zero4(); float d = 0.f; const float a = 1.0001f;");
+        e.l("for (long b = (long)blockIdx.x * STEP; b < N4; b += (long)GRID * STEP) {");
+        e.ind++;
+        e.l("for (int u = 0; u < U; ++u) {");
+        e.ind++;
+        e.l("const long i4 = b + (long)u * NT + tid;");
+        e.l("if (i4 < N4) {");
+        e.ind++;
+        e.l("const kf_f4 x = kf_zero4() + (float)(i4 & 1023);");
+        switch (routine) {
+            case KF_ROUTINE_LOAD_VEC: e.l("acc += kf_ld4_nt(src + 4 * i4);"); tag = "load_vec"; break;
+            case KF_ROUTINE_STORE_VEC: e.l("kf_st4_nt(dst + 4 * i4, x);"); tag = "store_vec"; break;
+            case KF_ROUTINE_COMPUTE_SCAL: e.l("acc += kf_mul4s(a, x);"); tag = "scal"; break;
+            case KF_ROUTINE_COMPUTE_AXPY: e.l("acc = kf_fma4s(a, x, acc);"); tag = "axpy"; break;
+            case KF_ROUTINE_COMPUTE_DOT: e.l("d = kf_dot4(x, x, d);"); tag = "dot"; break;
+        }
+        e.ind--;
+        e.l("}");
+        e.ind--;
+        e.l("}");
+        e.ind--;
+        e.l("}");
+        e.l("const float s = ((acc.x + acc.y) + (acc.z + acc.w)) + d;");
+        e.l("if (s == 1234.5678f) sink[tid] = s;");
+        std::string key = F("probe %s U%d NT%d G%d N%ld", tag.c_str(), U, NT, GRID, N) + e.o.str();
+        kc.name = F("kf_probe_%016llx", (unsigned long long)fnv1a(key));
+        Launch l;
+        l.name = kc.name;
+        l.grid = GRID;
+        l.block = NT;
+        kc.launches.push_back(l);
+        kc.params_json = F("{\"unroll\": %d, \"threads\": %d, \"grid\": %d}", U, NT, GRID);
+        kc.mat = false;
+    }
+    std::string sigs;
+    for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
+    std::ostringstream src;
+    src << "extern \"C\" __global__ void __launch_bounds__(" << kc.launches[0].block << ") " << kc.name
+        << "(\n" << sigs << ") {\n" << e.o.str() << "}\n";
+    kc.source = src.str();
+    return kc;
+}
+
+// ---- features of one plan kernel (inputs of the learned cost model) --------
+static float lg2(double x) { return (float)std::log2(x > 1.0 ? x : 1.0); }
+
+void kernel_features(const Script& s, const KernelCode& kc, const std::vector<int>& part,
+                     const MatParams& mp, const VecParams& vp, float* f) {
+    for (int i = 0; i < KF_FEATURE_DIM; ++i) f[i] = 0.f;
+    const Space sp = call_space(s, kc.calls[0]);
+    const int kid = part[kc.calls[0]];
+    f[0] = sp.mat ? 1.f : 0.f;
+    f[1] = lg2((double)sp.a);
+    f[2] = sp.mat ? lg2((double)sp.b) : 0.f;
+    f[3] = lg2((double)kc.bytes_read + 1);
+    f[4] = lg2((double)kc.bytes_written + 1);
+    // bytes the same calls would move as separate kernels
+    double alone = 0;
+    auto vbytes = [&](int v) -> double {
+        const Value& x = s.values[v];
+        return x.kind == VK::Vec ? 4.0 * x.n : x.kind == VK::Mat ? 4.0 * x.rows * x.cols
+                                                                 : x.kind == VK::DevScalar ? 4.0 : 0.0;
+    };
+    int chained = 0;
+    for (int c : kc.calls) {
+        const Call& k = s.calls[c];
+        int ops[5] = {k.alpha, k.beta, k.in[0], k.in[1], k.in[2]};
+        for (int v : ops)
+            if (v >= 0) alone += vbytes(v);
+        if (s.values[k.out].output || !s.values[k.out].consumers.empty()) alone += vbytes(k.out);
+        f[6 + (int)k.op] += 1.f;
+        if (k.in[2] >= 0 && k.op != Op::Ger && produced_in(s, part, kid, k.in[2])) chained = 1;
+    }
+    f[5] = lg2(alone - (double)(kc.bytes_read + kc.bytes_written) + 1);
+    int mi = 0, mo = 0, vi = 0, vo = 0;
+    for (const Launch& l : kc.launches)
+        for (const KArg& a : l.args) {
+            if (a.kind == ArgKind::MatIn) ++mi;
+            else if (a.kind == ArgKind::MatOut) ++mo;
+            else if (a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn) ++vi;
+            else if (a.kind == ArgKind::VecOut || a.kind == ArgKind::DevScalarOut) ++vo;
+        }
+    f[12] = (float)mi;
+    f[13] = (float)mo;
+    f[14] = (float)vi;
+    f[15] = (float)vo;
+    if (sp.mat) {
+        MatParams p = default_mat_params(sp.a, sp.b, mp);
+        f[16] = (float)p.k;
+        f[17] = (float)p.waves;
+        f[18] = lg2(p.group);
+        f[19] = lg2(p.rows);
+    } else {
+        VecParams p = default_vec_params(sp.a, vp);
+        f[20] = (float)p.unroll;
+        f[21] = (float)p.threads / 256.f;
+        f[22] = lg2(p.grid);
+    }
+    f[23] = lg2(kc.launches[0].grid);
+    f[24] = lg2(kc.launches[0].block);
+    f[25] = (float)kc.launches.size();
+    f[26] = lg2((double)kc.ws_floats + 1);
+    f[27] = (float)kc.lds_bytes / 4096.f;
+    f[28] = (float)kc.calls.size();
+    f[29] = (float)chained;
+    f[30] = lg2(sp.mat ? (double)sp.a * (double)sp.b : (double)sp.a);
+    const double tot = (double)(kc.bytes_read + kc.bytes_written);
+    f[31] = tot > 0 ? (float)(kc.bytes_written / tot) : 0.f;
+}
+
+}  // namespace kf

@@ -1,14 +1,20 @@
 // jit.cpp -- run-time compilation of generated kernels with hipRTC for gfx950.
 //
 // The paper's compiler emits CUDA source and hands it to the vendor compiler
-// (Section 4.3); here the generated HIP source is compiled in-process by
-// hipRTC into a gfx950 code object. All kernels of one request are compiled
-// as one translation unit behind the building-block header.
+// (Section 4.3); here every generated kernel is compiled in-process by hipRTC
+// into a gfx950 code object, one translation unit per plan kernel (building
+// blocks + the kernel's launches). Code objects are cached in memory and, when
+// KF_CACHE_DIR names a directory, on disk under a hash of the unit's text and
+// options, so that separate processes can compile candidate plans in parallel
+// and the process that times them only loads the results.
 #include <hip/hiprtc.h>
-#include <cstdio>
 
+#include <cstdio>
 #include <cstdlib>
+#include <fstream>
 #include <mutex>
+#include <sstream>
+#include <unistd.h>
 
 #include "kf_internal.h"
 
@@ -18,30 +24,61 @@ static const char kBlocksText[] =
 #include "kf_blocks_embed.inc"
     ;
 
+static const char* kOpts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+
 const std::string& blocks_source() {
     static const std::string s(kBlocksText);
     return s;
 }
 
-bool jit_compile(const std::vector<const KernelCode*>& ks, std::string* code_object,
-                 std::string* log) {
-    static std::mutex mu;  // hipRTC programs are independent, but keep logs ordered
-    std::lock_guard<std::mutex> lock(mu);
-    std::string src = blocks_source();
-    src += "\n";
-    for (const KernelCode* k : ks) {
-        src += k->source;
-        src += "\n";
+static uint64_t fnv1a64(const std::string& s, uint64_t h = 1469598103934665603ULL) {
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ULL;
     }
+    return h;
+}
+
+static std::string unit_text(const KernelCode& k) { return blocks_source() + "\n" + k.source; }
+
+static std::string cache_path(const std::string& text) {
+    const char* dir = std::getenv("KF_CACHE_DIR");
+    if (!dir || !*dir) return "";
+    std::string key = text;
+    for (const char* o : kOpts) key += std::string("\n") + o;
+    char name[64];
+    std::snprintf(name, sizeof name, "/kf_%016llx.co", (unsigned long long)fnv1a64(key));
+    return std::string(dir) + name;
+}
+
+static bool read_file(const std::string& path, std::string* out) {
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return false;
+    std::ostringstream ss;
+    ss << f.rdbuf();
+    *out = ss.str();
+    return !out->empty();
+}
+
+static void write_file_atomic(const std::string& path, const std::string& data) {
+    std::string tmp = path + ".tmp" + std::to_string((long long)std::rand()) + std::to_string((long long)(uintptr_t)&data);
+    {
+        std::ofstream f(tmp, std::ios::binary);
+        if (!f) return;
+        f.write(data.data(), (std::streamsize)data.size());
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+static bool rtc_compile(const std::string& text, std::string* code_object, std::string* log) {
     hiprtcProgram prog = nullptr;
-    if (hiprtcCreateProgram(&prog, src.c_str(), "kf_generated.hip", 0, nullptr, nullptr) !=
+    if (hiprtcCreateProgram(&prog, text.c_str(), "kf_generated.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS) {
         *log = "hiprtcCreateProgram failed";
         return false;
     }
-    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof kOpts / sizeof kOpts[0]), kOpts);
     size_t lsz = 0;
     hiprtcGetProgramLogSize(prog, &lsz);
     std::string lg(lsz, '\0');
@@ -50,7 +87,10 @@ bool jit_compile(const std::vector<const KernelCode*>& ks, std::string* code_obj
         *log = std::string("hipRTC: ") + hiprtcGetErrorString(r) + "\n" + lg;
         if (const char* dump = std::getenv("KF_DUMP_FAILED_SOURCE")) {
             FILE* f = std::fopen(dump, "w");
-            if (f) { std::fwrite(src.data(), 1, src.size(), f); std::fclose(f); }
+            if (f) {
+                std::fwrite(text.data(), 1, text.size(), f);
+                std::fclose(f);
+            }
         }
         hiprtcDestroyProgram(&prog);
         return false;
@@ -61,6 +101,54 @@ bool jit_compile(const std::vector<const KernelCode*>& ks, std::string* code_obj
     hiprtcGetCode(prog, &(*code_object)[0]);
     hiprtcDestroyProgram(&prog);
     *log = lg;
+    return true;
+}
+
+bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string* log) {
+    const std::string text = unit_text(k);
+    const std::string path = cache_path(text);
+    if (!path.empty() && read_file(path, code_object)) return true;
+    if (!rtc_compile(text, code_object, log)) return false;
+    if (!path.empty()) write_file_atomic(path, *code_object);
+    return true;
+}
+
+}  // namespace kf
+
+namespace kf {
+
+bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log) {
+    std::vector<const KernelCode*> todo;
+    std::vector<std::string> paths;
+    std::string dummy;
+    for (const KernelCode* k : ks) {
+        std::string path = cache_path(unit_text(*k));
+        if (path.empty()) {
+            *log = "KF_CACHE_DIR is not set";
+            return false;
+        }
+        std::ifstream f(path, std::ios::binary);
+        if (f.good()) continue;
+        bool dup = false;
+        for (const std::string& q : paths)
+            if (q == path) dup = true;
+        if (dup) continue;
+        todo.push_back(k);
+        paths.push_back(path);
+    }
+    if (todo.empty()) return true;
+    std::string text = blocks_source() + "\n";
+    for (const KernelCode* k : todo) text += k->source + "\n";
+    std::string co;
+    if (!rtc_compile(text, &co, log)) return false;
+    // one shared code object; every kernel's cache entry links to it
+    std::string batch = paths[0] + ".batch";
+    write_file_atomic(batch, co);
+    for (const std::string& q : paths) {
+        std::remove(q.c_str());
+        if (::link(batch.c_str(), q.c_str()) != 0) write_file_atomic(q, co);
+    }
+    std::remove(batch.c_str());
     return true;
 }
 

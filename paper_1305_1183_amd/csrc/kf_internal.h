@@ -6,6 +6,7 @@
 #include <set>
 #include <string>
 #include <vector>
+#include <cmath>
 
 #include "../../include/kf.h"
 
@@ -105,22 +106,65 @@ struct KernelCode {
 KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
                            const std::vector<int>& part, const MatParams& mp,
                            const VecParams& vp);
+// Single-routine probe kernel (one launch; args: src, dst, sink).
+KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatParams& mp,
+                          const VecParams& vp);
+// KF_FEATURE_DIM features of one plan kernel.
+void kernel_features(const Script& s, const KernelCode& kc, const std::vector<int>& part,
+                     const MatParams& mp, const VecParams& vp, float* f);
 // Operand-level byte accounting of one kernel (reads, writes) in HBM.
 void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vector<int>& part,
                   uint64_t* rd, uint64_t* wr);
 
 // ---- JIT (jit.cpp) ------------------------------------------------------------
 const std::string& blocks_source();
-// Compile the given kernels (one translation unit) to a code object for gfx950.
-// Returns false and fills log on failure.
-bool jit_compile(const std::vector<const KernelCode*>& ks, std::string* code_object,
-                 std::string* log);
+// Compile one plan kernel (all its launches, one translation unit) to a gfx950
+// code object, through the memory/disk cache. Returns false and fills log on
+// failure.
+bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string* log);
 
 // ---- errors ---------------------------------------------------------------------
 kf_status set_error(kf_status st, const std::string& msg);
 
+// ---- plans -------------------------------------------------------------------
+struct PlanKernel {
+    KernelCode code;
+    std::vector<void*> fns;   // hipFunction_t per launch
+    size_t ws_off = 0;        // bytes from workspace base to this kernel's partial sums
+};
+// Compile (through the caches) and load a kernel (needs a GPU).
+kf_status load_kernel(const KernelCode& kc, std::vector<void*>* fns);
+// Compile several kernels as one translation unit into the disk cache (each
+// kernel's cache entry is a link to the shared code object).
+bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log);
+
 }  // namespace kf
+
+kf_status build_plan(const kf::Script& sc, const std::vector<int>& part, const kf_compile_opts& o,
+                     kf_plan** out);
+
+struct kf_plan {
+    kf::Script s;
+    std::vector<int> part;
+    std::vector<kf::PlanKernel> ks;
+    std::vector<void*> bind;          // per value (caller buffers)
+    std::vector<float> consts;        // per value (kf_const)
+    std::vector<size_t> inter_off;    // per value: workspace offset of intermediates, or SIZE_MAX
+    std::vector<char> is_read, is_written;
+    kf::MatParams mp;                 // requested parameters (0 = default per shape)
+    kf::VecParams vp;
+    void* ws = nullptr;
+    size_t ws_bound = 0;
+    size_t ws_need = 0;
+    bool loaded = false;
+    int mode = 0;
+};
 
 // Opaque C handles.
 struct kf_script { kf::Script s; bool compiled_from = false; };
-struct kf_planset { std::vector<std::vector<int>> parts; };
+struct kf_planset {
+    std::vector<std::vector<int>> parts;      // partition per entry
+    std::vector<kf_compile_opts> params;      // implementation parameters per entry (candidates)
+    kf::Script s;                             // copy of the script (candidates)
+    bool candidates = false;
+};

@@ -1,2 +1,343 @@
-// search.cpp -- plan ranking (filled in with the cost models).
+// search.cpp -- plan ranking: the additive routine predictor, routine probes
+// and the features of the learned cost model (Section 4.2).
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <memory>
+#include <set>
+
 #include "kf_internal.h"
+
+using namespace kf;
+
+namespace {
+
+bool env_match(const kf_routine_entry& e, bool mat, const MatParams& mp, const VecParams& vp) {
+    if (e.cls != (mat ? 1 : 0)) return false;
+    if (mat) return e.env[0] == mp.k && e.env[1] == mp.waves && e.env[2] == mp.group && e.env[3] == mp.rows;
+    return e.env[0] == vp.unroll && e.env[1] == vp.threads && e.env[2] == vp.grid;
+}
+
+const kf_routine_entry* find(const kf_routine_entry* t, int n, bool mat, const MatParams& mp,
+                             const VecParams& vp, int routine) {
+    for (int i = 0; i < n; ++i)
+        if (t[i].routine == routine && env_match(t[i], mat, mp, vp)) return &t[i];
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols, const kf_compile_opts* params,
+                          void* buf, size_t buf_bytes, void* stream, int32_t warmup, int32_t reps,
+                          float* median_us) {
+    if (!buf || !median_us || reps < 1 || warmup < 0) return set_error(KF_ERR_ARG, "bad argument");
+    if (routine < 0 || routine >= KF_ROUTINE_FINISH) return set_error(KF_ERR_ARG, "routine has no probe");
+    const bool mat = routine <= KF_ROUTINE_COMPUTE_GER;
+    if (rows < 1 || (mat && (cols < 4 || cols % 4))) return set_error(KF_ERR_SHAPE, "probe shape");
+    const size_t need = (mat ? (size_t)rows * cols * 4 : (size_t)rows * 4) + 65536;
+    if (buf_bytes < need) return set_error(KF_ERR_WORKSPACE, "probe buffer too small");
+    if ((uintptr_t)buf % 256) return set_error(KF_ERR_ALIGN, "probe buffer must be 256-byte aligned");
+    MatParams mp;
+    VecParams vp;
+    if (params) {
+        mp.k = params->mat_k; mp.waves = params->mat_waves; mp.group = params->mat_group; mp.rows = params->mat_rows;
+        vp.unroll = params->vec_unroll; vp.threads = params->vec_threads; vp.grid = params->vec_grid;
+    }
+    if (mat) {
+        MatParams q = default_mat_params(rows, cols, mp);
+        if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of waves*group");
+    }
+    KernelCode kc;
+    try {
+        kc = generate_probe(routine, rows, cols, mp, vp);
+    } catch (...) {
+        return set_error(KF_ERR_INTERNAL, "probe generation failed");
+    }
+    std::vector<void*> fns;
+    kf_status st = load_kernel(kc, &fns);
+    if (st != KF_OK) return st;
+    const size_t data = mat ? (size_t)rows * cols * 4 : (size_t)rows * 4;
+    void* src = buf;
+    void* dst = buf;
+    void* sink = (char*)buf + (data + 255) / 256 * 256;
+    void* args[3] = {&src, &dst, &sink};
+    hipStream_t s = (hipStream_t)stream;
+    const Launch& l = kc.launches[0];
+    auto launch = [&]() {
+        return hipModuleLaunchKernel((hipFunction_t)fns[0], (unsigned)l.grid, 1, 1, (unsigned)l.block, 1, 1, 0, s,
+                                     args, nullptr);
+    };
+    for (int i = 0; i < warmup; ++i)
+        if (launch() != hipSuccess) return set_error(KF_ERR_HIP, "probe launch");
+    std::vector<hipEvent_t> ev(2 * reps);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) return set_error(KF_ERR_HIP, "hipEventCreate");
+    kf_status out = KF_OK;
+    for (int i = 0; i < reps && out == KF_OK; ++i) {
+        if (hipEventRecord(ev[2 * i], s) != hipSuccess || launch() != hipSuccess ||
+            hipEventRecord(ev[2 * i + 1], s) != hipSuccess)
+            out = set_error(KF_ERR_HIP, "probe launch");
+    }
+    std::vector<float> t;
+    if (out == KF_OK && hipStreamSynchronize(s) != hipSuccess) out = set_error(KF_ERR_HIP, "sync");
+    for (int i = 0; i < reps && out == KF_OK; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess) out = set_error(KF_ERR_HIP, "elapsed");
+        t.push_back(ms * 1000.f);
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (out != KF_OK) return out;
+    std::sort(t.begin(), t.end());
+    *median_us = t.size() % 2 ? t[t.size() / 2] : 0.5f * (t[t.size() / 2 - 1] + t[t.size() / 2]);
+    return KF_OK;
+}
+
+kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n, float* us) {
+    if (!p || !table || !us || n < 1) return set_error(KF_ERR_ARG, "bad argument");
+    double total = 0;
+    for (const PlanKernel& pk : p->ks) {
+        const KernelCode& kc = pk.code;
+        const Space sp = call_space(p->s, kc.calls[0]);
+        const bool mat = sp.mat;
+        MatParams mp = mat ? default_mat_params(sp.a, sp.b, p->mp) : MatParams();
+        VecParams vp = mat ? VecParams() : default_vec_params(sp.a, p->vp);
+        auto get = [&](int r) -> const kf_routine_entry* { return find(table, n, mat, mp, vp, r); };
+        double tt = 0, tc = 0;
+        // transfers: every operand the kernel's launches move through HBM
+        for (const Launch& l : kc.launches)
+            for (const KArg& a : l.args) {
+                if (a.value < 0) continue;
+                const Value& x = p->s.values[a.value];
+                double elems = x.kind == VK::Mat ? (double)x.rows * x.cols : x.kind == VK::Vec ? (double)x.n
+                                                                              : x.kind == VK::DevScalar ? 1.0 : 0.0;
+                if (elems == 0) continue;
+                bool in = a.kind == ArgKind::MatIn || a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn;
+                bool outk = a.kind == ArgKind::MatOut || a.kind == ArgKind::VecOut || a.kind == ArgKind::DevScalarOut;
+                if (!in && !outk) continue;
+                int r;
+                if (mat) r = in ? KF_ROUTINE_LOAD_MAT : KF_ROUTINE_STORE_MAT;  // vectors priced per element as matrix data
+                else r = in ? KF_ROUTINE_LOAD_VEC : KF_ROUTINE_STORE_VEC;
+                const kf_routine_entry* e = get(r);
+                if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no transfer entry for this environment");
+                tt += elems * e->us_per_unit;
+            }
+        for (int c : kc.calls) {
+            int r = -1;
+            switch (p->s.calls[c].op) {
+                case Op::Scal: r = KF_ROUTINE_COMPUTE_SCAL; break;
+                case Op::Axpy: r = KF_ROUTINE_COMPUTE_AXPY; break;
+                case Op::Dot: r = KF_ROUTINE_COMPUTE_DOT; break;
+                case Op::Gemv: r = KF_ROUTINE_COMPUTE_GEMV; break;
+                case Op::Gemtv: r = KF_ROUTINE_COMPUTE_GEMTV; break;
+                case Op::Ger: r = KF_ROUTINE_COMPUTE_GER; break;
+            }
+            const kf_routine_entry* e = get(r);
+            if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no compute entry for this environment");
+            tc += (mat ? (double)sp.a * sp.b : (double)sp.a) * e->us_per_unit;
+        }
+        double t = std::max(tt, tc);
+        if (kc.launches.size() > 1) {
+            const kf_routine_entry* e = get(KF_ROUTINE_FINISH);
+            if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no FINISH entry for this environment");
+            t += (double)(kc.launches.size() - 1) * e->us_per_unit;
+        }
+        total += t;
+    }
+    *us = (float)total;
+    return KF_OK;
+}
+
+kf_status kf_plan_features(const kf_plan* p, float* out, int32_t rows, int32_t* nk) {
+    if (!p || !nk) return set_error(KF_ERR_ARG, "null argument");
+    *nk = (int32_t)p->ks.size();
+    if (!out) return KF_OK;
+    if (rows < *nk) return set_error(KF_ERR_ARG, "feature buffer has too few rows");
+    for (size_t k = 0; k < p->ks.size(); ++k)
+        kernel_features(p->s, p->ks[k].code, p->part, p->mp, p->vp, out + k * KF_FEATURE_DIM);
+    return KF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// candidates
+// ---------------------------------------------------------------------------
+namespace {
+
+kf_compile_opts cand_opts(const kf_planset* ps, int i) {
+    kf_compile_opts o = ps->params[i];
+    o.mode = KF_MODE_PARTITION;
+    o.partition = ps->parts[i].data();
+    o.partition_len = (int32_t)ps->parts[i].size();
+    o.table = nullptr;
+    o.table_len = 0;
+    o.grid = nullptr;
+    o.grid_len = 0;
+    return o;
+}
+
+// Default parameter points: the autotuner's best points for large shapes.
+std::vector<kf_compile_opts> default_grid() {
+    std::vector<kf_compile_opts> g;
+    const int mat[][4] = {{1, 4, 4, 1024}, {2, 8, 2, 1024}, {1, 4, 4, 256}, {2, 4, 4, 512}};
+    const int vec[][3] = {{4, 256, 2048}, {4, 256, 4096}, {2, 256, 1024}};
+    for (auto& m : mat)
+        for (auto& v : vec) {
+            kf_compile_opts o;
+            kf_compile_opts_init(&o);
+            o.mat_k = m[0]; o.mat_waves = m[1]; o.mat_group = m[2]; o.mat_rows = m[3];
+            o.vec_unroll = v[0]; o.vec_threads = v[1]; o.vec_grid = v[2];
+            g.push_back(o);
+        }
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_compile_opts* grid, int32_t grid_len,
+                        kf_planset** out) {
+    if (!s || !out) return set_error(KF_ERR_ARG, "null argument");
+    if (s->s.calls.empty()) return set_error(KF_ERR_STATE, "script has no calls");
+    try {
+        auto* ps = new kf_planset();
+        std::unique_ptr<kf_planset> guard(ps);
+        ps->s = s->s;
+        ps->candidates = true;
+        std::vector<kf_compile_opts> g = grid && grid_len > 0 ? std::vector<kf_compile_opts>(grid, grid + grid_len)
+                                                              : default_grid();
+        auto parts = enumerate_partitions(s->s, max_partitions > 0 ? max_partitions : 64);
+        bool has_mat = false, has_vec = false;
+        for (size_t c = 0; c < s->s.calls.size(); ++c) (call_space(s->s, (int)c).mat ? has_mat : has_vec) = true;
+        std::set<std::string> seen;
+        for (const auto& part : parts)
+            for (const auto& go : g) {
+                kf_compile_opts o = go;
+                if (!has_mat) o.mat_k = o.mat_waves = o.mat_group = o.mat_rows = 0;
+                if (!has_vec) o.vec_unroll = o.vec_threads = o.vec_grid = 0;
+                o.mode = KF_MODE_PARTITION;
+                o.partition = part.data();
+                o.partition_len = (int32_t)part.size();
+                o.table = nullptr; o.table_len = 0; o.grid = nullptr; o.grid_len = 0;
+                o.flags = KF_COMPILE_CODEGEN_ONLY;
+                kf_plan* p = nullptr;
+                if (build_plan(s->s, part, o, &p) != KF_OK) continue;  // illegal point for this shape
+                std::string sig;
+                for (auto& k : p->ks) sig += k.code.name + ",";
+                kf_plan_destroy(p);
+                if (!seen.insert(sig).second) continue;
+                o.flags = 0;
+                ps->parts.push_back(part);
+                ps->params.push_back(o);
+            }
+        *out = guard.release();
+    } catch (const std::bad_alloc&) {
+        return set_error(KF_ERR_NOMEM, "host allocation failed");
+    }
+    return KF_OK;
+}
+
+kf_status kf_planset_params(const kf_planset* ps, int32_t i, kf_compile_opts* out) {
+    if (!ps || !out || !ps->candidates) return set_error(KF_ERR_ARG, "not a candidate set");
+    if (i < 0 || i >= (int32_t)ps->parts.size()) return set_error(KF_ERR_ARG, "index out of range");
+    *out = cand_opts(ps, i);
+    return KF_OK;
+}
+
+kf_status kf_planset_compile(const kf_planset* ps, int32_t i, int32_t flags, kf_plan** out) {
+    if (!ps || !out || !ps->candidates) return set_error(KF_ERR_ARG, "not a candidate set");
+    if (i < 0 || i >= (int32_t)ps->parts.size()) return set_error(KF_ERR_ARG, "index out of range");
+    kf_compile_opts o = cand_opts(ps, i);
+    o.flags = flags;
+    try {
+        return build_plan(ps->s, ps->parts[i], o, out);
+    } catch (const std::bad_alloc&) {
+        return set_error(KF_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+kf_status kf_planset_precompile(const kf_planset* ps, const int32_t* idx, int32_t n) {
+    if (!ps || !ps->candidates || (n > 0 && !idx)) return set_error(KF_ERR_ARG, "bad argument");
+    std::vector<kf_plan*> plans;
+    std::vector<const KernelCode*> ks;
+    std::set<std::string> names;
+    kf_status st = KF_OK;
+    for (int j = 0; j < n && st == KF_OK; ++j) {
+        kf_plan* p = nullptr;
+        st = kf_planset_compile(ps, idx[j], KF_COMPILE_CODEGEN_ONLY, &p);
+        if (st != KF_OK) break;
+        plans.push_back(p);
+        for (auto& k : p->ks)
+            if (names.insert(k.code.name).second) ks.push_back(&k.code);
+    }
+    std::string log;
+    if (st == KF_OK && !jit_precompile(ks, &log)) st = set_error(KF_ERR_COMPILE, log);
+    for (kf_plan* p : plans) kf_plan_destroy(p);
+    return st;
+}
+
+kf_status kf_planset_predict_additive(const kf_planset* ps, const kf_routine_entry* table, int32_t table_len,
+                                      float* pred_us) {
+    if (!ps || !ps->candidates || !pred_us) return set_error(KF_ERR_ARG, "bad argument");
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        kf_plan* p = nullptr;
+        kf_status st = kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p);
+        if (st != KF_OK) return st;
+        st = kf_predict_additive(p, table, table_len, &pred_us[i]);
+        kf_plan_destroy(p);
+        if (st != KF_OK) return st;
+    }
+    return KF_OK;
+}
+
+}  // extern "C"
+
+kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {
+    if (!o.table || o.table_len < 1) return set_error(KF_ERR_ARG, "KF_MODE_ADDITIVE needs a routine table");
+    std::vector<kf_compile_opts> grid;
+    if (o.grid && o.grid_len > 0) {
+        grid.assign(o.grid, o.grid + o.grid_len);
+    } else {
+        // every (BLAS-2 environment, BLAS-1 environment) pair present in the table
+        std::vector<std::array<int, 4>> me, ve;
+        for (int i = 0; i < o.table_len; ++i) {
+            std::array<int, 4> e = {o.table[i].env[0], o.table[i].env[1], o.table[i].env[2], o.table[i].env[3]};
+            auto& v = o.table[i].cls ? me : ve;
+            if (std::find(v.begin(), v.end(), e) == v.end()) v.push_back(e);
+        }
+        if (me.empty()) me.push_back({0, 0, 0, 0});
+        if (ve.empty()) ve.push_back({0, 0, 0, 0});
+        for (auto& m : me)
+            for (auto& v : ve) {
+                kf_compile_opts g;
+                kf_compile_opts_init(&g);
+                g.mat_k = m[0]; g.mat_waves = m[1]; g.mat_group = m[2]; g.mat_rows = m[3];
+                g.vec_unroll = v[0]; g.vec_threads = v[1]; g.vec_grid = v[2];
+                grid.push_back(g);
+            }
+    }
+    kf_planset* ps = nullptr;
+    kf_status st = kf_candidates(s, o.max_partitions, grid.data(), (int32_t)grid.size(), &ps);
+    if (st != KF_OK) return st;
+    std::unique_ptr<kf_planset> guard(ps);
+    std::vector<float> pred(ps->parts.size());
+    int best = -1;
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        kf_plan* p = nullptr;
+        if (kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p) != KF_OK) continue;
+        float us = 0;
+        kf_status e = kf_predict_additive(p, o.table, o.table_len, &us);
+        kf_plan_destroy(p);
+        if (e != KF_OK) continue;
+        // within 0.1% counts as equal (Table 4): keep the earlier candidate (fewer kernels first)
+        if (best < 0 || us < pred[best] * 0.999f) best = (int)i;
+        pred[i] = us;
+    }
+    if (best < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be predicted with this routine table");
+    return kf_planset_compile(ps, best, o.flags, out);
+}

@@ -28,6 +28,7 @@ ERRORS = {
 KF_NONE = -1
 MODES = {"unfused": 0, "fused": 1, "additive": 2, "learned": 3, "exhaustive": 4, "partition": 5}
 KF_COMPILE_NO_LOAD = 1
+KF_COMPILE_CODEGEN_ONLY = 2
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -45,13 +46,26 @@ class KFError(RuntimeError):
         self.name = ERRORS.get(status, str(status))
 
 
-class kf_compile_opts(ctypes.Structure):
-    _fields_ = [("mode", _i32), ("flags", _i32),
-                ("mat_k", _i32), ("mat_waves", _i32), ("mat_group", _i32), ("mat_rows", _i32),
-                ("vec_unroll", _i32), ("vec_threads", _i32), ("vec_grid", _i32),
-                ("partition", _P(_i32)), ("partition_len", _i32),
-                ("reserved", _i32 * 8)]
+class kf_routine_entry(ctypes.Structure):
+    _fields_ = [("cls", _i32), ("env", _i32 * 4), ("routine", _i32), ("us_per_unit", _f32)]
 
+
+class kf_compile_opts(ctypes.Structure):
+    pass
+
+
+kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
+                            ("mat_k", _i32), ("mat_waves", _i32), ("mat_group", _i32), ("mat_rows", _i32),
+                            ("vec_unroll", _i32), ("vec_threads", _i32), ("vec_grid", _i32),
+                            ("partition", _P(_i32)), ("partition_len", _i32),
+                            ("table", _P(kf_routine_entry)), ("table_len", _i32), ("max_partitions", _i32),
+                            ("grid", _P(kf_compile_opts)), ("grid_len", _i32)]
+PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid"]
+
+
+ROUTINES = ["LOAD_MAT", "STORE_MAT", "COMPUTE_GEMV", "COMPUTE_GEMTV", "COMPUTE_GER", "LOAD_VEC",
+            "STORE_VEC", "COMPUTE_SCAL", "COMPUTE_AXPY", "COMPUTE_DOT", "FINISH"]
+FEATURE_DIM = 32
 
 _SIGS = {
     "kf_last_error": ([], ctypes.c_char_p),
@@ -79,6 +93,11 @@ _SIGS = {
     "kf_planset_destroy": ([_vp], None),
     "kf_planset_count": ([_vp, _P(_i32)], _i32),
     "kf_planset_get": ([_vp, _i32, _P(_i32), _i32], _i32),
+    "kf_candidates": ([_vp, _i32, _P(kf_compile_opts), _i32, _P(_vp)], _i32),
+    "kf_planset_params": ([_vp, _i32, _P(kf_compile_opts)], _i32),
+    "kf_planset_compile": ([_vp, _i32, _i32, _P(_vp)], _i32),
+    "kf_planset_precompile": ([_vp, _P(_i32), _i32], _i32),
+    "kf_planset_predict_additive": ([_vp, _P(kf_routine_entry), _i32, _P(_f32)], _i32),
     "kf_plan_workspace_bytes": ([_vp, _P(_sz)], _i32),
     "kf_bind": ([_vp, _i32, _vp], _i32),
     "kf_bind_workspace": ([_vp, _vp, _sz], _i32),
@@ -94,6 +113,20 @@ _SIGS = {
     "kf_plan_source": ([_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)], _i32),
     "kf_plan_kernel_geometry": ([_vp, _i32, _P(_i32), _P(_i32)], _i32),
     "kf_util_copy": ([_vp, _vp, _sz, _vp], _i32),
+    "kf_jit_release": ([], _i32),
+    "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_predict_additive": ([_vp, _P(kf_routine_entry), _i32, _P(_f32)], _i32),
+    "kf_plan_features": ([_vp, _P(_f32), _i32, _P(_i32)], _i32),
+    "kf_mlp_create": ([_i32, _i32, _i32, _P(_vp)], _i32),
+    "kf_mlp_destroy": ([_vp], None),
+    "kf_mlp_param_count": ([_vp, _P(_i64)], _i32),
+    "kf_mlp_layout": ([_vp, _i32, _P(_i64), _P(_i64), _P(_i64), _P(_i64)], _i32),
+    "kf_mlp_init_params": ([_vp, _u64, _P(_f32)], _i32),
+    "kf_mlp_workspace_bytes": ([_vp, _i32, _P(_sz)], _i32),
+    "kf_mlp_forward": ([_vp, _vp, _vp, _i32, _vp, _vp, _sz, _vp], _i32),
+    "kf_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
+    "kf_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
+    "kf_jit_stats": ([_P(_i64), _P(_i64)], _i32),
 }
 EXPORTED = sorted(_SIGS)
 
@@ -208,15 +241,28 @@ def kf_script_num_calls(s) -> int:
 
 
 # ---- compile / enumerate --------------------------------------------------------
-def kf_compile_opts_init(mode="fused", flags=0, partition=None, **params) -> kf_compile_opts:
+def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid=None, max_partitions=0,
+                         **params) -> kf_compile_opts:
     o = kf_compile_opts()
     lib().kf_compile_opts_init(ctypes.byref(o))
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.flags = flags
+    o.max_partitions = max_partitions
     for k, v in params.items():
-        if not hasattr(o, k):
+        if k not in PARAM_FIELDS:
             raise TypeError("unknown compile option %s" % k)
         setattr(o, k, int(v))
+    keep = []
+    if table is not None:
+        o.table = ctypes.cast(table, _P(kf_routine_entry))
+        o.table_len = len(table)
+        keep.append(table)
+    if grid is not None:
+        garr = grid_array(grid)
+        o.grid = ctypes.cast(garr, _P(kf_compile_opts))
+        o.grid_len = len(garr)
+        keep.append(garr)
+    o._keep = keep
     if partition is not None:
         arr = (_i32 * len(partition))(*partition)
         o.partition = ctypes.cast(arr, _P(_i32))
@@ -253,6 +299,70 @@ def kf_enumerate(s, max_plans: int = 0) -> list:
         return out
     finally:
         lib().kf_planset_destroy(h)
+
+
+def grid_array(points) -> ctypes.Array:
+    """Array of kf_compile_opts from dicts of implementation parameters."""
+    points = list(points)
+    arr = (kf_compile_opts * max(1, len(points)))()
+    for i, pt in enumerate(points):
+        lib().kf_compile_opts_init(ctypes.byref(arr[i]))
+        for k, v in pt.items():
+            if k not in PARAM_FIELDS:
+                raise TypeError("unknown parameter %s" % k)
+            setattr(arr[i], k, int(v))
+    return arr
+
+
+class Candidates:
+    """Candidate plans of a script (partitions x parameter points)."""
+
+    def __init__(self, script, max_partitions=64, grid=None):
+        self.script = script
+        h = _vp()
+        garr = grid_array(grid) if grid is not None else None
+        _chk(lib().kf_candidates(script, max_partitions, garr, len(garr) if garr is not None else 0,
+                                 ctypes.byref(h)))
+        self.h = h
+        n = _i32()
+        _chk(lib().kf_planset_count(h, ctypes.byref(n)))
+        self.n = n.value
+        self.ncalls = kf_script_num_calls(script)
+
+    def __len__(self):
+        return self.n
+
+    def __del__(self):
+        try:
+            lib().kf_planset_destroy(self.h)
+        except Exception:
+            pass
+
+    def partition(self, i):
+        buf = (_i32 * max(1, self.ncalls))()
+        _chk(lib().kf_planset_get(self.h, i, buf, self.ncalls))
+        return list(buf[:self.ncalls])
+
+    def params(self, i) -> dict:
+        o = kf_compile_opts()
+        _chk(lib().kf_planset_params(self.h, i, ctypes.byref(o)))
+        return {k: getattr(o, k) for k in PARAM_FIELDS}
+
+    def compile(self, i, flags=0):
+        p = _vp()
+        _chk(lib().kf_planset_compile(self.h, i, flags, ctypes.byref(p)))
+        return p
+
+    def precompile(self, idx) -> None:
+        idx = list(idx)
+        arr = (_i32 * max(1, len(idx)))(*idx)
+        _chk(lib().kf_planset_precompile(self.h, arr, len(idx)))
+
+    def predict_additive(self, table):
+        import numpy as np
+        out = np.zeros(self.n, dtype=np.float32)
+        _chk(lib().kf_planset_predict_additive(self.h, table, len(table), out.ctypes.data_as(_P(_f32))))
+        return out
 
 
 # ---- bind / run ------------------------------------------------------------------
@@ -332,5 +442,105 @@ def kf_plan_kernel_geometry(p, k: int):
     return g.value, b.value
 
 
+def kf_jit_release() -> None:
+    _chk(lib().kf_jit_release())
+
+
+def kf_jit_stats():
+    a, b = _i64(), _i64()
+    _chk(lib().kf_jit_stats(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def kf_util_copy(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
     _chk(lib().kf_util_copy(_vp(dst), _vp(src), nbytes, _vp(stream)))
+
+
+# ---- plan ranking ------------------------------------------------------------------
+def kf_routine_time(routine: int, rows: int, cols: int, buf: int, buf_bytes: int, stream: int = 0,
+                    warmup: int = 2, reps: int = 10, **params) -> float:
+    o = kf_compile_opts_init(**params)
+    t = _f32()
+    _chk(lib().kf_routine_time(routine, rows, cols, ctypes.byref(o), _vp(buf), buf_bytes, _vp(stream),
+                               warmup, reps, ctypes.byref(t)))
+    return t.value
+
+
+def routine_table(entries) -> ctypes.Array:  # noqa: F811
+    """entries: iterable of (cls, (e0, e1, e2, e3), routine, us_per_unit)."""
+    entries = list(entries)
+    arr = (kf_routine_entry * max(1, len(entries)))()
+    for i, (cls, env, r, us) in enumerate(entries):
+        arr[i].cls = cls
+        for j in range(4):
+            arr[i].env[j] = int(env[j])
+        arr[i].routine = r
+        arr[i].us_per_unit = us
+    return arr
+
+
+def kf_predict_additive(p, table) -> float:
+    t = _f32()
+    _chk(lib().kf_predict_additive(p, table, len(table), ctypes.byref(t)))
+    return t.value
+
+
+def kf_plan_features(p):
+    import numpy as np
+    nk = _i32()
+    _chk(lib().kf_plan_features(p, None, 0, ctypes.byref(nk)))
+    out = np.zeros((nk.value, FEATURE_DIM), dtype=np.float32)
+    _chk(lib().kf_plan_features(p, out.ctypes.data_as(_P(_f32)), nk.value, ctypes.byref(nk)))
+    return out
+
+
+# ---- learned cost model ----------------------------------------------------------------
+def kf_mlp_create(in_dim: int, hidden: int, layers: int):
+    h = _vp()
+    _chk(lib().kf_mlp_create(in_dim, hidden, layers, ctypes.byref(h)))
+    return h
+
+
+def kf_mlp_destroy(m) -> None:
+    lib().kf_mlp_destroy(m)
+
+
+def kf_mlp_param_count(m) -> int:
+    n = _i64()
+    _chk(lib().kf_mlp_param_count(m, ctypes.byref(n)))
+    return n.value
+
+
+def kf_mlp_layout(m, layer: int):
+    a, b, r, c = _i64(), _i64(), _i64(), _i64()
+    _chk(lib().kf_mlp_layout(m, layer, ctypes.byref(a), ctypes.byref(b), ctypes.byref(r), ctypes.byref(c)))
+    return a.value, b.value, r.value, c.value
+
+
+def kf_mlp_init_params(m, seed: int):
+    import numpy as np
+    out = np.zeros(kf_mlp_param_count(m), dtype=np.float32)
+    _chk(lib().kf_mlp_init_params(m, seed, out.ctypes.data_as(_P(_f32))))
+    return out
+
+
+def kf_mlp_workspace_bytes(m, batch: int) -> int:
+    n = _sz()
+    _chk(lib().kf_mlp_workspace_bytes(m, batch, ctypes.byref(n)))
+    return n.value
+
+
+def kf_mlp_forward(m, params: int, X: int, n: int, pred: int, ws: int, ws_bytes: int, stream: int = 0) -> None:
+    _chk(lib().kf_mlp_forward(m, _vp(params), _vp(X), n, _vp(pred), _vp(ws), ws_bytes, _vp(stream)))
+
+
+def kf_mlp_loss_grad(m, params: int, X: int, y: int, n: int, grads: int, loss: int, ws: int, ws_bytes: int,
+                     stream: int = 0) -> None:
+    _chk(lib().kf_mlp_loss_grad(m, _vp(params), _vp(X), _vp(y), n, _vp(grads), _vp(loss), _vp(ws), ws_bytes,
+                                _vp(stream)))
+
+
+def kf_mlp_adam(m, params: int, grads: int, mstate: int, vstate: int, step: int, lr: float, beta1: float = 0.9,
+                beta2: float = 0.999, eps: float = 1e-8, stream: int = 0) -> None:
+    _chk(lib().kf_mlp_adam(m, _vp(params), _vp(grads), _vp(mstate), _vp(vstate), step, lr, beta1, beta2, eps,
+                           _vp(stream)))
