@@ -106,6 +106,11 @@ kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value 
 kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* d0,
                         int64_t* d1, int64_t* d2);
 kf_status kf_script_num_calls(const kf_script* s, int32_t* n);
+/* Call i of the script: op (0 scal, 1 axpy, 2 dot, 3 gemv, 4 gemtv, 5 ger),
+ * scalar operands alpha and beta, operands in[0..2] as documented for the
+ * recorders (KF_NONE where absent) and the output value. */
+kf_status kf_script_call(const kf_script* s, int32_t i, int32_t* op, kf_value* alpha,
+                         kf_value* beta, kf_value* in3, kf_value* out);
 
 /* ---- compilation (Section 4.2: fusions, implementations, combinations) -- */
 enum {
@@ -136,6 +141,11 @@ typedef struct kf_compile_opts {
      * workgroups (grid-stride beyond). */
     int32_t mat_k, mat_waves, mat_group, mat_rows;
     int32_t vec_unroll, vec_threads, vec_grid;
+    /* BLAS-2 schedule: 0 = column strips x row blocks (mat_k used), 1 = row-
+     * resident (a workgroup owns whole rows, mat_waves split the columns,
+     * cols <= 32768). Kernels in which a gemv result feeds a gemtv of the same
+     * kernel always use the row-resident schedule. */
+    int32_t mat_sched;
     /* KF_MODE_PARTITION: partition[i] = kernel id of call i (calls numbered in
      * recording order), ids 0..K-1. */
     const int32_t* partition;
@@ -270,7 +280,8 @@ kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols,
  * sum of its transfer routines (every matrix and vector it moves through HBM)
  * and t_c the sum of its compute routines (one per call), plus one FINISH per
  * finishing launch; summed over kernels. Entries are matched on class and
- * environment; KF_ERR_UNSUPPORTED if a needed entry is missing. */
+ * environment (row-resident kernels use the table's first BLAS-2
+ * environment); KF_ERR_UNSUPPORTED if a needed entry is missing. */
 kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n,
                               float* us);
 

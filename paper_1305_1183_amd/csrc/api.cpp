@@ -26,10 +26,43 @@ struct Registry {
     std::map<std::string, hipFunction_t> funcs;  // launch name -> loaded function
     std::set<std::string> compiled;               // kernel names compiled in this process
     std::vector<hipModule_t> modules;
+    std::map<std::string, hipModule_t> by_ident;  // disk-cache file identity -> module
 };
 static Registry& registry() {
     static Registry* r = new Registry();  // never destroyed: modules outlive static dtors
     return *r;
+}
+
+// Make the launches of kc available (registry lock held): reuse loaded
+// functions, else a module already loaded from the same cache file, else
+// compile or read the code object and load it.
+static kf_status ensure_loaded_locked(Registry& reg, const KernelCode& kc) {
+    bool have = true;
+    for (const Launch& l : kc.launches)
+        if (!reg.funcs.count(l.name)) have = false;
+    if (have) return KF_OK;
+    hipModule_t mod = nullptr;
+    const std::string ident = jit_cache_ident(kc);
+    auto it = ident.empty() ? reg.by_ident.end() : reg.by_ident.find(ident);
+    if (it != reg.by_ident.end()) {
+        mod = it->second;
+    } else {
+        std::string co, log;
+        if (!jit_compile_one(kc, &co, &log)) return set_error(KF_ERR_COMPILE, log);
+        reg.compiled.insert(kc.name);
+        hipError_t e = hipModuleLoadData(&mod, co.data());
+        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
+        reg.modules.push_back(mod);
+        const std::string id2 = ident.empty() ? jit_cache_ident(kc) : ident;
+        if (!id2.empty()) reg.by_ident[id2] = mod;
+    }
+    for (const Launch& l : kc.launches) {
+        hipFunction_t fn = nullptr;
+        hipError_t e = hipModuleGetFunction(&fn, mod, l.name.c_str());
+        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
+        reg.funcs[l.name] = fn;
+    }
+    return KF_OK;
 }
 
 // Compile (through the caches) and load one kernel; fills fns with one
@@ -37,24 +70,8 @@ static Registry& registry() {
 kf_status load_kernel(const KernelCode& kc, std::vector<void*>* fns) {
     Registry& reg = registry();
     std::lock_guard<std::mutex> lock(reg.mu);
-    bool have = true;
-    for (const Launch& l : kc.launches)
-        if (!reg.funcs.count(l.name)) have = false;
-    if (!have) {
-        std::string co, log;
-        if (!jit_compile_one(kc, &co, &log)) return set_error(KF_ERR_COMPILE, log);
-        reg.compiled.insert(kc.name);
-        hipModule_t mod = nullptr;
-        hipError_t e = hipModuleLoadData(&mod, co.data());
-        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
-        reg.modules.push_back(mod);
-        for (const Launch& l : kc.launches) {
-            hipFunction_t fn = nullptr;
-            e = hipModuleGetFunction(&fn, mod, l.name.c_str());
-            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
-            reg.funcs[l.name] = fn;
-        }
-    }
+    kf_status st = ensure_loaded_locked(reg, kc);
+    if (st != KF_OK) return st;
     fns->clear();
     for (const Launch& l : kc.launches) fns->push_back((void*)reg.funcs[l.name]);
     return KF_OK;
@@ -310,6 +327,20 @@ kf_status kf_script_num_calls(const kf_script* s, int32_t* n) {
     return KF_OK;
 }
 
+kf_status kf_script_call(const kf_script* s, int32_t i, int32_t* op, kf_value* alpha, kf_value* beta,
+                         kf_value* in3, kf_value* out) {
+    if (!s) return set_error(KF_ERR_ARG, "null script");
+    if (i < 0 || i >= (int32_t)s->s.calls.size()) return set_error(KF_ERR_ARG, "call index out of range");
+    const Call& c = s->s.calls[i];
+    if (op) *op = (int32_t)c.op;
+    if (alpha) *alpha = c.alpha;
+    if (beta) *beta = c.beta;
+    if (in3)
+        for (int j = 0; j < 3; ++j) in3[j] = c.in[j];
+    if (out) *out = c.out;
+    return KF_OK;
+}
+
 void kf_compile_opts_init(kf_compile_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof *o);
@@ -385,6 +416,7 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     p->mode = o.mode;
     const size_t nv = sc.values.size();
     p->mp.k = o.mat_k; p->mp.waves = o.mat_waves; p->mp.group = o.mat_group; p->mp.rows = o.mat_rows;
+    p->mp.sched = o.mat_sched;
     p->vp.unroll = o.vec_unroll; p->vp.threads = o.vec_threads; p->vp.grid = o.vec_grid;
     p->bind.assign(nv, nullptr);
     p->consts.assign(nv, 0.f);
@@ -399,6 +431,8 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     mp.waves = o.mat_waves;
     mp.group = o.mat_group;
     mp.rows = o.mat_rows;
+    mp.sched = o.mat_sched;
+    if (mp.sched < 0 || mp.sched > 1) return set_error(KF_ERR_ARG, "mat_sched must be 0 or 1");
     VecParams vp;
     vp.unroll = o.vec_unroll;
     vp.threads = o.vec_threads;
@@ -414,7 +448,13 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     for (auto& calls : order) {
         PlanKernel pk;
         Space sp = call_space(sc, calls[0]);
-        if (sp.mat) {
+        if (sp.mat && (mp.sched == 1 || needs_rowres(sc, calls))) {
+            if (sp.b > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
+            if (mp.sched == 1 && mp.rows && mp.group && mp.rows % mp.group)
+                return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_group");
+            if (mp.sched == 1 && mp.waves && (int64_t)mp.waves * 256 * 8 < sp.b)
+                return set_error(KF_ERR_ARG, "row-resident schedule: mat_waves too small for the row length");
+        } else if (sp.mat) {
             MatParams q = default_mat_params(sp.a, sp.b, mp);
             if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_waves * mat_group");
         }
@@ -452,22 +492,15 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     const bool load = !(o.flags & KF_COMPILE_NO_LOAD);
     for (auto& k : p->ks) {
         const std::string& nm = k.code.name;
-        bool have = load ? reg.funcs.count(nm) > 0 : (reg.compiled.count(nm) > 0 || reg.funcs.count(nm) > 0);
-        if (have) continue;
-        std::string co, log;
-        if (!jit_compile_one(k.code, &co, &log)) return set_error(KF_ERR_COMPILE, log);
-        reg.compiled.insert(nm);
-        if (!load) continue;
-        hipModule_t mod = nullptr;
-        hipError_t e = hipModuleLoadData(&mod, co.data());
-        if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleLoadData: ") + hipGetErrorString(e));
-        reg.modules.push_back(mod);
-        for (const Launch& l : k.code.launches) {
-            hipFunction_t fn = nullptr;
-            e = hipModuleGetFunction(&fn, mod, l.name.c_str());
-            if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("hipModuleGetFunction: ") + hipGetErrorString(e));
-            reg.funcs[l.name] = fn;
+        if (!load) {
+            if (reg.compiled.count(nm) || reg.funcs.count(k.code.launches[0].name)) continue;
+            std::string co, log;
+            if (!jit_compile_one(k.code, &co, &log)) return set_error(KF_ERR_COMPILE, log);
+            reg.compiled.insert(nm);
+            continue;
         }
+        kf_status st = ensure_loaded_locked(reg, k.code);
+        if (st != KF_OK) return st;
     }
     if (load)
         for (auto& k : p->ks)
@@ -743,6 +776,7 @@ kf_status kf_jit_release(void) {
     reg.modules.clear();
     reg.funcs.clear();
     reg.compiled.clear();
+    reg.by_ident.clear();
     return KF_OK;
 }
 

@@ -184,7 +184,13 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     for (int v : mat_in) sig.push_back(F("const float* __restrict__ M%d", v));
     for (int v : mat_out) sig.push_back(F("float* __restrict__ O%d", v));
     for (int v : vec_in) sig.push_back(F("const float* __restrict__ V%d", v));
-    for (int v : vec_out) sig.push_back(F("float* __restrict__ Y%d", v));
+    // outputs the main pass writes itself (the rest are written by the finishing launch)
+    std::vector<int> main_out;
+    for (int v : vec_out) {
+        Op op = s.calls[s.values[v].producer].op;
+        if (!((op == Op::Gemv && row_part) || (op == Op::Gemtv && col_part))) main_out.push_back(v);
+    }
+    for (int v : main_out) sig.push_back(F("float* __restrict__ Y%d", v));
     std::vector<KArg> kc_scalar_args;
     {
         for (int c : calls) {
@@ -201,7 +207,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     for (int v : mat_in) mainl.args.push_back({ArgKind::MatIn, v});
     for (int v : mat_out) mainl.args.push_back({ArgKind::MatOut, v});
     for (int v : vec_in) mainl.args.push_back({ArgKind::VecIn, v});
-    for (int v : vec_out) mainl.args.push_back({ArgKind::VecOut, v});
+    for (int v : main_out) mainl.args.push_back({ArgKind::VecOut, v});
     for (auto& a : kc_scalar_args) mainl.args.push_back(a);
     mainl.args.push_back({ArgKind::Workspace, -1});
     sig.push_back("float* __restrict__ ws");
@@ -724,6 +730,338 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
     return kc;
 }
 
+// ============================================================================
+// BLAS-2 kernels, row-resident schedule
+// ============================================================================
+// One workgroup owns R whole rows; its W waves split the columns (each wave a
+// segment of CW = 256 kp columns, kp float4 per lane). A row dot is finished
+// inside the workgroup -- a transposing cross-lane reduction per wave, then the
+// W wave partials added in wave order after one barrier per group of G rows --
+// so its result can feed, in the same pass over the row held in registers,
+// the column accumulation of a gemtv: A^T (A x) reads A once. This is the row
+// reuse the paper reports as impossible without a global barrier (Section
+// 5.2); here the barrier is local because the row never leaves the workgroup.
+bool needs_rowres(const Script& s, const std::vector<int>& calls) {
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        if (k.op != Op::Gemtv) continue;
+        int p = s.values[k.in[1]].producer;
+        if (p >= 0 && std::find(calls.begin(), calls.end(), p) != calls.end()) return true;
+    }
+    return false;
+}
+
+static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
+                                 const std::vector<int>& part, const MatParams& p0) {
+    KernelCode kc;
+    kc.mat = true;
+    kc.calls = calls;
+    const int kid = part[calls[0]];
+    const Space sp = call_space(s, calls[0]);
+    const long M = (long)sp.a, N = (long)sp.b;
+    // defaults: enough waves to cover the row 256 columns each (at most 16), and
+    // G rows per group so that a group's loads fit the register budget
+    const int W = p0.waves > 0 ? p0.waves : (int)std::min<long>(16, std::max<long>(1, (N + 255) / 256));
+    const int KP = (int)((N + 256L * W - 1) / (256L * W));
+    const int G = p0.group > 0 ? p0.group : std::max(1, std::min(4, 16 / KP));
+    int LG = 0;
+    while ((1 << LG) < G) ++LG;
+    const long CW = 256L * KP;
+    const int NT = 64 * W;
+    long R = p0.rows;
+    if (R <= 0) {
+        R = (M + 255) / 256;
+        R = (R + G - 1) / G * G;
+        if (R < G) R = G;
+    }
+    const long NB = (M + R - 1) / R;
+    const long NP = (N + 3) / 4 * 4;
+    const bool edge_cols = (long)W * CW > N;
+
+    std::vector<int> mat_in, mat_out, colv, rowv, vec_in, vec_out, gemv_calls, gemtv_calls, scalars;
+    auto push_u = [](std::vector<int>& v, int x) {
+        if (std::find(v.begin(), v.end(), x) == v.end()) v.push_back(x);
+    };
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        if (!produced_in(s, part, kid, k.in[0])) push_u(mat_in, k.in[0]);
+        if (k.op == Op::Ger) {
+            push_u(rowv, k.in[1]);
+            push_u(colv, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(mat_out, k.out);
+        } else if (k.op == Op::Gemv) {
+            push_u(colv, k.in[1]);
+            gemv_calls.push_back(c);
+            if (k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(rowv, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
+        } else {
+            if (!produced_in(s, part, kid, k.in[1])) push_u(rowv, k.in[1]);
+            gemtv_calls.push_back(c);
+            if (k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(vec_in, k.in[2]);
+            if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
+        }
+    }
+    for (int v : colv) push_u(vec_in, v);
+    for (int v : rowv) push_u(vec_in, v);
+    const bool col_part = !gemtv_calls.empty() && NB > 1;
+    std::map<int, size_t> ws_off;
+    size_t wsz = 0;
+    if (col_part)
+        for (int c : gemtv_calls) { ws_off[c] = wsz; wsz += (size_t)NB * NP; }
+    kc.ws_floats = wsz;
+
+    std::vector<int> main_out;
+    for (int v : vec_out) {
+        Op op = s.calls[s.values[v].producer].op;
+        if (!(op == Op::Gemtv && col_part)) main_out.push_back(v);
+    }
+    std::vector<std::string> sig;
+    Launch mainl;
+    for (int v : mat_in) { mainl.args.push_back({ArgKind::MatIn, v}); sig.push_back(F("const float* __restrict__ M%d", v)); }
+    for (int v : mat_out) { mainl.args.push_back({ArgKind::MatOut, v}); sig.push_back(F("float* __restrict__ O%d", v)); }
+    for (int v : vec_in) { mainl.args.push_back({ArgKind::VecIn, v}); sig.push_back(F("const float* __restrict__ V%d", v)); }
+    for (int v : main_out) { mainl.args.push_back({ArgKind::VecOut, v}); sig.push_back(F("float* __restrict__ Y%d", v)); }
+    std::vector<KArg> sargs;
+    for (int c : calls) {
+        add_scalar_args(s, s.calls[c].alpha, &sargs, &scalars);
+        if (s.calls[c].in[2] >= 0 && s.calls[c].op != Op::Ger) add_scalar_args(s, s.calls[c].beta, &sargs, &scalars);
+    }
+    for (auto& a : sargs) {
+        mainl.args.push_back(a);
+        sig.push_back(a.kind == ArgKind::ConstScalar ? F("float P%d", a.value) : F("const float* __restrict__ P%d", a.value));
+    }
+    mainl.args.push_back({ArgKind::Workspace, -1});
+    sig.push_back("float* __restrict__ ws");
+
+    Emitter e;
+    e.l(F("constexpr long M = %ldL, N = %ldL, NB = %ldL, NP = %ldL, CW = %ldL, R = %ldL;", M, N, NB, NP, CW, R));
+    e.l(F("constexpr int KP = %d, W = %d, G = %d, LG = %d, NT = %d;", KP, W, G, LG, NT));
+    for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
+    e.l("const long rb = blockIdx.x, r0 = rb * R, r1 = (r0 + R < M) ? r0 + R : M;");
+    e.l("(void)ws;");
+    for (int v : scalars)
+        e.l(s.values[v].kind == VK::Const ? F("const float %s = P%d;", scal_name(v).c_str(), v)
+                                          : F("const float %s = *P%d;", scal_name(v).c_str(), v));
+    e.l("long col[KP];");
+    e.l("for (int j = 0; j < KP; ++j) col[j] = (long)wave * CW + (long)(j * 64 + lane) * 4;");
+    for (int v : colv) {
+        e.l(F("kf_f4 cv%d[KP];", v));
+        e.l(F("for (int j = 0; j < KP; ++j) cv%d[j] = kf_ld4_tail(V%d, col[j], N);", v, v));
+    }
+    for (int v : rowv) {
+        e.l(F("__shared__ float rv%d[R];", v));
+        e.l(F("for (long i = tid; i < R; i += NT) rv%d[i] = (r0 + i < M) ? V%d[r0 + i] : 0.f;", v, v));
+    }
+    const int ngv = (int)gemv_calls.size();
+    if (ngv) e.l(F("__shared__ float kf_part[2][%d][G][W];", ngv));
+    for (int c : gemtv_calls) {
+        e.l(F("kf_f4 acc%d[KP];", c));
+        e.l(F("for (int j = 0; j < KP; ++j) acc%d[j] = kf_zero4();", c));
+    }
+    e.l("__syncthreads();");
+    e.l("int slot = 0;");
+    auto mexpr = [&](int v) { return produced_in(s, part, kid, v) ? F("m%d[gi]", v) : F("L%d[gi]", v); };
+    auto emit_group = [&](bool edge) {
+        for (int v : mat_in) e.l(F("kf_f4 L%d[G][KP];", v));
+        e.l("for (int gi = 0; gi < G; ++gi) {");
+        e.ind++;
+        e.l("const long row = g0 + gi;");
+        for (int v : mat_in) {
+            if (!edge) e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = kf_ld4_nt(M%d + row * LD%d + col[j]);", v, v, v));
+            else e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = (row < r1) ? kf_ldm_edge(M%d + row * LD%d, col[j], N) : kf_zero4();", v, v, v));
+        }
+        e.ind--;
+        e.l("}");
+        for (int c : gemv_calls) e.l(F("float rp%d[G];", c));
+        for (int c : calls)
+            if (s.calls[c].op == Op::Ger) e.l(F("kf_f4 m%d[G][KP];", s.calls[c].out));
+        // maps and row dots
+        e.l("for (int gi = 0; gi < G; ++gi) {");
+        e.ind++;
+        e.l("const long row = g0 + gi; const int rl = (int)(row - r0); (void)rl;");
+        for (int c : calls) {
+            const Call& k = s.calls[c];
+            std::string Min = mexpr(k.in[0]);
+            if (k.op == Op::Ger) {
+                e.l(F("const float cu%d = %s * rv%d[rl];", c, scal_name(k.alpha).c_str(), k.in[1]));
+                e.l(F("for (int j = 0; j < KP; ++j) m%d[gi][j] = kf_fma4s(cu%d, cv%d[j], %s[j]);", k.out, c, k.in[2], Min.c_str()));
+                if (must_store(s, part, kid, k.out)) {
+                    if (!edge) e.l(F("for (int j = 0; j < KP; ++j) kf_st4_nt(O%d + row * LD%d + col[j], m%d[gi][j]);", k.out, k.out, k.out));
+                    else e.l(F("if (row < r1) for (int j = 0; j < KP; ++j) kf_stm_edge(O%d + row * LD%d, col[j], N, m%d[gi][j]);", k.out, k.out, k.out));
+                }
+            } else if (k.op == Op::Gemv) {
+                e.l(F("float t%d = 0.f;", c));
+                e.l(F("for (int j = 0; j < KP; ++j) t%d = kf_dot4(%s[j], cv%d[j], t%d);", c, Min.c_str(), k.in[1], c));
+                e.l(F("rp%d[gi] = t%d;", c, c));
+            }
+        }
+        e.ind--;
+        e.l("}");
+        // finish the row dots inside the workgroup
+        for (int i = 0; i < ngv; ++i) {
+            int c = gemv_calls[i];
+            e.l(F("{ const float sw = kf_rows_reduce<LG>(rp%d); if ((lane & ((64 >> LG) - 1)) == 0) kf_part[slot][%d][lane >> (6 - LG)][wave] = sw; }", c, i));
+        }
+        if (ngv) e.l("__syncthreads();");
+        // per row: gemv epilogues, gemtv accumulation (script order)
+        e.l("for (int gi = 0; gi < G; ++gi) {");
+        e.ind++;
+        e.l("const long row = g0 + gi; const int rl = (int)(row - r0); (void)rl;");
+        for (int i = 0; i < ngv; ++i) {
+            int c = gemv_calls[i];
+            e.l(F("float sum%d = 0.f;", c));
+            e.l(F("for (int w = 0; w < W; ++w) sum%d += kf_part[slot][%d][gi][w];", c, i));
+        }
+        for (int c : calls) {
+            const Call& k = s.calls[c];
+            std::string Min = mexpr(k.in[0]);
+            if (k.op == Op::Gemv) {
+                std::string val = F("%s * sum%d", scal_name(k.alpha).c_str(), c);
+                if (k.in[2] >= 0) {
+                    std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                         : F("rv%d[rl]", k.in[2]);
+                    val = F("__builtin_fmaf(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+                }
+                e.l(F("const float f%d = %s;", c, val.c_str()));
+                if (must_store(s, part, kid, k.out))
+                    e.l(edge ? F("if (tid == 0 && row < r1) Y%d[row] = f%d;", k.out, c) : F("if (tid == 0) Y%d[row] = f%d;", k.out, c));
+                else e.l(F("(void)f%d;", c));
+            } else if (k.op == Op::Gemtv) {
+                std::string xr = produced_in(s, part, kid, k.in[1]) ? F("f%d", s.values[k.in[1]].producer)
+                                                                     : F("rv%d[rl]", k.in[1]);
+                if (edge && produced_in(s, part, kid, k.in[1])) xr = "((row < r1) ? " + xr + " : 0.f)";
+                e.l(F("for (int j = 0; j < KP; ++j) acc%d[j] = kf_fma4s(%s, %s[j], acc%d[j]);", c, xr.c_str(), Min.c_str(), c));
+            }
+        }
+        e.ind--;
+        e.l("}");
+        e.l("slot ^= 1;");
+    };
+    e.l("for (long g0 = r0; g0 < r1; g0 += G) {");
+    e.ind++;
+    e.l(edge_cols ? "if (false) {" : "if (g0 + G <= r1) {");
+    e.ind++;
+    emit_group(false);
+    e.ind--;
+    e.l("} else {");
+    e.ind++;
+    emit_group(true);
+    e.ind--;
+    e.l("}");
+    e.ind--;
+    e.l("}");
+    // column results: each wave owns its columns (all gemtv calls in one loop so
+    // that a chained y0 is at hand)
+    if (!gemtv_calls.empty()) {
+        e.l("for (int j = 0; j < KP; ++j) {");
+        e.ind++;
+        e.l("const long cc = col[j];");
+        e.l("if (cc < N) {");
+        e.ind++;
+        for (int c : gemtv_calls) {
+            const Call& k = s.calls[c];
+            if (!col_part) {
+                std::string val = F("kf_mul4s(%s, acc%d[j])", scal_name(k.alpha).c_str(), c);
+                if (k.in[2] >= 0) {
+                    std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("g%d", s.values[k.in[2]].producer)
+                                                                         : F("kf_ld4_tail(V%d, cc, N)", k.in[2]);
+                    val = F("kf_fma4s(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+                }
+                e.l(F("const kf_f4 g%d = %s;", c, val.c_str()));
+                if (must_store(s, part, kid, k.out)) e.l(F("kf_st4_tail(Y%d, cc, N, g%d);", k.out, c));
+                else e.l(F("(void)g%d;", c));
+            } else {
+                e.l(F("kf_st4(ws + %zuL + rb * NP + cc, acc%d[j]);", ws_off[c], c));
+            }
+        }
+        e.ind--;
+        e.l("}");
+        e.ind--;
+        e.l("}");
+    }
+
+    // finishing launch (column partials), as in the strip schedule
+    Emitter f;
+    Launch finl;
+    std::vector<std::string> fsig;
+    if (col_part) {
+        std::vector<int> fin_in, fin_out;
+        for (int c : gemtv_calls) {
+            const Call& k = s.calls[c];
+            if (k.in[2] >= 0 && !produced_in(s, part, kid, k.in[2])) push_u(fin_in, k.in[2]);
+            if (must_store(s, part, kid, k.out)) fin_out.push_back(k.out);
+        }
+        for (int v : fin_in) { finl.args.push_back({ArgKind::VecIn, v}); fsig.push_back(F("const float* __restrict__ V%d", v)); }
+        for (int v : fin_out) { finl.args.push_back({ArgKind::VecOut, v}); fsig.push_back(F("float* __restrict__ Y%d", v)); }
+        for (auto& a : sargs) {
+            finl.args.push_back(a);
+            fsig.push_back(a.kind == ArgKind::ConstScalar ? F("float P%d", a.value) : F("const float* __restrict__ P%d", a.value));
+        }
+        finl.args.push_back({ArgKind::Workspace, -1});
+        fsig.push_back("const float* __restrict__ ws");
+        f.l(F("constexpr long N = %ldL, NB = %ldL, NP = %ldL;", N, NB, NP));
+        for (int v : scalars)
+            f.l(s.values[v].kind == VK::Const ? F("const float %s = P%d;", scal_name(v).c_str(), v)
+                                              : F("const float %s = *P%d;", scal_name(v).c_str(), v));
+        f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
+        f.l("const long cc = 4L * ((long)blockIdx.x * 64 + lane);");
+        f.l(F("__shared__ kf_f4 kf_fr[%d][4][64];", (int)gemtv_calls.size()));
+        for (size_t i = 0; i < gemtv_calls.size(); ++i) {
+            int c = gemtv_calls[i];
+            f.l(F("kf_f4 part%d = kf_zero4();", c));
+            f.l(F("if (cc < N) for (long b = wave; b < NB; b += 4) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+            f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
+        }
+        f.l("__syncthreads();");
+        f.l("if (wave == 0 && cc < N) {");
+        f.ind++;
+        for (size_t i = 0; i < gemtv_calls.size(); ++i) {
+            int c = gemtv_calls[i];
+            const Call& k = s.calls[c];
+            f.l(F("const kf_f4 sum%d = ((kf_fr[%zu][0][lane] + kf_fr[%zu][1][lane]) + kf_fr[%zu][2][lane]) + kf_fr[%zu][3][lane];", c, i, i, i, i));
+            std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
+            if (k.in[2] >= 0) {
+                std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
+                                                                     : F("kf_ld4_tail(V%d, cc, N)", k.in[2]);
+                val = F("kf_fma4s(%s, %s, %s)", scal_name(k.beta).c_str(), y0.c_str(), val.c_str());
+            }
+            f.l(F("const kf_f4 f%d = %s;", c, val.c_str()));
+            if (must_store(s, part, kid, k.out)) f.l(F("kf_st4_tail(Y%d, cc, N, f%d);", k.out, c));
+            else f.l(F("(void)f%d;", c));
+        }
+        f.ind--;
+        f.l("}");
+        finl.grid = (int)((NP / 4 + 63) / 64);
+        finl.block = 256;
+    }
+    std::string sigs, fsigs;
+    for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
+    for (size_t i = 0; i < fsig.size(); ++i) fsigs += (i ? ",\n    " : "    ") + fsig[i];
+    std::string key = F("rowres W%d G%d R%ld M%ld N%ld|", W, G, R, M, N) + sigs + e.o.str() + fsigs + f.o.str();
+    kc.name = F("kf_row_%016llx", (unsigned long long)fnv1a(key));
+    std::ostringstream head;
+    head << "extern \"C\" __global__ void __launch_bounds__(" << NT << ") " << kc.name << "(\n" << sigs << ") {\n"
+         << e.o.str() << "}\n";
+    mainl.name = kc.name;
+    mainl.grid = (int)NB;
+    mainl.block = NT;
+    kc.launches.push_back(mainl);
+    if (col_part) {
+        finl.name = kc.name + "_fin";
+        head << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n" << fsigs << ") {\n"
+             << f.o.str() << "}\n";
+        kc.launches.push_back(finl);
+    }
+    kc.source = head.str();
+    kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + (size_t)ngv * 2 * G * W * 4;
+    kc.params_json = F("{\"schedule\": \"row-resident\", \"waves\": %d, \"group\": %d, \"rows\": %ld, \"kp\": %d, \"row_blocks\": %ld}",
+                       W, G, R, KP, NB);
+    kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
+    return kc;
+}
+
 // Operand bytes one launch moves through HBM (workspace partials excluded).
 static void launch_bytes(const Script& s, Launch* l) {
     l->bytes_read = l->bytes_written = 0;
@@ -745,8 +1083,15 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
                            const std::vector<int>& part, const MatParams& mp,
                            const VecParams& vp) {
     Space sp = call_space(s, calls[0]);
-    KernelCode kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp))
-                           : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+    KernelCode kc;
+    if (sp.mat && (mp.sched == 1 || needs_rowres(s, calls))) {
+        MatParams q = mp;
+        if (q.sched != 1) q.waves = q.group = q.rows = 0;   // strip-schedule parameters do not carry over
+        kc = gen_mat_rowres(s, calls, part, q);
+    } else {
+        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp))
+                    : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+    }
     for (Launch& l : kc.launches) launch_bytes(s, &l);
     return kc;
 }

@@ -14,6 +14,7 @@
 #include <fstream>
 #include <mutex>
 #include <sstream>
+#include <sys/stat.h>
 #include <unistd.h>
 
 #include "kf_internal.h"
@@ -102,6 +103,14 @@ static bool rtc_compile(const std::string& text, std::string* code_object, std::
     hiprtcDestroyProgram(&prog);
     *log = lg;
     return true;
+}
+
+std::string jit_cache_ident(const KernelCode& k) {
+    const std::string path = cache_path(unit_text(k));
+    if (path.empty()) return "";
+    struct stat st;
+    if (::stat(path.c_str(), &st) != 0) return "";
+    return "ino:" + std::to_string((unsigned long long)st.st_dev) + ":" + std::to_string((unsigned long long)st.st_ino);
 }
 
 bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string* log) {

@@ -72,7 +72,7 @@ std::vector<int> unfused_partition(const Script& s);
 std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vector<int>& part);
 
 // ---- implementation parameters ---------------------------------------------
-struct MatParams { int k = 0, waves = 0, group = 0, rows = 0; };
+struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0; };  // sched 1 = row-resident
 struct VecParams { int unroll = 0, threads = 0, grid = 0; };
 MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req);
 VecParams default_vec_params(int64_t n, const VecParams& req);
@@ -106,6 +106,9 @@ struct KernelCode {
 KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
                            const std::vector<int>& part, const MatParams& mp,
                            const VecParams& vp);
+// Does the call set need the row-resident schedule (a gemv result feeding a
+// gemtv of the same kernel)?
+bool needs_rowres(const Script& s, const std::vector<int>& calls);
 // Single-routine probe kernel (one launch; args: src, dst, sink).
 KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatParams& mp,
                           const VecParams& vp);
@@ -122,6 +125,9 @@ const std::string& blocks_source();
 // code object, through the memory/disk cache. Returns false and fills log on
 // failure.
 bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string* log);
+// Identity of the disk-cache file holding kernel k ("" if not cached): kernels
+// compiled together share one file, which is then loaded once per process.
+std::string jit_cache_ident(const KernelCode& k);
 
 // ---- errors ---------------------------------------------------------------------
 kf_status set_error(kf_status st, const std::string& msg);

@@ -100,6 +100,11 @@ std::string block_illegal_reason(const Script& s, const std::vector<int>& calls)
             const Call& kd = s.calls[d];
             bool ok = (k.op == Op::Gemv || k.op == Op::Gemtv) && kd.op == k.op &&
                       used_only_as_y0(kd, k.out);
+            // R3'': a row dot may feed the row-indexed x of a gemtv when the kernel
+            // keeps whole rows in one workgroup (row-resident schedule, cols <= 32768)
+            if (!ok && k.op == Op::Gemv && kd.op == Op::Gemtv && kd.in[1] == k.out && kd.in[0] != k.out &&
+                kd.in[2] != k.out && kd.alpha != k.out && kd.beta != k.out && call_space(s, c).b <= 32768)
+                ok = true;
             if (!ok)
                 return std::string("R3: result of ") + op_name(k.op) +
                        " consumed inside the kernel that reduces it";

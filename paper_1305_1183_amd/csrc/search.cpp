@@ -105,7 +105,21 @@ kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, i
         const bool mat = sp.mat;
         MatParams mp = mat ? default_mat_params(sp.a, sp.b, p->mp) : MatParams();
         VecParams vp = mat ? VecParams() : default_vec_params(sp.a, p->vp);
-        auto get = [&](int r) -> const kf_routine_entry* { return find(table, n, mat, mp, vp, r); };
+        if (!mat && p->vp.grid > 0) vp.grid = p->vp.grid;  // the environment is the requested point (grid is capped for short vectors)
+        const bool rowres = mat && (p->mp.sched == 1 || needs_rowres(p->s, kc.calls));
+        const kf_routine_entry* first_mat = nullptr;
+        for (int i = 0; i < n && rowres && !first_mat; ++i)
+            if (table[i].cls == 1) first_mat = &table[i];
+        auto get = [&](int r) -> const kf_routine_entry* {
+            if (rowres && first_mat) {
+                // row-resident kernels have no probe geometry of their own: they are
+                // priced with the routines of the table's first BLAS-2 environment
+                MatParams e;
+                e.k = first_mat->env[0]; e.waves = first_mat->env[1]; e.group = first_mat->env[2]; e.rows = first_mat->env[3];
+                return find(table, n, true, e, vp, r);
+            }
+            return find(table, n, mat, mp, vp, r);
+        };
         double tt = 0, tc = 0;
         // transfers: every operand the kernel's launches move through HBM
         for (const Launch& l : kc.launches)

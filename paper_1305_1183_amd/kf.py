@@ -57,10 +57,12 @@ class kf_compile_opts(ctypes.Structure):
 kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("mat_k", _i32), ("mat_waves", _i32), ("mat_group", _i32), ("mat_rows", _i32),
                             ("vec_unroll", _i32), ("vec_threads", _i32), ("vec_grid", _i32),
+                            ("mat_sched", _i32),
                             ("partition", _P(_i32)), ("partition_len", _i32),
                             ("table", _P(kf_routine_entry)), ("table_len", _i32), ("max_partitions", _i32),
                             ("grid", _P(kf_compile_opts)), ("grid_len", _i32)]
-PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid"]
+PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
+                "mat_sched"]
 
 
 ROUTINES = ["LOAD_MAT", "STORE_MAT", "COMPUTE_GEMV", "COMPUTE_GEMTV", "COMPUTE_GER", "LOAD_VEC",
@@ -86,6 +88,7 @@ _SIGS = {
     "kf_ger": ([_vp, _i32, _i32, _i32, _i32, _P(_i32)], _i32),
     "kf_value_info": ([_vp, _i32, _P(_i32), _P(_i64), _P(_i64), _P(_i64)], _i32),
     "kf_script_num_calls": ([_vp, _P(_i32)], _i32),
+    "kf_script_call": ([_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)], _i32),
     "kf_compile_opts_init": ([_P(kf_compile_opts)], None),
     "kf_compile": ([_vp, _P(kf_compile_opts), _P(_vp)], _i32),
     "kf_plan_destroy": ([_vp], None),
@@ -238,6 +241,16 @@ def kf_script_num_calls(s) -> int:
     n = _i32()
     _chk(lib().kf_script_num_calls(s, ctypes.byref(n)))
     return n.value
+
+
+OP_NAMES = ["scal", "axpy", "dot", "gemv", "gemtv", "ger"]
+
+
+def kf_script_call(s, i: int) -> dict:
+    op, a, b, o = _i32(), _i32(), _i32(), _i32()
+    ins = (_i32 * 3)()
+    _chk(lib().kf_script_call(s, i, ctypes.byref(op), ctypes.byref(a), ctypes.byref(b), ins, ctypes.byref(o)))
+    return {"op": OP_NAMES[op.value], "alpha": a.value, "beta": b.value, "in": list(ins), "out": o.value}
 
 
 # ---- compile / enumerate --------------------------------------------------------

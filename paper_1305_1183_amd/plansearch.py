@@ -1,0 +1,194 @@
+"""Plan-search study on random scripts (command line).
+
+    python -m paper_1305_1183_amd.plansearch table    --out T.json
+    python -m paper_1305_1183_amd.plansearch collect  --seeds 0:50 --out D0.npz
+    python -m paper_1305_1183_amd.plansearch evaluate --data D*.npz --table T.json \
+        --train 0:150 --eval 150:200 --out report.json --model model.npz
+
+`collect` times every sampled candidate plan of each script on the GPU
+(exhaustive search); `evaluate` trains the cost model on the training scripts
+with the library's GPU kernels, then ranks the candidates of the evaluation
+scripts with the additive predictor and with the model, and reports the rank
+of the true best plan, the regret of the chosen plan and the search time
+against exhaustive timing.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import json
+import os
+import shutil
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+
+def _range(s):
+    a, b = s.split(":")
+    return list(range(int(a), int(b)))
+
+
+def cmd_table(a):
+    from . import search as SE
+    entries = SE.measure_routine_table(reps=a.reps)
+    json.dump({"entries": [[c, list(e), r, u] for c, e, r, u in entries],
+               "note": "us per matrix element / vector entry / launch (FINISH); probes on 8192x8192 and 2^24"},
+              open(a.out, "w"), indent=0)
+    print("routine table: %d entries -> %s" % (len(entries), a.out), flush=True)
+
+
+def cmd_collect(a):
+    from . import search as SE
+    d = SE.collect(_range(a.seeds), max_cands=a.max_cands, cache_dir=a.cache, workers=a.workers, reps=a.reps,
+                   log=lambda s: print(s, flush=True),
+                   checkpoint=lambda part: np.savez_compressed(a.out, **part))
+    np.savez_compressed(a.out, **d)
+    print("saved %d candidate timings, %d kernel timings, %d unique kernels -> %s" %
+          (len(d["plan_us"]), len(d["kern_us"]), len(d["uk_seed"]), a.out), flush=True)
+
+
+def cmd_evaluate(a):
+    import torch
+    from . import kf
+    from . import randscript as R
+    from . import search as SE
+    from .costmodel import CostModel
+
+    files = sorted(sum([glob.glob(p) for p in a.data], []))
+    data = SE.merge([dict(np.load(f, allow_pickle=False)) for f in files])
+    train, evals = set(_range(a.train)), set(_range(a.eval))
+    have = set(int(s) for s in data["script_seed"])
+    train, evals = sorted(train & have), sorted(evals & have)
+    X, y = SE.kernel_training_set(data, train)
+    print("training on %d kernel samples from %d scripts (%d plan timings in all)" %
+          (len(y), len(train), len(data["plan_us"])), flush=True)
+    t0 = time.perf_counter()
+    cm = CostModel(seed=a.seed)
+    hist = cm.fit(X, y, epochs=a.epochs, batch=256, lr=a.lr, seed=a.seed, verbose=True)
+    train_s = time.perf_counter() - t0
+    kpred = np.exp(cm.predict_log(data["uk_feat"]))[data["kern_uk"]]
+    c_launch = SE.fit_launch_term(data, train, kpred)
+    if a.model:
+        cm.save(a.model)
+    table = None
+    if a.table:
+        T = json.load(open(a.table))
+        table = kf.routine_table([(c, tuple(e), r, u) for c, e, r, u in T["entries"]])
+    per, summary = [], {}
+    for seed in evals:
+        m = np.where(data["cand_seed"] == seed)[0]
+        true = data["plan_us"][m]
+        idx = data["cand_idx"][m]
+        walls = data["cand_wall"][m]
+        srow = int(np.where(data["script_seed"] == seed)[0][0])
+        rs = R.random_script(seed)
+        cands = kf.Candidates(rs.script, 64, SE.grid_points())
+        # learned ranking: features + model (timed as the search would run it)
+        t1 = time.perf_counter()
+        feats, nl = [], []
+        for i in idx:
+            p = cands.compile(int(i), kf.KF_COMPILE_CODEGEN_ONLY)
+            f = kf.kf_plan_features(p)
+            feats.append(f)
+            nl.append(float(np.sum(f[:, 25])))
+            kf.kf_plan_destroy(p)
+        t_feat = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        learned = cm.predict_plan_us(feats) + c_launch * np.array(nl)
+        t_pred = time.perf_counter() - t1
+        row = {"seed": seed, "script": rs.describe(), "candidates": int(len(m)),
+               "best_us": float(true.min()), "learned": SE.rank_metrics(true, learned)}
+        if table is not None:
+            t1 = time.perf_counter()
+            add_all = cands.predict_additive(table)
+            t_add = time.perf_counter() - t1
+            additive = add_all[idx]
+            row["additive"] = SE.rank_metrics(true, additive)
+        # search time: exhaustive vs learned top-k (compile measured in a fresh cache)
+        exh = float(data["script_codegen_s"][srow] + data["script_compile_s"][srow] + data["script_load_s"][srow]
+                    + walls.sum())
+        row["exhaustive_search_s"] = exh
+        for k in a.topk:
+            order = np.argsort(learned, kind="stable")[:k]
+            tmp = tempfile.mkdtemp(prefix="kfeval")
+            old = os.environ.get("KF_CACHE_DIR")
+            os.environ["KF_CACHE_DIR"] = tmp
+            t1 = time.perf_counter()
+            cands.precompile([int(idx[j]) for j in order])
+            t_comp = time.perf_counter() - t1
+            if old is None:
+                del os.environ["KF_CACHE_DIR"]
+            else:
+                os.environ["KF_CACHE_DIR"] = old
+            shutil.rmtree(tmp, ignore_errors=True)
+            tl = t_feat + t_pred + t_comp + float(walls[order].sum())
+            row["learned_top%d_search_s" % k] = tl
+            row["learned_top%d_regret" % k] = float(true[order].min() / true.min() - 1.0)
+        per.append(row)
+        print(json.dumps(row), flush=True)
+        kf.kf_jit_release()
+
+    def agg(key, sub):
+        v = [r[key][sub] for r in per if key in r]
+        return v
+
+    for meth in ("learned", "additive"):
+        if not per or meth not in per[0]:
+            continue
+        regret = np.array(agg(meth, "regret_top1"))
+        summary[meth] = {
+            "mean_regret_top1": float(regret.mean()), "median_regret_top1": float(np.median(regret)),
+            "frac_within_5pct": float(np.mean(regret <= 0.05)),
+            "mean_first_pct_of_best": float(np.mean(agg(meth, "first_pct_of_best"))),
+            "median_rank_of_best": float(np.median(agg(meth, "rank_of_best"))),
+            "mean_regret_top3": float(np.mean(agg(meth, "regret_top3")))}
+    exh = np.array([r["exhaustive_search_s"] for r in per])
+    for k in a.topk:
+        lt = np.array([r["learned_top%d_search_s" % k] for r in per])
+        rg = np.array([r["learned_top%d_regret" % k] for r in per])
+        summary["learned_top%d" % k] = {"total_search_s": float(lt.sum()), "exhaustive_total_s": float(exh.sum()),
+                                        "search_time_ratio": float(exh.sum() / lt.sum()),
+                                        "mean_regret": float(rg.mean()), "frac_within_5pct": float(np.mean(rg <= 0.05)),
+                                        "plan_time_total_ratio_vs_best": float(
+                                            np.sum([r["best_us"] * (1 + g) for r, g in zip(per, rg)]) /
+                                            np.sum([r["best_us"] for r in per]))}
+    report = {"train_scripts": len(train), "eval_scripts": len(evals), "kernel_samples": int(len(y)),
+              "plan_timings": int(len(data["plan_us"])), "train_seconds": train_s,
+              "final_train_loss": hist[-1], "launch_term_us": c_launch, "summary": summary, "per_script": per}
+    json.dump(report, open(a.out, "w"), indent=1)
+    print(json.dumps(summary, indent=1), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("table")
+    t.add_argument("--out", required=True)
+    t.add_argument("--reps", type=int, default=10)
+    c = sub.add_parser("collect")
+    c.add_argument("--seeds", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--max-cands", type=int, default=512)
+    c.add_argument("--workers", type=int, default=14)
+    c.add_argument("--reps", type=int, default=3)
+    c.add_argument("--cache", default="/tmp/kf_cache")
+    e = sub.add_parser("evaluate")
+    e.add_argument("--data", nargs="+", required=True)
+    e.add_argument("--table", default="")
+    e.add_argument("--train", default="0:150")
+    e.add_argument("--eval", default="150:200")
+    e.add_argument("--out", required=True)
+    e.add_argument("--model", default="")
+    e.add_argument("--epochs", type=int, default=150)
+    e.add_argument("--lr", type=float, default=1e-3)
+    e.add_argument("--seed", type=int, default=0)
+    e.add_argument("--topk", type=lambda s: [int(x) for x in s.split(",")], default=[1, 3])
+    a = ap.parse_args(argv)
+    {"table": cmd_table, "collect": cmd_collect, "evaluate": cmd_evaluate}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -65,17 +65,22 @@ def test_validation_errors():
     assert err(kf.kf_compile, kf.kf_script_create()) == "KF_ERR_STATE"  # no calls
     kf.kf_output(s, q)
     # an illegal explicit partition is refused
-    q2 = S.atax(16, 12)   # keep the Sequence alive: it owns the script
+    q2 = S.gemver(16, 12, 1.5, 0.5)   # keep the Sequence alive: it owns the script
     s2 = q2.script
-    with pytest.raises(kf.KFError) as e:
-        kf.kf_compile(s2, mode="partition", partition=[0, 0], flags=kf.KF_COMPILE_NO_LOAD)
+    with pytest.raises(kf.KFError) as e:   # gemtv result feeding gemv in one kernel
+        kf.kf_compile(s2, mode="partition", partition=[0, 1, 2, 2], flags=kf.KF_COMPILE_NO_LOAD)
     assert e.value.name == "KF_ERR_UNSUPPORTED" and "R3" in str(e.value)
+    with pytest.raises(kf.KFError) as e:   # {ger1, gemtv} without ger2 between them
+        kf.kf_compile(s2, mode="partition", partition=[0, 1, 0, 2], flags=kf.KF_COMPILE_NO_LOAD)
+    assert "R1" in str(e.value)
     with pytest.raises(kf.KFError):
         kf.kf_compile(s2, mode="partition", partition=[0], flags=kf.KF_COMPILE_NO_LOAD)
     with pytest.raises(kf.KFError):
         kf.kf_compile(s2, mode="fused", mat_k=3, flags=kf.KF_COMPILE_NO_LOAD)
     with pytest.raises(kf.KFError):
         kf.kf_compile(s2, mode="fused", mat_waves=4, mat_group=4, mat_rows=24, flags=kf.KF_COMPILE_NO_LOAD)
+    with pytest.raises(kf.KFError):
+        kf.kf_compile(s2, mode="fused", mat_sched=1, mat_group=4, mat_rows=6, flags=kf.KF_COMPILE_NO_LOAD)
 
 
 def test_run_without_gpu_state_errors():
@@ -94,7 +99,7 @@ def test_run_without_gpu_state_errors():
 # ---- legality facts of Section 3.2 and Section 5.1 ------------------------------
 EXPECTED_PLANS = {
     "bicgk": 2,     # fused (Algorithm 3) or two kernels
-    "atax": 1,      # A^T (A x): the global barrier forbids fusion
+    "atax": 2,      # A^T (A x): fused only by the row-resident schedule (R3'')
     "gemver": 4,
     "gesummv": 2,
     "axpydot": 2,
@@ -127,7 +132,7 @@ def test_gemver_partitions_exact():
 
 
 def test_fused_plans():
-    for name, nk in [("bicgk", 1), ("atax", 2), ("gemver", 2), ("gesummv", 1), ("axpydot", 1), ("waxpby", 1)]:
+    for name, nk in [("bicgk", 1), ("atax", 1), ("gemver", 2), ("gesummv", 1), ("axpydot", 1), ("waxpby", 1)]:
         q = build(name)
         p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
         assert kf.kf_plan_num_kernels(p) == nk, name
@@ -142,7 +147,7 @@ N2 = 16384
     ("axpydot", 1073741824 + 4, 1342177280 + 4),   # + the 4-byte scalar r
     ("waxpby", 805306368, 1342177280),
     ("bicgk", 1074003968, 2147745792),
-    ("atax", 2147745792, 2147745792),
+    ("atax", 1073872896, 2147745792),   # fused: one pass over A (row-resident)
     ("gesummv", 2147614720, 2147811328),
     ("gemver", 3221815296, 6443040768),
 ])
@@ -169,7 +174,10 @@ def test_bytes_per_flop_match_paper_tables():
             "GEMVER": S.gemver(n, n, 1.5, 0.5), "GESUMMV": S.gesummv(n, n, 1.5, 0.5),
             "WAXPBY": S.waxpby(n * n, 1.5, 0.5)}
     for key, q in seqs.items():
-        p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+        # the paper's ATAX plan is two kernels (it cannot fuse it); ours also has
+        # a one-pass plan, so the paper's plan is the unfused one here
+        mode = "unfused" if key == "ATAX" else "fused"
+        p = kf.kf_compile(q.script, mode=mode, flags=kf.KF_COMPILE_NO_LOAD)
         r, w = kf.kf_plan_bytes(p)
         ours = (r + w) / flops[key]
         paper = g[key]["gbps"] / g[key]["gflops"]

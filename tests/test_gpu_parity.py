@@ -196,3 +196,29 @@ def test_enumerated_plans_agree():
         outs = prog.run()
         torch.cuda.synchronize()
         SC.check_against_oracle("gemver", m, n, {k: v.cpu().numpy() for k, v in outs.items()}, ref)
+
+
+@pytest.mark.parametrize("params", [dict(mat_sched=1), dict(mat_sched=1, mat_waves=2, mat_group=2, mat_rows=6),
+                                    dict(mat_sched=1, mat_waves=16, mat_group=1, mat_rows=64),
+                                    dict(mat_sched=1, mat_waves=8, mat_group=4, mat_rows=4)])
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_row_resident_schedule(params, mode):
+    """Row-resident kernels (whole rows per workgroup): ATAX in one pass over A,
+    and every other sequence under the same schedule."""
+    for name, (m, n) in [("atax", (777, 1555)), ("bicgk", (777, 1555)), ("gemver", (513, 1027)),
+                         ("gesummv", (300, 2049)), ("atax", (5, 3)), ("atax", (2049, 4097))]:
+        print("case", name, m, n, params, mode, flush=True)
+        arrays, scal = WL.make(name, m, n, seed=18)
+        q, prog, host = SC.run_gpu(name, m, n, arrays, scal, mode=mode, **params)
+        SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))
+
+
+def test_atax_single_pass_reads_a_once():
+    """The fused ATAX plan is one kernel that moves A through HBM once."""
+    m, n = 2048, 2048
+    arrays, scal = WL.make("atax", m, n, seed=19)
+    q, prog, host = SC.run_gpu("atax", m, n, arrays, scal, mode="fused")
+    assert prog.num_kernels == 1
+    r, w = prog.bytes()
+    assert r == m * n * 4 + n * 4 and w == n * 4
+    SC.check_against_oracle("atax", m, n, host, SC.oracle_outputs("atax", arrays, scal, n))
