@@ -68,12 +68,28 @@ const char* kf_version(void);
 kf_status kf_script_create(kf_script** out);
 void kf_script_destroy(kf_script* s);
 
+/* Storage formats of matrices. FP32 is the default. BF16 (upper half of an
+ * IEEE single) and OCP FP8-E4M3 (1 sign, 4 exponent bits with bias 7, 3
+ * mantissa bits, largest finite 448, no infinities) hold a row-scaled matrix:
+ * element (i, j) stands for scale[i] * decode(q_ij), where scale is an FP32
+ * vector of `rows` entries. Quantised matrices are read-only inputs of gemv,
+ * gemtv and ger (whose result is FP32); arithmetic stays FP32 (the scale is
+ * folded into the row dot, into the gemtv multiplier, or applied before the
+ * ger update). Their ld is counted in elements and must make each row a
+ * multiple of 16 bytes. */
+enum { KF_F32 = 0, KF_BF16 = 1, KF_FP8_E4M3 = 2 };
+
 /* Declarations. A vector has n >= 1 FP32 entries; a matrix is rows x cols
  * row-major with leading dimension ld (0 = cols rounded up to a multiple of 4).
  * kf_const is a host FP32 scalar passed to the kernels by value (rebindable
  * with kf_set_const); kf_scalar is an FP32 scalar in device memory. */
 kf_status kf_vector(kf_script* s, int64_t n, kf_value* out);
 kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_value* out);
+/* A quantised matrix (dtype KF_BF16 or KF_FP8_E4M3; KF_F32 is kf_matrix with
+ * scale KF_NONE) with its row-scale vector `scale` (an input vector of rows
+ * entries). ld 0 = cols rounded up to a 16-byte row. */
+kf_status kf_matrix_q(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t dtype,
+                      kf_value scale, kf_value* out);
 kf_status kf_const(kf_script* s, float v, kf_value* out);
 kf_status kf_scalar(kf_script* s, kf_value* out);
 /* Listing 1 `input` and `return`. Declared values must be marked input before
@@ -102,7 +118,7 @@ kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value 
                  kf_value* B);
 
 /* Shape of a value: kind 0 vector (d0 = n), 1 matrix (d0 = rows, d1 = cols,
- * d2 = ld), 2 const scalar, 3 device scalar. */
+ * d2 = ld in elements), 2 const scalar, 3 device scalar. */
 kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* d0,
                         int64_t* d1, int64_t* d2);
 kf_status kf_script_num_calls(const kf_script* s, int32_t* n);

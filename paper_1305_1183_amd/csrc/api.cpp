@@ -139,6 +139,32 @@ kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_val
     return add_value(s, v, out);
 }
 
+kf_status kf_matrix_q(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t dtype, kf_value scale,
+                      kf_value* out) {
+    if (dtype == KF_F32) {
+        if (scale != KF_NONE) return set_error(KF_ERR_ARG, "FP32 matrices take no scale vector");
+        return kf_matrix(s, rows, cols, ld, out);
+    }
+    if (dtype != KF_BF16 && dtype != KF_FP8_E4M3) return set_error(KF_ERR_DTYPE, "unknown matrix storage format");
+    if (rows < 1 || cols < 1) return set_error(KF_ERR_SHAPE, "matrix dimensions must be >= 1");
+    const int64_t per16 = 16 / dtype_size(dtype);
+    if (ld == 0) ld = (cols + per16 - 1) / per16 * per16;
+    if (ld < cols) return set_error(KF_ERR_SHAPE, "ld < cols");
+    if (ld % per16) return set_error(KF_ERR_ALIGN, "ld must make every row a multiple of 16 bytes");
+    if (!valid_value(s, scale)) return set_error(KF_ERR_ARG, "bad scale vector handle");
+    const Value& sv = s->s.values[scale];
+    if (sv.kind != VK::Vec || sv.n != rows) return set_error(KF_ERR_SHAPE, "scale vector must have rows entries");
+    if (!sv.input) return set_error(KF_ERR_STATE, "scale vector is not marked input");
+    Value v;
+    v.kind = VK::Mat;
+    v.rows = rows;
+    v.cols = cols;
+    v.ld = ld;
+    v.dtype = dtype;
+    v.scale = scale;
+    return add_value(s, v, out);
+}
+
 kf_status kf_const(kf_script* s, float c, kf_value* out) {
     Value v;
     v.kind = VK::Const;
@@ -193,6 +219,7 @@ static kf_status record(kf_script* s, const Call& c, const Value& outv, kf_value
         int ops[5] = {k.alpha, k.beta, k.in[0], k.in[1], k.in[2]};
         for (int o : ops)
             if (o >= 0) s->s.values[o].consumers.push_back(ci);
+        if (k.in[0] >= 0 && s->s.values[k.in[0]].scale >= 0) s->s.values[s->s.values[k.in[0]].scale].consumers.push_back(ci);
         *out = k.out;
     });
     return KF_OK;
@@ -384,7 +411,7 @@ static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 static size_t value_bytes(const Value& v) {
     switch (v.kind) {
         case VK::Vec: return (size_t)v.n * 4;
-        case VK::Mat: return (size_t)v.rows * v.ld * 4;
+        case VK::Mat: return (size_t)v.rows * v.ld * (size_t)dtype_size(v.dtype);
         case VK::DevScalar: return 4;
         default: return 0;
     }
@@ -450,12 +477,14 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
         Space sp = call_space(sc, calls[0]);
         if (sp.mat && (mp.sched == 1 || needs_rowres(sc, calls))) {
             if (sp.b > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
+            if (kernel_unit_elems(sc, calls) != 4)
+                return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule reads FP32 matrices only");
             if (mp.sched == 1 && mp.rows && mp.group && mp.rows % mp.group)
                 return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_group");
             if (mp.sched == 1 && mp.waves && (int64_t)mp.waves * 256 * 8 < sp.b)
                 return set_error(KF_ERR_ARG, "row-resident schedule: mat_waves too small for the row length");
         } else if (sp.mat) {
-            MatParams q = default_mat_params(sp.a, sp.b, mp);
+            MatParams q = default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(sc, calls));
             if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_waves * mat_group");
         }
         pk.code = generate_kernel(sc, calls, part, mp, vp);

@@ -101,7 +101,10 @@ void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vec
         for (int v : ops) {
             if (v < 0) continue;
             if (s.values[v].kind == VK::Const) continue;
-            if (!produced_in(s, part, kid, v)) reads.insert(v);
+            if (!produced_in(s, part, kid, v)) {
+                reads.insert(v);
+                if (s.values[v].scale >= 0) reads.insert(s.values[v].scale);   // row scales of a quantised matrix
+            }
         }
         if (must_store(s, part, kid, k.out)) writes.insert(k.out);
     }
@@ -109,7 +112,7 @@ void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vec
         const Value& x = s.values[v];
         switch (x.kind) {
             case VK::Vec: return (uint64_t)x.n * 4;
-            case VK::Mat: return (uint64_t)x.rows * (uint64_t)x.cols * 4;
+            case VK::Mat: return (uint64_t)x.rows * (uint64_t)x.cols * (uint64_t)dtype_size(x.dtype);
             case VK::DevScalar: return 4;
             default: return 0;
         }
@@ -132,10 +135,13 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     const int kid = part[calls[0]];
     const Space sp = call_space(s, calls[0]);
     const long M = (long)sp.a, N = (long)sp.b;
-    const int K = p.k, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
+    // E matrix elements per 16-byte load unit (4 FP32, 8 BF16, 16 FP8); a lane
+    // takes p.k units per row, i.e. K = k E / 4 float4 column groups.
+    const int E = kernel_unit_elems(s, calls), EG = E / 4;
+    const int U = p.k, K = p.k * EG, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
     int LG = 0;
     while ((1 << LG) < G) ++LG;
-    const long C = 256L * K;
+    const long C = 64L * E * U;
     const long S = (N + C - 1) / C, NB = (M + R - 1) / R;
     const long NP = (N + 3) / 4 * 4;
 
@@ -165,6 +171,9 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             if (must_store(s, part, kid, k.out)) push_u(vec_out, k.out);
         }
     }
+    // quantised matrices bring their row scales (staged like other row vectors)
+    for (int v : mat_in)
+        if (s.values[v].scale >= 0) push_u(rowv, s.values[v].scale);
     for (int v : colv) push_u(vec_in, v);
     for (int v : rowv) push_u(vec_in, v);
     const bool row_part = !gemv_calls.empty() && S > 1;
@@ -181,7 +190,9 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
 
     // ---- arguments
     std::vector<std::string> sig;
-    for (int v : mat_in) sig.push_back(F("const float* __restrict__ M%d", v));
+    for (int v : mat_in)
+        sig.push_back(s.values[v].dtype == KF_F32 ? F("const float* __restrict__ M%d", v)
+                                                  : F("const unsigned char* __restrict__ M%d", v));
     for (int v : mat_out) sig.push_back(F("float* __restrict__ O%d", v));
     for (int v : vec_in) sig.push_back(F("const float* __restrict__ V%d", v));
     // outputs the main pass writes itself (the rest are written by the finishing launch)
@@ -215,7 +226,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     // ---- body
     Emitter e;
     e.l(F("constexpr long M = %ldL, N = %ldL, C = %ldL, S = %ldL, NB = %ldL, NP = %ldL;", M, N, C, S, NB, NP));
-    e.l(F("constexpr int K = %d, W = %d, G = %d, LG = %d, R = %d, NT = %d;", K, W, G, LG, R, NT));
+    e.l(F("constexpr int K = %d, W = %d, G = %d, LG = %d, R = %d, NT = %d, E = %d, EG = %d;", K, W, G, LG, R, NT, E, EG));
     for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
     for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
     e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
@@ -229,7 +240,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     }
     e.l("long col[K];");
     e.l("#pragma unroll");
-    e.l("for (int j = 0; j < K; ++j) col[j] = c0 + (long)(j * 64 + lane) * 4;");
+    e.l("for (int j = 0; j < K; ++j) col[j] = c0 + (long)((j / EG) * 64 + lane) * E + 4 * (j % EG);");
     // invariant column vectors (Algorithm 1, "load invariant data")
     for (int v : colv) {
         e.l(F("kf_f4 cv%d[K];", v));
@@ -281,7 +292,25 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         e.l("const long row = g0 + gi;");
         for (int v : mat_in) {
             e.l("#pragma unroll");
-            if (!edge)
+            const int dt = s.values[v].dtype;
+            if (dt != KF_F32) {
+                // one 16-byte unit per (row, u) decodes into 16/es elements = EQ float4 groups;
+                // a BF16 matrix in a kernel with 16-element units takes two units per span
+                const int es = dtype_size(dt), per = 16 / es, EQ = per / 4;
+                const char* dec = dt == KF_BF16 ? "kf_dec_bf16" : "kf_dec_fp8";
+                e.l(F("for (int u = 0; u < %d; ++u) {", U * (E / per)));
+                e.ind++;
+                e.l(F("const long cu0 = col[(u / %d) * EG] + (long)(u %% %d) * %d;", E / per, E / per, per));
+                if (!edge) {
+                    e.l(F("%s(kf_ldu_nt(M%d + (row * LD%d + cu0) * %d), &L%d[gi][u * %d]);", dec, v, v, es, v, EQ));
+                } else {
+                    e.l(F("if (row < r1 && cu0 < N) { %s(kf_ldu_nt(M%d + (row * LD%d + cu0) * %d), &L%d[gi][u * %d]);", dec, v, v, es, v, EQ));
+                    e.l(F("  for (int q = 0; q < %d; ++q) L%d[gi][u * %d + q] = kf_mask4(L%d[gi][u * %d + q], cu0 + 4 * q, N); }", EQ, v, EQ, v, EQ));
+                    e.l(F("else { for (int q = 0; q < %d; ++q) L%d[gi][u * %d + q] = kf_zero4(); }", EQ, v, EQ));
+                }
+                e.ind--;
+                e.l("}");
+            } else if (!edge)
                 e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = kf_ld4_nt(M%d + row * LD%d + col[j]);", v, v, v));
             else
                 e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = (row < r1) ? kf_ldm_edge(M%d + row * LD%d, col[j], N) : kf_zero4();", v, v, v));
@@ -299,12 +328,16 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         for (int c : calls) {
             const Call& k = s.calls[c];
             std::string Min = mexpr(k.in[0]);
+            const int qscale = s.values[k.in[0]].scale;   // row scale of a quantised matrix, or -1
             if (k.op == Op::Ger) {
                 int o = k.out;
                 e.l(F("const float cu%d = %s * rv%d[rl];", c, scal_name(k.alpha).c_str(), k.in[1]));
                 e.l(F("kf_f4 m%d[K];", o));
                 e.l("#pragma unroll");
-                e.l(F("for (int j = 0; j < K; ++j) m%d[j] = kf_fma4s(cu%d, cv%d[j], %s[j]);", o, c, k.in[2], Min.c_str()));
+                if (qscale >= 0)
+                    e.l(F("for (int j = 0; j < K; ++j) m%d[j] = kf_fma4s(cu%d, cv%d[j], kf_mul4s(rv%d[rl], %s[j]));", o, c, k.in[2], qscale, Min.c_str()));
+                else
+                    e.l(F("for (int j = 0; j < K; ++j) m%d[j] = kf_fma4s(cu%d, cv%d[j], %s[j]);", o, c, k.in[2], Min.c_str()));
                 if (must_store(s, part, kid, o)) {
                     if (!edge) {
                         e.l("#pragma unroll");
@@ -317,14 +350,16 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
                     }
                 }
             } else if (k.op == Op::Gemtv) {
-                e.l(F("const float xr%d = rv%d[rl];", c, k.in[1]));
+                if (qscale >= 0) e.l(F("const float xr%d = rv%d[rl] * rv%d[rl];", c, qscale, k.in[1]));
+                else e.l(F("const float xr%d = rv%d[rl];", c, k.in[1]));
                 e.l("#pragma unroll");
                 e.l(F("for (int j = 0; j < K; ++j) acc%d[j] = kf_fma4s(xr%d, %s[j], acc%d[j]);", c, c, Min.c_str(), c));
             } else if (k.op == Op::Gemv) {
                 e.l(F("float t%d = 0.f;", c));
                 e.l("#pragma unroll");
                 e.l(F("for (int j = 0; j < K; ++j) t%d = kf_dot4(%s[j], cv%d[j], t%d);", c, Min.c_str(), k.in[1], c));
-                e.l(F("rp%d[gi] = t%d;", c, c));
+                if (qscale >= 0) e.l(F("rp%d[gi] = rv%d[rl] * t%d;", c, qscale, c));
+                else e.l(F("rp%d[gi] = t%d;", c, c));
             }
         }
         e.ind--;
@@ -510,7 +545,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     std::string sigs, fsigs;
     for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
     for (size_t i = 0; i < fsig.size(); ++i) fsigs += (i ? ",\n    " : "    ") + fsig[i];
-    std::string key = F("mat K%d W%d G%d R%d M%ld N%ld|", K, W, G, R, M, N) + sigs + e.o.str() + fsigs + f.o.str();
+    std::string key = F("mat K%d W%d G%d R%d E%d M%ld N%ld|", K, W, G, R, E, M, N) + sigs + e.o.str() + fsigs + f.o.str();
     kc.name = F("kf_mat_%016llx", (unsigned long long)fnv1a(key));
     head << "extern \"C\" __global__ void __launch_bounds__(" << NT << ") " << kc.name << "(\n"
          << sigs << ") {\n" << e.o.str() << "}\n";
@@ -526,8 +561,8 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     }
     kc.source = head.str();
     kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + gemtv_calls.size() * (size_t)W * (C / 4) * 16;
-    kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d, \"strips\": %ld, \"row_blocks\": %ld}",
-                       K, W, G, R, S, NB);
+    kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d, \"unit_elems\": %d, \"strips\": %ld, \"row_blocks\": %ld}",
+                       U, W, G, R, E, S, NB);
     kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
     return kc;
 }
@@ -1069,7 +1104,7 @@ static void launch_bytes(const Script& s, Launch* l) {
         if (a.value < 0) continue;
         const Value& x = s.values[a.value];
         uint64_t b = x.kind == VK::Vec ? (uint64_t)x.n * 4
-                   : x.kind == VK::Mat ? (uint64_t)x.rows * (uint64_t)x.cols * 4
+                   : x.kind == VK::Mat ? (uint64_t)x.rows * (uint64_t)x.cols * (uint64_t)dtype_size(x.dtype)
                    : x.kind == VK::DevScalar ? 4 : 0;
         switch (a.kind) {
             case ArgKind::MatIn: case ArgKind::VecIn: case ArgKind::DevScalarIn: l->bytes_read += b; break;
@@ -1089,7 +1124,7 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
         if (q.sched != 1) q.waves = q.group = q.rows = 0;   // strip-schedule parameters do not carry over
         kc = gen_mat_rowres(s, calls, part, q);
     } else {
-        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp))
+        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(s, calls)))
                     : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
     }
     for (Launch& l : kc.launches) launch_bytes(s, &l);
@@ -1240,7 +1275,7 @@ void kernel_features(const Script& s, const KernelCode& kc, const std::vector<in
     double alone = 0;
     auto vbytes = [&](int v) -> double {
         const Value& x = s.values[v];
-        return x.kind == VK::Vec ? 4.0 * x.n : x.kind == VK::Mat ? 4.0 * x.rows * x.cols
+        return x.kind == VK::Vec ? 4.0 * x.n : x.kind == VK::Mat ? (double)dtype_size(x.dtype) * x.rows * x.cols
                                                                  : x.kind == VK::DevScalar ? 4.0 : 0.0;
     };
     int chained = 0;

@@ -67,6 +67,43 @@ __device__ __forceinline__ void kf_stm_edge(float* row, long col, long n, kf_f4 
     if (col + 2 < n) row[col + 2] = x.z;
 }
 
+// ---- quantised matrix storage (BF16, OCP FP8-E4M3) ---------------------------
+typedef unsigned int kf_u4 __attribute__((ext_vector_type(4)));
+typedef float kf_f2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ kf_u4 kf_ldu_nt(const unsigned char* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const kf_u4*>(p));
+}
+// 8 BF16 values (the upper halves of IEEE singles), lowest address first.
+__device__ __forceinline__ void kf_dec_bf16(kf_u4 w, kf_f4* out) {
+    out[0].x = __uint_as_float(w.x << 16); out[0].y = __uint_as_float(w.x & 0xffff0000u);
+    out[0].z = __uint_as_float(w.y << 16); out[0].w = __uint_as_float(w.y & 0xffff0000u);
+    out[1].x = __uint_as_float(w.z << 16); out[1].y = __uint_as_float(w.z & 0xffff0000u);
+    out[1].z = __uint_as_float(w.w << 16); out[1].w = __uint_as_float(w.w & 0xffff0000u);
+}
+// 16 FP8-E4M3 values with the hardware conversion (two bytes per instruction).
+__device__ __forceinline__ kf_f4 kf_dec_fp8_word(unsigned int x) {
+    const kf_f2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, false);
+    const kf_f2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)x, true);
+    kf_f4 r;
+    r.x = a.x; r.y = a.y; r.z = b.x; r.w = b.y;
+    return r;
+}
+__device__ __forceinline__ void kf_dec_fp8(kf_u4 w, kf_f4* out) {
+    out[0] = kf_dec_fp8_word(w.x);
+    out[1] = kf_dec_fp8_word(w.y);
+    out[2] = kf_dec_fp8_word(w.z);
+    out[3] = kf_dec_fp8_word(w.w);
+}
+// Zero the components of v at column index >= n (v holds columns col..col+3).
+__device__ __forceinline__ kf_f4 kf_mask4(kf_f4 v, long col, long n) {
+    v.x = (col + 0 < n) ? v.x : 0.f;
+    v.y = (col + 1 < n) ? v.y : 0.f;
+    v.z = (col + 2 < n) ? v.z : 0.f;
+    v.w = (col + 3 < n) ? v.w : 0.f;
+    return v;
+}
+
 // ---- B8: element-wise map arithmetic (explicit FMAs, no contraction) --------
 __device__ __forceinline__ kf_f4 kf_fma4s(float s, kf_f4 v, kf_f4 c) {
     kf_f4 r;

@@ -19,6 +19,8 @@ struct Value {
     VK kind = VK::Vec;
     int64_t n = 0;                 // vector length
     int64_t rows = 0, cols = 0, ld = 0;
+    int dtype = 0;                 // matrices: KF_F32, KF_BF16, KF_FP8_E4M3
+    int scale = -1;                // quantised matrices: value id of the row-scale vector
     float cval = 0.f;              // kf_const value
     int producer = -1;             // call index, -1 for declared values
     bool input = false, output = false;
@@ -74,7 +76,13 @@ std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vecto
 // ---- implementation parameters ---------------------------------------------
 struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0; };  // sched 1 = row-resident
 struct VecParams { int unroll = 0, threads = 0, grid = 0; };
-MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req);
+// e_per_unit: matrix elements per 16-byte load unit of the kernel (4 for FP32,
+// 8 with a BF16 matrix, 16 with an FP8 matrix).
+MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req, int e_per_unit = 4);
+int dtype_size(int dtype);
+// Elements per 16-byte unit of the kernel made of `calls` (smallest element size
+// of the matrices it loads).
+int kernel_unit_elems(const Script& s, const std::vector<int>& calls);
 VecParams default_vec_params(int64_t n, const VecParams& req);
 
 // ---- code generation (codegen.cpp) --------------------------------------------

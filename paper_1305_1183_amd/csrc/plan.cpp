@@ -103,7 +103,8 @@ std::string block_illegal_reason(const Script& s, const std::vector<int>& calls)
             // R3'': a row dot may feed the row-indexed x of a gemtv when the kernel
             // keeps whole rows in one workgroup (row-resident schedule, cols <= 32768)
             if (!ok && k.op == Op::Gemv && kd.op == Op::Gemtv && kd.in[1] == k.out && kd.in[0] != k.out &&
-                kd.in[2] != k.out && kd.alpha != k.out && kd.beta != k.out && call_space(s, c).b <= 32768)
+                kd.in[2] != k.out && kd.alpha != k.out && kd.beta != k.out && call_space(s, c).b <= 32768 &&
+                s.values[k.in[0]].dtype == KF_F32 && s.values[kd.in[0]].dtype == KF_F32)
                 ok = true;
             if (!ok)
                 return std::string("R3: result of ") + op_name(k.op) +
@@ -274,14 +275,25 @@ std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vecto
     return order;
 }
 
-MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req) {
+int dtype_size(int dtype) { return dtype == KF_BF16 ? 2 : dtype == KF_FP8_E4M3 ? 1 : 4; }
+
+int kernel_unit_elems(const Script& s, const std::vector<int>& calls) {
+    int es = 4;
+    for (int c : calls) {
+        const Value& A = s.values[s.calls[c].in[0]];
+        if (A.kind == VK::Mat) es = std::min(es, dtype_size(A.dtype));
+    }
+    return 16 / es;
+}
+
+MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req, int e_per_unit) {
     MatParams p = req;
     if (p.k <= 0) p.k = 1;
     if (p.waves <= 0) p.waves = 4;
     if (p.group <= 0) p.group = 4;
     const int unit = p.waves * p.group;
     if (p.rows <= 0) {
-        const int64_t C = 256LL * p.k;
+        const int64_t C = 64LL * e_per_unit * p.k;
         const int64_t S = (cols + C - 1) / C;
         // Aim for about 2048 workgroups (8 per CU) with at most 512 rows each.
         int64_t want_nb = (2048 + S - 1) / S;

@@ -140,3 +140,38 @@ def loguniform_int(seed: int, tensor_id: int, count: int, lo: int, hi: int) -> n
     u = bits.astype(np.float64) * 2.0 ** -53
     v = np.floor(np.exp(np.log(lo) + u * (np.log(hi + 1) - np.log(lo)))).astype(np.int64)
     return np.clip(v, lo, hi)
+
+
+def _normal_from_bits(h1: np.ndarray, h2: np.ndarray) -> np.ndarray:
+    # Box-Muller: u1 in (0, 1], u2 in [0, 1) from 53 random bits each
+    u1 = ((h1 >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
+    u2 = (h2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def normal_at(seed: int, tensor_id: int, idx: np.ndarray) -> np.ndarray:
+    """float64 N(0, 1) values of element indices idx (element k uses hashes 2k, 2k + 1)."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    key = np.uint64(stream_key(seed, tensor_id))
+    with np.errstate(over="ignore"):
+        h1 = _mix64(key + (np.uint64(2) * idx + np.uint64(1)) * np.uint64(GAMMA))
+        h2 = _mix64(key + (np.uint64(2) * idx + np.uint64(2)) * np.uint64(GAMMA))
+    return _normal_from_bits(h1, h2)
+
+
+def normal(seed: int, tensor_id: int, count: int, start: int = 0) -> np.ndarray:
+    """float64 N(0, 1) values of elements start .. start + count - 1."""
+    out = np.empty(count, dtype=np.float64)
+
+    def fill(o):
+        c = min(_CHUNK, count - o)
+        out[o:o + c] = normal_at(seed, tensor_id, np.arange(start + o, start + o + c, dtype=np.uint64))
+
+    offs = list(range(0, count, _CHUNK))
+    if len(offs) <= 1:
+        if count:
+            fill(0)
+        return out
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(fill, offs))
+    return out

@@ -76,6 +76,7 @@ _SIGS = {
     "kf_script_destroy": ([_vp], None),
     "kf_vector": ([_vp, _i64, _P(_i32)], _i32),
     "kf_matrix": ([_vp, _i64, _i64, _i64, _P(_i32)], _i32),
+    "kf_matrix_q": ([_vp, _i64, _i64, _i64, _i32, _i32, _P(_i32)], _i32),
     "kf_const": ([_vp, _f32, _P(_i32)], _i32),
     "kf_scalar": ([_vp, _P(_i32)], _i32),
     "kf_input": ([_vp, _i32], _i32),
@@ -188,6 +189,15 @@ def kf_vector(s, n: int) -> int:
 
 def kf_matrix(s, rows: int, cols: int, ld: int = 0) -> int:
     return _new(lib().kf_matrix, s, rows, cols, ld)
+
+
+KF_F32, KF_BF16, KF_FP8_E4M3 = 0, 1, 2
+DTYPES = {"f32": KF_F32, "bf16": KF_BF16, "fp8": KF_FP8_E4M3}
+
+
+def kf_matrix_q(s, rows: int, cols: int, dtype, scale: int, ld: int = 0) -> int:
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    return _new(lib().kf_matrix_q, s, rows, cols, ld, dt, scale)
 
 
 def kf_const(s, v: float) -> int:

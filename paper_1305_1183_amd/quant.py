@@ -1,0 +1,68 @@
+"""Row-scaled reduced-precision matrix storage (BF16, OCP FP8-E4M3).
+
+A float64 matrix is stored as codes plus one FP32 scale per row: element
+(i, j) stands for scale[i] * decode(code_ij). Rounding is to nearest, ties to
+even, directly from float64. BF16 rows keep scale 1 (BF16 has the FP32
+exponent range); FP8 rows use scale = amax_i / 448 (448 is the largest finite
+E4M3 value) and saturate at +-448.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+E4M3_MAX = 448.0
+
+
+def _round_to(x: np.ndarray, mbits: int, emin: int) -> np.ndarray:
+    """x rounded to the nearest value with `mbits` fraction bits (ties to even),
+    exponents below `emin` falling on the subnormal grid 2**(emin - mbits)."""
+    x = np.asarray(x, dtype=np.float64)
+    _, e = np.frexp(x)                     # x = m 2**e, 0.5 <= |m| < 1
+    e = np.maximum(e - 1, emin)            # floor(log2 |x|), clamped to the subnormal range
+    q = np.ldexp(1.0, (e - mbits).astype(np.int64))
+    return np.rint(x / q) * q
+
+
+def to_bf16_codes(x: np.ndarray) -> np.ndarray:
+    r = _round_to(x, 7, -126).astype(np.float32)       # exact: r has <= 8 significant bits
+    return (r.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+
+
+def to_e4m3_codes(x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    r = np.clip(_round_to(x, 3, -6), -E4M3_MAX, E4M3_MAX)
+    sign = (np.signbit(r)).astype(np.uint8) << np.uint8(7)
+    a = np.abs(r)
+    code = np.zeros(a.shape, dtype=np.uint8)
+    nz = a > 0
+    _, e = np.frexp(a[nz])
+    e = e - 1
+    sub = e < -6
+    mant = np.where(sub, a[nz] / 2.0 ** -9, a[nz] / np.ldexp(1.0, e - 3) - 8.0)
+    expf = np.where(sub, 0, e + 7)
+    code[nz] = (expf.astype(np.uint8) << np.uint8(3)) | mant.astype(np.uint8)
+    return code | sign
+
+
+def quantize_rows(A: np.ndarray, fmt: str, ld: int | None = None):
+    """(storage rows x ld, scales float32 rows) of a float64 matrix."""
+    A = np.asarray(A, dtype=np.float64)
+    rows, cols = A.shape
+    if fmt == "f32":
+        ld = ld or (cols + 3) // 4 * 4
+        out = np.zeros((rows, ld), np.float32)
+        out[:, :cols] = A.astype(np.float32)
+        return out, np.ones(rows, np.float32)
+    if fmt == "bf16":
+        ld = ld or (cols + 7) // 8 * 8
+        out = np.zeros((rows, ld), np.uint16)
+        out[:, :cols] = to_bf16_codes(A)
+        return out, np.ones(rows, np.float32)
+    if fmt == "fp8":
+        ld = ld or (cols + 15) // 16 * 16
+        amax = np.max(np.abs(A), axis=1)
+        scale = np.where(amax > 0, amax / E4M3_MAX, 1.0).astype(np.float32)
+        out = np.zeros((rows, ld), np.uint8)
+        out[:, :cols] = to_e4m3_codes(A / scale.astype(np.float64)[:, None])
+        return out, scale
+    raise ValueError(fmt)

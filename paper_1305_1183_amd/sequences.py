@@ -76,8 +76,9 @@ class Program:
         """Bind input tensors by name; allocate outputs and the workspace."""
         for name in self.seq.inputs:
             t = tensors[name]
-            if t.dtype != torch.float32 or not t.is_contiguous():
-                raise ValueError("%s must be a contiguous float32 tensor" % name)
+            want = {"bf16": torch.int16, "fp8": torch.uint8}.get(getattr(self.seq, "dtypes", {}).get(name), torch.float32)
+            if t.dtype != want or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous %s tensor" % (name, want))
             self.tensors[name] = t
             kf.kf_bind(self.plan, self.seq.values[name], t.data_ptr())
         for name in self.seq.outputs:
@@ -236,3 +237,58 @@ def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0) -> Sequence:
     if name == "gemver":
         return gemver(m, n, scal["alpha"], scal["beta"], ld)
     raise KeyError(name)
+
+
+def _qmat(q, name, rows, cols, fmt):
+    """Matrix input in storage format fmt ('f32', 'bf16', 'fp8') with its row scales."""
+    if fmt == "f32":
+        return _mat(q, name, rows, cols)
+    sc = _vec(q, name + "_scale", rows)
+    v = kf.kf_matrix_q(q.script, rows, cols, fmt, sc)
+    kf.kf_input(q.script, v)
+    ld = kf.kf_value_info(q.script, v)[3]
+    q.values[name] = v
+    q.inputs.append(name)
+    q.shapes[name] = (rows, ld)
+    q.dtypes = getattr(q, "dtypes", {})
+    q.dtypes[name] = fmt
+    return v
+
+
+def bicgk_q(m: int, n: int, fmt: str) -> Sequence:
+    """BiCGK with A stored as fmt (row-scaled BF16 / FP8-E4M3, or FP32)."""
+    q = _seq("bicgk_" + fmt)
+    A = _qmat(q, "A", m, n, fmt)
+    p, r = _vec(q, "p", n), _vec(q, "r", m)
+    one = _const(q, "one", 1.0)
+    _out(q, "q", kf.kf_gemv(q.script, one, A, p))
+    _out(q, "s", kf.kf_gemtv(q.script, one, A, r))
+    return q
+
+
+def gemver_q(m: int, n: int, alpha: float, beta: float, fmt: str) -> Sequence:
+    """GEMVER with A stored as fmt; B, x, w are FP32."""
+    q = _seq("gemver_" + fmt)
+    A = _qmat(q, "A", m, n, fmt)
+    u1, v1 = _vec(q, "u1", m), _vec(q, "v1", n)
+    u2, v2 = _vec(q, "u2", m), _vec(q, "v2", n)
+    y, z = _vec(q, "y", m), _vec(q, "z", n)
+    a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
+    B1 = kf.kf_ger(q.script, one, A, u1, v1)
+    B = kf.kf_ger(q.script, one, B1, u2, v2)
+    x = kf.kf_gemtv(q.script, b, B, y, one, z)
+    w = kf.kf_gemv(q.script, a, B, x)
+    _out(q, "B", B)
+    _out(q, "x", x)
+    _out(q, "w", w)
+    return q
+
+
+def decode_probe(ncodes: int, fmt: str) -> Sequence:
+    """gemtv of a 1 x ncodes matrix in format fmt by x = [1]: returns the decoded row."""
+    q = _seq("decode_" + fmt)
+    A = _qmat(q, "A", 1, ncodes, fmt)
+    x = _vec(q, "x", 1)
+    one = _const(q, "one", 1.0)
+    _out(q, "y", kf.kf_gemtv(q.script, one, A, x))
+    return q

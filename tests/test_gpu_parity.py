@@ -198,7 +198,7 @@ def test_enumerated_plans_agree():
         SC.check_against_oracle("gemver", m, n, {k: v.cpu().numpy() for k, v in outs.items()}, ref)
 
 
-@pytest.mark.parametrize("params", [dict(mat_sched=1), dict(mat_sched=1, mat_waves=2, mat_group=2, mat_rows=6),
+@pytest.mark.parametrize("params", [dict(mat_sched=1), dict(mat_sched=1, mat_waves=4, mat_group=2, mat_rows=6),
                                     dict(mat_sched=1, mat_waves=16, mat_group=1, mat_rows=64),
                                     dict(mat_sched=1, mat_waves=8, mat_group=4, mat_rows=4)])
 @pytest.mark.parametrize("mode", ["fused", "unfused"])
