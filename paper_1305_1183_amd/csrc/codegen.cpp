@@ -404,7 +404,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         for (int i = 0; i < ngt; ++i) {
             int c = gemtv_calls[i];
             e.l("#pragma unroll");
-            e.l(F("for (int j = 0; j < K; ++j) kf_red[%d][wave * (C / 4) + j * 64 + lane] = acc%d[j];", i, c));
+            e.l(F("for (int j = 0; j < K; ++j) kf_red[%d][wave * (C / 4) + (int)((col[j] - c0) >> 2)] = acc%d[j];", i, c));
         }
         e.l("__syncthreads();");
         e.l("for (int q = tid; q < C / 4; q += NT) {");
