@@ -465,9 +465,12 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         }
         finl.args.push_back({ArgKind::Workspace, -1});
         fsig.push_back("const float* __restrict__ ws");
-        const long RBK = row_part ? (M + 255) / 256 : 0;
+        const int FWb = (col_part && NB >= 64) ? 1024 : 256;
+        const long RBK = row_part ? (M + FWb - 1) / FWb : 0;
         const long CBK = col_part ? (NP / 4 + 63) / 64 : 0;
+        const int FW = NB >= 64 ? 16 : 4;   // waves of the finishing pass that split the row blocks
         f.l(F("constexpr long M = %ldL, N = %ldL, S = %ldL, NB = %ldL, NP = %ldL, RBK = %ldL;", M, N, S, NB, NP, RBK));
+        f.l(F("constexpr int FW = %d; (void)FW;", FW));
         for (int v : scalars) {
             if (s.values[v].kind == VK::Const) f.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
             else f.l(F("const float %s = *P%d;", scal_name(v).c_str(), v));
@@ -475,7 +478,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         if (row_part) {
             f.l("if (blockIdx.x < RBK) {");
             f.ind++;
-            f.l("const long row = (long)blockIdx.x * 256 + threadIdx.x;");
+            f.l("const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;");
             f.l("if (row < M) {");
             f.ind++;
             for (int c : gemv_calls) {
@@ -506,11 +509,11 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.ind++;
             f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
             f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 64 + lane);");
-            f.l(F("__shared__ kf_f4 kf_fr[%d][4][64];", (int)gemtv_calls.size()));
+            f.l(F("__shared__ kf_f4 kf_fr[%d][FW][64];", (int)gemtv_calls.size()));
             for (size_t i = 0; i < gemtv_calls.size(); ++i) {
                 int c = gemtv_calls[i];
                 f.l(F("kf_f4 part%d = kf_zero4();", c));
-                f.l(F("if (cc < N) for (long b = wave; b < NB; b += 4) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+                f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
                 f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
             }
             f.l("__syncthreads();");
@@ -518,7 +521,8 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.ind++;
             for (size_t i = 0; i < gemtv_calls.size(); ++i) {
                 int c = gemtv_calls[i];
-                f.l(F("const kf_f4 sum%d = ((kf_fr[%zu][0][lane] + kf_fr[%zu][1][lane]) + kf_fr[%zu][2][lane]) + kf_fr[%zu][3][lane];", c, i, i, i, i));
+                f.l(F("kf_f4 sum%d = kf_fr[%zu][0][lane];", c, i));
+                f.l(F("for (int w = 1; w < FW; ++w) sum%d += kf_fr[%zu][w][lane];", c, i));
             }
             for (int c : gemtv_calls) {
                 const Call& k = s.calls[c];
@@ -538,7 +542,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.l("}");
         }
         finl.grid = (int)(RBK + CBK);
-        finl.block = 256;
+        finl.block = col_part ? 64 * FW : 256;
     }
     // the main pass no longer stores outputs that the finishing launch writes
     std::ostringstream head;
@@ -555,7 +559,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     kc.launches.push_back(mainl);
     if (row_part || col_part) {
         finl.name = kc.name + "_fin";
-        head << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n"
+        head << "extern \"C\" __global__ void __launch_bounds__(" << finl.block << ") " << finl.name << "(\n"
              << fsigs << ") {\n" << f.o.str() << "}\n";
         kc.launches.push_back(finl);
     }
@@ -1040,13 +1044,15 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         for (int v : scalars)
             f.l(s.values[v].kind == VK::Const ? F("const float %s = P%d;", scal_name(v).c_str(), v)
                                               : F("const float %s = *P%d;", scal_name(v).c_str(), v));
+        const int FW = NB >= 64 ? 16 : 4;   // waves that split the row blocks
+        f.l(F("constexpr int FW = %d;", FW));
         f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
         f.l("const long cc = 4L * ((long)blockIdx.x * 64 + lane);");
-        f.l(F("__shared__ kf_f4 kf_fr[%d][4][64];", (int)gemtv_calls.size()));
+        f.l(F("__shared__ kf_f4 kf_fr[%d][FW][64];", (int)gemtv_calls.size()));
         for (size_t i = 0; i < gemtv_calls.size(); ++i) {
             int c = gemtv_calls[i];
             f.l(F("kf_f4 part%d = kf_zero4();", c));
-            f.l(F("if (cc < N) for (long b = wave; b < NB; b += 4) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
+            f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
             f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
         }
         f.l("__syncthreads();");
@@ -1055,7 +1061,8 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         for (size_t i = 0; i < gemtv_calls.size(); ++i) {
             int c = gemtv_calls[i];
             const Call& k = s.calls[c];
-            f.l(F("const kf_f4 sum%d = ((kf_fr[%zu][0][lane] + kf_fr[%zu][1][lane]) + kf_fr[%zu][2][lane]) + kf_fr[%zu][3][lane];", c, i, i, i, i));
+            f.l(F("kf_f4 sum%d = kf_fr[%zu][0][lane];", c, i));
+            f.l(F("for (int w = 1; w < FW; ++w) sum%d += kf_fr[%zu][w][lane];", c, i));
             std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
             if (k.in[2] >= 0) {
                 std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)
@@ -1069,7 +1076,7 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         f.ind--;
         f.l("}");
         finl.grid = (int)((NP / 4 + 63) / 64);
-        finl.block = 256;
+        finl.block = 64 * FW;
     }
     std::string sigs, fsigs;
     for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
@@ -1085,8 +1092,8 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     kc.launches.push_back(mainl);
     if (col_part) {
         finl.name = kc.name + "_fin";
-        head << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n" << fsigs << ") {\n"
-             << f.o.str() << "}\n";
+        head << "extern \"C\" __global__ void __launch_bounds__(" << finl.block << ") " << finl.name << "(\n" << fsigs
+             << ") {\n" << f.o.str() << "}\n";
         kc.launches.push_back(finl);
     }
     kc.source = head.str();
