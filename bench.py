@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -37,6 +39,8 @@ def parse():
                     help="only run the 1 GiB streaming copy (memory-counter calibration)")
     ap.add_argument("--tune", action="store_true",
                     help="grid-search the implementation parameters of every sequence and print them")
+    ap.add_argument("--precision", action="store_true",
+                    help="reduced-precision suite: BiCGK and GEMVER at n = 32768 with A in FP32, BF16, FP8-E4M3")
     return ap.parse_args()
 
 
@@ -75,13 +79,49 @@ def cpu_baseline():
                       "AXPYDOT/WAXPBY on 2^26 entries; %.1f s total" % (rows, n, total_s)}
 
 
+def precision_suite(args, torch, kf, S, WL, dev):
+    """GB/s of BiCGK and GEMVER at n = 32768 with A stored as FP32, BF16 and
+    FP8-E4M3 (row scales), fused and unfused (one JSON line; not the headline)."""
+    n = WL.PREC_N
+    res = {}
+    for name in WL.PREC_SEQ:
+        t0 = time.time()
+        stored, vecs, scal = WL.precision_inputs(name, n, WL.PREC_FORMATS, seed=4000 + WL.SEQ_INDEX[name])
+        log("precision inputs %s: %.1f s" % (name, time.time() - t0))
+        for fmt in WL.PREC_FORMATS:
+            arrays = WL.precision_arrays(fmt, stored, vecs)
+            q = S.bicgk_q(n, n, fmt) if name == "bicgk" else S.gemver_q(n, n, scal["alpha"], scal["beta"], fmt)
+            devin = {}
+            for k, v in arrays.items():
+                if v.dtype == np.uint16:
+                    v = v.view(np.int16)
+                devin[k] = torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+            del arrays
+            row = {}
+            for mode in ("fused", "unfused"):
+                prog = q.compile(mode=mode).bind(device=dev, **devin)
+                r, w = prog.bytes()
+                us = prog.time(3, 20)
+                row[mode] = {"us": round(us, 2), "bytes": r + w, "gbps": round((r + w) / us / 1e3, 1),
+                             "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+                del prog
+            row["speedup"] = round(row["unfused"]["us"] / row["fused"]["us"], 3)
+            res["%s/%s" % (name, fmt)] = row
+            log("precision %s %s: fused %.1f us (%.1f GB/s), unfused %.1f us" %
+                (name, fmt, row["fused"]["us"], row["fused"]["gbps"], row["unfused"]["us"]))
+            del devin
+            torch.cuda.empty_cache()
+        del stored
+    print(json.dumps({"metric": "reduced-precision A: GB/s and speedup vs unfused (not the headline)",
+                      "n": n, "results": res, "unit": "GB/s", "peak": HBM_PEAK_GBPS}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_1305_1183_amd import kf
@@ -105,6 +145,9 @@ def main():
 
     names = [s for s in args.only.split(",") if s] or list(WL.ORDER)
     n, vec = WL.SUITE_N, WL.SUITE_VEC
+    if args.precision:
+        precision_suite(args, torch, kf, S, WL, dev)
+        return
     if args.tune:
         from paper_1305_1183_amd import autotune
         for name in names:

@@ -271,17 +271,26 @@ def gesummv_sampled(alpha, A, beta, B, x, rows, cols=None):
     return gemv(beta, Br, xd, 1.0, t)
 
 
-def gemver_sampled(alpha, beta, A, u1, v1, u2, v2, y, z, rows, cols=None, panel=512):
-    """B on the given rows, the whole x, and w on the given rows."""
+def gemver_sampled(alpha, beta, A, u1, v1, u2, v2, y, z, rows, cols=None, panel=512, workers=1):
+    """B on the given rows, the whole x, and w on the given rows. Column
+    panels of x are independent outputs; `workers` threads may take them."""
     n = int(cols) if cols is not None else A.shape[1]
     f = lambda a: np.asarray(a, dtype=np.float64)
     u1d, v1d, u2d, v2d, yd, zd = f(u1), f(v1), f(u2), f(v2), f(y), f(z)
     # x = beta B^T y + z, one column panel of B at a time
     x = np.empty(n, dtype=np.float64)
-    for c0 in range(0, n, panel):
+
+    def x_panel(c0):
         c = np.arange(c0, min(n, c0 + panel))
         Bp = ger(1.0, ger(1.0, _mat_panel(A, c), u1d, v1d[c]), u2d, v2d[c])
         x[c] = gemtv(beta, Bp, yd, 1.0, zd[c])
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(x_panel, range(0, n, panel)))
+    else:
+        for c0 in range(0, n, panel):
+            x_panel(c0)
     Ar = np.ascontiguousarray(A[rows, :n], dtype=np.float64)
     Br = ger(1.0, ger(1.0, Ar, u1d[rows], v1d), u2d[rows], v2d)
     w = gemv(alpha, Br, x)

@@ -23,25 +23,39 @@ def _round_to(x: np.ndarray, mbits: int, emin: int) -> np.ndarray:
     return np.rint(x / q) * q
 
 
+def _rne_bits(b: np.ndarray, drop: int) -> np.ndarray:
+    """Round the float64 bit patterns b (non-negative values) to nearest, ties
+    to even, keeping 52 - drop fraction bits; a carry moves into the exponent."""
+    one = np.uint64(1)
+    half = (one << np.uint64(drop - 1)) - one
+    lsb = (b >> np.uint64(drop)) & one
+    return ((b + half + lsb) >> np.uint64(drop)) << np.uint64(drop)
+
+
 def to_bf16_codes(x: np.ndarray) -> np.ndarray:
-    r = _round_to(x, 7, -126).astype(np.float32)       # exact: r has <= 8 significant bits
-    return (r.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
+    x = np.asarray(x, dtype=np.float64)
+    a = np.abs(x)
+    r = _rne_bits(a.view(np.uint64), 45).view(np.float64)      # 7 fraction bits
+    tiny = a < 2.0 ** -126                                     # BF16 subnormal range
+    if np.any(tiny):
+        r = np.where(tiny, np.rint(a / 2.0 ** -133) * 2.0 ** -133, r)
+    r32 = np.copysign(r, x).astype(np.float32)                 # exact: <= 8 significant bits
+    return (r32.view(np.uint32) >> np.uint32(16)).astype(np.uint16)
 
 
 def to_e4m3_codes(x: np.ndarray) -> np.ndarray:
     x = np.asarray(x, dtype=np.float64)
-    r = np.clip(_round_to(x, 3, -6), -E4M3_MAX, E4M3_MAX)
-    sign = (np.signbit(r)).astype(np.uint8) << np.uint8(7)
-    a = np.abs(r)
-    code = np.zeros(a.shape, dtype=np.uint8)
-    nz = a > 0
-    _, e = np.frexp(a[nz])
-    e = e - 1
-    sub = e < -6
-    mant = np.where(sub, a[nz] / 2.0 ** -9, a[nz] / np.ldexp(1.0, e - 3) - 8.0)
-    expf = np.where(sub, 0, e + 7)
-    code[nz] = (expf.astype(np.uint8) << np.uint8(3)) | mant.astype(np.uint8)
-    return code | sign
+    a = np.abs(x)
+    b = _rne_bits(a.view(np.uint64), 49)                       # 3 fraction bits (normal range)
+    sub = a < 2.0 ** -6                                        # subnormals: multiples of 2**-9
+    m_sub = np.rint(a * 2.0 ** 9)                              # 0..8 (8 = smallest normal)
+    e = (b >> np.uint64(52)).astype(np.int64) - 1023
+    m = ((b >> np.uint64(49)) & np.uint64(7)).astype(np.int64)
+    code = ((e + 7) << 3) | m
+    code = np.where(sub, m_sub.astype(np.int64), code)         # m_sub = 8 encodes 0x08 = 2**-6
+    code = np.minimum(code, 0x7E)                               # saturate at 448 (0x7E)
+    code = np.where(np.isnan(x), 0x7F, code)
+    return (code.astype(np.uint8) | (np.signbit(x).astype(np.uint8) << np.uint8(7))).astype(np.uint8)
 
 
 def quantize_rows(A: np.ndarray, fmt: str, ld: int | None = None):

@@ -117,3 +117,59 @@ def traffic_from_profiles(profile_dir: str, kernel_name: str):
     if not k:
         return None
     return int(round(k["fetch_bytes_scaled"] + k["write_bytes_scaled"]))
+
+
+# ---- reduced-precision suite: A ~ N(0, 1) drawn in float64, stored per format
+PREC_N = 32768
+PREC_FORMATS = ("f32", "bf16", "fp8")
+PREC_SEQ = ("bicgk", "gemver")
+
+
+PREC_PANEL = 512
+
+
+def normal_panel(seed: int, n: int, r0: int, panel: int = PREC_PANEL) -> np.ndarray:
+    """Rows r0 .. r0 + panel - 1 of the float64 N(0, 1) matrix: numpy PCG64
+    seeded per row panel (seed, panel index), so any panel can be redrawn."""
+    rng = np.random.Generator(np.random.PCG64([int(seed), int(r0 // panel)]))
+    return rng.standard_normal((min(panel, n - r0), n))
+
+
+def precision_inputs(name: str, n: int, formats, seed: int, panel: int = PREC_PANEL):
+    """Operands of BiCGK or GEMVER with A (n x n) drawn N(0, 1) in float64
+    (row panels, normal_panel) and stored in each of `formats` with row
+    scales; vectors uniform [-1, 1). Returns ({fmt: (storage, scales)},
+    vectors, scalars)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from . import quant as Q
+    out = {}
+
+    ld = {"f32": (n + 3) // 4 * 4, "bf16": (n + 7) // 8 * 8, "fp8": (n + 15) // 16 * 16}
+    dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
+    for f in formats:
+        out[f] = (np.zeros((n, ld[f]), dt[f]), np.empty(n, np.float32))
+
+    def do_panel(r0):
+        A64 = normal_panel(seed, n, r0, panel)
+        for c0 in range(0, A64.shape[0], 4):          # small row groups stay in cache
+            blk = A64[c0:c0 + 4]
+            for f in formats:
+                st, sc = Q.quantize_rows(blk, f, ld[f])
+                out[f][0][r0 + c0:r0 + c0 + blk.shape[0]] = st
+                out[f][1][r0 + c0:r0 + c0 + blk.shape[0]] = sc
+
+    with ThreadPoolExecutor(I._threads()) as ex:
+        list(ex.map(do_panel, range(0, n, panel)))
+    names = ["p", "r"] if name == "bicgk" else ["u1", "v1", "u2", "v2", "y", "z"]
+    vecs = {k: I.vector(seed, 1 + i, n) for i, k in enumerate(names)}
+    scal = {} if name == "bicgk" else {"alpha": I.scalar_uniform(seed, 100), "beta": I.scalar_uniform(seed, 101)}
+    return out, vecs, scal
+
+
+def precision_arrays(fmt, stored, vecs):
+    """Bindable arrays of one format (FP32 matrices take no scale vector)."""
+    st, sc = stored[fmt]
+    arrays = dict(vecs, A=st)
+    if fmt != "f32":
+        arrays["A_scale"] = sc
+    return arrays
