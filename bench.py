@@ -61,7 +61,7 @@ def cpu_baseline():
     n, rows, vec = WL.SUITE_N, WL.SUITE_N, 1 << 26
     total_bytes, total_s = 0, 0.0
     for name in WL.ORDER:
-        m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (rows, n)
+        m, nn = (vec, vec) if name in WL.BLAS1 else (rows, n)
         arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
         q = S.by_name(name, m, nn, scal)
         p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
@@ -151,7 +151,7 @@ def main():
     if args.tune:
         from paper_1305_1183_amd import autotune
         for name in names:
-            m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (n, n)
+            m, nn = (vec, vec) if name in WL.BLAS1 else (n, n)
             arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
             q = S.by_name(name, m, nn, scal)
             devin = {k: torch.from_numpy(v).to(dev) for k, v in arrays.items()}
@@ -164,10 +164,8 @@ def main():
             del devin
             torch.cuda.empty_cache()
         return
-    progs = {}
-    t0 = time.time()
-    for name in names:
-        m, nn = (vec, vec) if name in ("axpydot", "waxpby") else (n, n)
+    def prepare(name):
+        m, nn = (vec, vec) if name in WL.BLAS1 else (n, n)
         arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
         q = S.by_name(name, m, nn, scal)
         devin = {k: torch.from_numpy(v).to(dev) for k, v in arrays.items()}
@@ -175,7 +173,28 @@ def main():
         fused = q.compile(mode="fused", **WL.tuned_params(name, m, nn, "fused")).bind(device=dev, **devin)
         unfused = None if args.no_unfused else q.compile(
             mode="unfused", **WL.tuned_params(name, m, nn, "unfused")).bind(device=dev, **devin)
-        progs[name] = (q, fused, unfused, devin)
+        return q, fused, unfused, devin
+
+    def measure(prog_tuple):
+        q, fused, unfused, _ = prog_tuple
+        r, w = fused.bytes()
+        tf = fused.time(3, 20)
+        entry = {"fused_us": round(tf, 2), "fused_bytes": r + w,
+                 "fused_gbps": round((r + w) / tf / 1e3, 1),
+                 "fused_pct_peak": round((r + w) / tf / 1e3 / HBM_PEAK_GBPS * 100, 1),
+                 "kernels": fused.num_kernels}
+        if unfused is not None:
+            ru, wu = unfused.bytes()
+            tu = unfused.time(3, 20)
+            entry.update({"unfused_us": round(tu, 2), "unfused_bytes": ru + wu,
+                          "unfused_gbps": round((ru + wu) / tu / 1e3, 1),
+                          "speedup": round(tu / tf, 3), "unfused_kernels": unfused.num_kernels})
+        return entry
+
+    progs = {}
+    t0 = time.time()
+    for name in names:
+        progs[name] = prepare(name)
         log("prepared %s (%.1f s)" % (name, time.time() - t0))
 
     # launch table of the fused step: every HIP launch of every plan kernel
@@ -235,22 +254,17 @@ def main():
                 "avg_us": round(dom_us, 2), "bytes_per_launch": dk["bytes"],
                 "timing": "HIP events on the launch stream around this launch, mean over the timed steps"}
 
-    seqs = {}
-    for name in names:
-        q, fused, unfused, _ = progs[name]
-        r, w = fused.bytes()
-        tf = fused.time(3, 20)
-        entry = {"fused_us": round(tf, 2), "fused_bytes": r + w,
-                 "fused_gbps": round((r + w) / tf / 1e3, 1),
-                 "fused_pct_peak": round((r + w) / tf / 1e3 / HBM_PEAK_GBPS * 100, 1),
-                 "kernels": fused.num_kernels}
-        if unfused is not None:
-            ru, wu = unfused.bytes()
-            tu = unfused.time(3, 20)
-            entry.update({"unfused_us": round(tu, 2), "unfused_bytes": ru + wu,
-                          "unfused_gbps": round((ru + wu) / tu / 1e3, 1),
-                          "speedup": round(tu / tf, 3), "unfused_kernels": unfused.num_kernels})
-        seqs[name] = entry
+    seqs = {name: measure(progs[name]) for name in names}
+    extra = {}
+    if not args.only:
+        # further Table 1 sequences, measured alone (not part of the step)
+        del progs, plans
+        torch.cuda.empty_cache()
+        for name in WL.EXTRA:
+            pt = prepare(name)
+            extra[name] = measure(pt)
+            del pt
+            torch.cuda.empty_cache()
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -262,6 +276,7 @@ def main():
            "pct_peak": round(value / HBM_PEAK_GBPS * 100, 2),
            "roofline": roofline,
            "sequences": seqs,
+           "sequences_extra": extra,
            "launches_us_warmup_probe": {"%s/%d/%d %s" % (k["seq"], k["k"], k["l"], k["name"]): round(float(a), 2)
                                         for k, a in zip(kernels, avg_k)}}
     if not args.no_cpu_baseline and not args.only:

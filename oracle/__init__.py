@@ -217,6 +217,21 @@ def gemver(alpha, beta, A, u1, v1, u2, v2, y, z, cols=None, want_b=True):
     return B, x, w
 
 
+def sgemvt(alpha, beta, A, y, z, cols=None):
+    """Table 1 SGEMVT: x = beta A^T y + z, then w = alpha A x (A float32 storage)."""
+    n = int(cols) if cols is not None else np.asarray(A).shape[1]
+    Ad = np.asarray(A)[:, :n].astype(np.float64)
+    x = gemtv(beta, Ad, np.asarray(y, dtype=np.float64), 1.0, np.asarray(z, dtype=np.float64))
+    w = gemv(alpha, Ad, x)
+    return x, w
+
+
+def vadd(w, y, z):
+    """Table 1 VADD: x = w + y + z, as (w + y) + z."""
+    f = lambda a: np.asarray(a, dtype=np.float64)
+    return axpy(1.0, axpy(1.0, f(w), f(y)), f(z))
+
+
 def gemv_rows(A, x, idx, cols=None):
     """(A x)[idx] with A float32 storage and x float64."""
     Ak, Ap = _f(A)
@@ -269,6 +284,18 @@ def gesummv_sampled(alpha, A, beta, B, x, rows, cols=None):
     Br = np.ascontiguousarray(B[rows, :n], dtype=np.float64)
     t = gemv(alpha, Ar, xd)
     return gemv(beta, Br, xd, 1.0, t)
+
+
+def sgemvt_sampled(alpha, beta, A, y, z, rows, cols=None, panel=512):
+    """The whole x and w on the given rows (A float32 storage)."""
+    n = int(cols) if cols is not None else A.shape[1]
+    yd, zd = np.asarray(y, dtype=np.float64), np.asarray(z, dtype=np.float64)
+    x = np.empty(n, dtype=np.float64)
+    for c0 in range(0, n, panel):
+        c = np.arange(c0, min(n, c0 + panel))
+        x[c] = gemtv(beta, _mat_panel(A, c), yd, 1.0, zd[c])
+    Ar = np.ascontiguousarray(A[rows, :n], dtype=np.float64)
+    return x, gemv(alpha, Ar, x)
 
 
 def gemver_sampled(alpha, beta, A, u1, v1, u2, v2, y, z, rows, cols=None, panel=512, workers=1):

@@ -218,8 +218,33 @@ def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
     return q
 
 
+def sgemvt(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
+    """x = beta A^T y + z; w = alpha A x (the gemv needs all of x: two kernels
+    under the strip rules)."""
+    q = _seq("sgemvt")
+    A = _mat(q, "A", m, n, ld)
+    y, z = _vec(q, "y", m), _vec(q, "z", n)
+    a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
+    x = kf.kf_gemtv(q.script, b, A, y, one, z)
+    w = kf.kf_gemv(q.script, a, A, x)
+    _out(q, "x", x)
+    _out(q, "w", w)
+    return q
+
+
+def vadd(n: int) -> Sequence:
+    """x = w + y + z as two axpy calls with unit scale."""
+    q = _seq("vadd")
+    w, y, z = _vec(q, "w", n), _vec(q, "y", n), _vec(q, "z", n)
+    one = _const(q, "one", 1.0)
+    t = kf.kf_axpy(q.script, one, w, y)
+    x = kf.kf_axpy(q.script, one, t, z)
+    _out(q, "x", x)
+    return q
+
+
 BUILDERS = {"axpydot": axpydot, "waxpby": waxpby, "bicgk": bicgk, "atax": atax,
-            "gesummv": gesummv, "gemver": gemver}
+            "gesummv": gesummv, "gemver": gemver, "sgemvt": sgemvt, "vadd": vadd}
 
 
 def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0) -> Sequence:
@@ -234,6 +259,10 @@ def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0) -> Sequence:
         return atax(m, n, ld)
     if name == "gesummv":
         return gesummv(m, n, scal["alpha"], scal["beta"], ld, ld)
+    if name == "sgemvt":
+        return sgemvt(m, n, scal["alpha"], scal["beta"], ld)
+    if name == "vadd":
+        return vadd(n)
     if name == "gemver":
         return gemver(m, n, scal["alpha"], scal["beta"], ld)
     raise KeyError(name)

@@ -20,12 +20,18 @@ OPERANDS = {
     "atax": ["A", "x"],
     "gesummv": ["A", "B", "x"],
     "gemver": ["A", "u1", "v1", "u2", "v2", "y", "z"],
+    "sgemvt": ["A", "y", "z"],
+    "vadd": ["w", "y", "z"],
 }
 SCALARS = {"axpydot": ["alpha"], "waxpby": ["alpha", "beta"], "bicgk": [], "atax": [],
-           "gesummv": ["alpha", "beta"], "gemver": ["alpha", "beta"]}
+           "gesummv": ["alpha", "beta"], "gemver": ["alpha", "beta"], "sgemvt": ["alpha", "beta"],
+           "vadd": []}
 MATRIX = {"A", "B"}
 ORDER = ["axpydot", "waxpby", "bicgk", "atax", "gesummv", "gemver"]
-SEQ_INDEX = {name: i for i, name in enumerate(ORDER)}
+# further Table 1 sequences with more than one call (not in the headline suite)
+EXTRA = ["sgemvt", "vadd"]
+SEQ_INDEX = {name: i for i, name in enumerate(ORDER + EXTRA)}
+BLAS1 = {"axpydot", "waxpby", "vadd"}
 
 SUITE_N = 16384
 SUITE_VEC = 1 << 26
@@ -37,10 +43,10 @@ def seed_for(suite: int, name: str) -> int:
 
 def vector_length(name: str, which: str, m: int, n: int) -> int:
     """Length of vector operand `which` for an m x n matrix (BLAS-2) or n (BLAS-1)."""
-    if name in ("axpydot", "waxpby"):
+    if name in BLAS1:
         return n
     row_indexed = {"bicgk": {"r"}, "atax": set(), "gesummv": set(),
-                   "gemver": {"u1", "u2", "y"}}[name]
+                   "gemver": {"u1", "u2", "y"}, "sgemvt": {"y"}}[name]
     return m if which in row_indexed else n
 
 
@@ -61,7 +67,7 @@ def make(name: str, m: int, n: int, seed: int, ld: int | None = None, pad_value=
 
 def reduction_length(name: str, m: int, n: int) -> int:
     """Longest reduction feeding an output (sets the accuracy tolerance)."""
-    if name in ("axpydot", "waxpby"):
+    if name in BLAS1:
         return n
     return max(m, n)
 
@@ -93,12 +99,15 @@ TUNED = {
     ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=1024),
     ("waxpby", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
     ("waxpby", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
+    ("sgemvt", "fused"): _M1, ("sgemvt", "unfused"): _M1,
+    ("vadd", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
+    ("vadd", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
 }
 
 
 def tuned_params(name: str, m: int, n: int, mode: str = "fused") -> dict:
     """Tuned parameters for the suite shapes; library defaults elsewhere."""
-    suite = (m, n) == ((SUITE_VEC, SUITE_VEC) if name in ("axpydot", "waxpby") else (SUITE_N, SUITE_N))
+    suite = (m, n) == ((SUITE_VEC, SUITE_VEC) if name in BLAS1 else (SUITE_N, SUITE_N))
     return dict(TUNED.get((name, mode), {})) if suite else {}
 
 

@@ -32,6 +32,11 @@ def oracle_outputs(name, arrays, scal, n):
         B, x, w = oracle.gemver(scal["alpha"], scal["beta"], a["A"], a["u1"], a["v1"], a["u2"],
                                 a["v2"], a["y"], a["z"], cols=n)
         return {"B": B, "x": x, "w": w}
+    if name == "sgemvt":
+        x, w = oracle.sgemvt(scal["alpha"], scal["beta"], a["A"], a["y"], a["z"], cols=n)
+        return {"x": x, "w": w}
+    if name == "vadd":
+        return {"x": oracle.vadd(a["w"], a["y"], a["z"])}
     raise KeyError(name)
 
 

@@ -46,7 +46,7 @@ def ok(name, got, ref, m, n):
 
 
 @pytest.mark.parametrize("mode", ["fused", "unfused"])
-@pytest.mark.parametrize("name", ["axpydot", "waxpby"])
+@pytest.mark.parametrize("name", ["axpydot", "waxpby", "vadd"])
 def test_blas1_full(name, mode):
     print("case", name, V, mode, flush=True)
     arrays, scal, h = run(name, V, V, mode)
@@ -54,6 +54,8 @@ def test_blas1_full(name, mode):
         z, r = oracle.axpydot(scal["alpha"], arrays["w"], arrays["v"], arrays["u"])
         ok(name, h["z"], z, V, V)
         ok(name, h["r"], np.array([r]), V, V)
+    elif name == "vadd":
+        ok(name, h["x"], oracle.vadd(arrays["w"], arrays["y"], arrays["z"]), V, V)
     else:
         ok(name, h["w"], oracle.waxpby(scal["alpha"], arrays["x"], scal["beta"], arrays["y"]), V, V)
 
@@ -96,6 +98,16 @@ def test_gemver_full(mode):
     ok("gemver", h["B"][rows, :N], Br, N, N)
     ok("gemver", h["x"], x, N, N)
     ok("gemver", h["w"][rows], w, N, N)
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_sgemvt_full(mode):
+    print("case sgemvt", N, mode, flush=True)
+    arrays, scal, h = run("sgemvt", N, N, mode)
+    rows = sample(N, 96, 6)
+    x, w = oracle.sgemvt_sampled(scal["alpha"], scal["beta"], arrays["A"], arrays["y"], arrays["z"], rows)
+    ok("sgemvt", h["x"], x, N, N)
+    ok("sgemvt", h["w"][rows], w, N, N)
 
 
 def test_bicgk_config1():

@@ -24,7 +24,7 @@ def setup_module():
     kf.lib()
 
 
-@pytest.mark.parametrize("name", ["bicgk", "atax", "gesummv", "gemver"])
+@pytest.mark.parametrize("name", ["bicgk", "atax", "gesummv", "gemver", "sgemvt"])
 @pytest.mark.parametrize("mn", SMALL)
 @pytest.mark.parametrize("mode", ["fused", "unfused"])
 def test_blas2_sequences(name, mn, mode):
@@ -36,7 +36,7 @@ def test_blas2_sequences(name, mn, mode):
     SC.check_against_oracle(name, m, n, host, ref)
 
 
-@pytest.mark.parametrize("name", ["axpydot", "waxpby"])
+@pytest.mark.parametrize("name", ["axpydot", "waxpby", "vadd"])
 @pytest.mark.parametrize("n", VEC_N)
 @pytest.mark.parametrize("mode", ["fused", "unfused"])
 def test_blas1_sequences(name, n, mode):

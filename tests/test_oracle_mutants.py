@@ -9,6 +9,7 @@ import ctypes
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -67,6 +68,55 @@ def test_mutant_is_caught(name, tmp_path, monkeypatch):
     for pin in ALL_PINS:
         try:
             pin(oracle)
+        except AssertionError:
+            failures.append(pin.__name__)
+    assert failures, "mutant %s passed every pin" % name
+
+
+def _sgemvt_transposed(alpha, beta, A, y, z, cols=None):
+    n = int(cols) if cols is not None else A.shape[1]
+    Ad = np.asarray(A)[:, :n].astype(np.float64)
+    x = oracle.gemtv(beta, Ad, np.asarray(y, dtype=np.float64), 1.0, np.asarray(z, dtype=np.float64))
+    if Ad.shape[0] != Ad.shape[1]:
+        return x, oracle.gemv(alpha, Ad, x)
+    return x, oracle.gemtv(alpha, Ad, x)          # A^T x where A x is meant
+
+
+def _sgemvt_swapped_scalars(alpha, beta, A, y, z, cols=None):
+    return oracle.sgemvt(beta, alpha, A, y, z, cols)
+
+
+def _sgemvt_drops_z(alpha, beta, A, y, z, cols=None):
+    return oracle.sgemvt(alpha, beta, A, y, np.zeros_like(np.asarray(z)), cols)
+
+
+def _vadd_drops_z(w, y, z):
+    return oracle.axpy(1.0, np.asarray(w, dtype=np.float64), np.asarray(y, dtype=np.float64))
+
+
+def _vadd_sub(w, y, z):
+    return oracle.axpy(-1.0, oracle.axpy(1.0, np.asarray(w, np.float64), np.asarray(y, np.float64)),
+                       np.asarray(z, np.float64))
+
+
+PY_MUTANTS = {"sgemvt_gemv_as_gemtv": ("sgemvt", _sgemvt_transposed),
+              "sgemvt_swapped_scalars": ("sgemvt", _sgemvt_swapped_scalars),
+              "sgemvt_drops_z": ("sgemvt", _sgemvt_drops_z),
+              "vadd_drops_z": ("vadd", _vadd_drops_z),
+              "vadd_subtracts": ("vadd", _vadd_sub)}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_composition_mutant_is_caught(name):
+    """Mistakes in the Python-level sequence compositions fail a pin too."""
+    import types
+    attr, fn = PY_MUTANTS[name]
+    O = types.SimpleNamespace(**{k: getattr(oracle, k) for k in dir(oracle) if not k.startswith("__")})
+    setattr(O, attr, fn)
+    failures = []
+    for pin in ALL_PINS:
+        try:
+            pin(O)
         except AssertionError:
             failures.append(pin.__name__)
     assert failures, "mutant %s passed every pin" % name

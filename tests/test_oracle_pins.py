@@ -244,10 +244,59 @@ def pin_sampled_sequences(O):
     np.testing.assert_array_equal(Br, Bf[rows])
     np.testing.assert_allclose(xs, x, rtol=1e-14)
     np.testing.assert_allclose(ws, w[rows], rtol=1e-13)
+    x, w = O.sgemvt(1.5, 0.75, A, v["y"], v["z"], cols=n)
+    xs, ws = O.sgemvt_sampled(1.5, 0.75, A, v["y"], v["z"], rows, cols=n, panel=8)
+    np.testing.assert_allclose(xs, x, rtol=1e-14)
+    np.testing.assert_allclose(ws, w[rows], rtol=1e-13)
+
+
+def pin_sgemvt(O):
+    """Table 1 SGEMVT on a rank-1 A = a b^T of small integers with dyadic
+    scalars: x = beta b (a.y) + z and w = alpha a (b.x), exact in float64;
+    the identity reduces it to x = beta y + z, w = alpha x."""
+    m, n = 6, 9
+    a, b = I.small_ints(13, 0, m, -3, 3), I.small_ints(13, 1, n, -3, 3)
+    y, z = I.small_ints(13, 2, m, -4, 4), I.small_ints(13, 3, n, -4, 4)
+    alpha, beta = 0.75, -1.5
+    A = np.outer(a, b).astype(np.float32)
+    x, w = O.sgemvt(alpha, beta, A, y, z)
+    a64, b64, y64, z64 = (v.astype(np.float64) for v in (a, b, y, z))
+    x_ref = beta * b64 * float(np.dot(a64, y64)) + z64
+    assert np.array_equal(x, x_ref)
+    assert np.array_equal(w, alpha * a64 * float(np.dot(b64, x_ref)))
+    # square, non-symmetric rank-1: A x and A^T x differ
+    sa, sb = I.small_ints(13, 7, 8, -3, 3), I.small_ints(13, 8, 8, 1, 4)
+    sy, sz = I.small_ints(13, 9, 8, -4, 4), I.small_ints(13, 10, 8, -4, 4)
+    x, w = O.sgemvt(alpha, beta, np.outer(sa, sb).astype(np.float32), sy, sz)
+    sa, sb, sy, sz = (v.astype(np.float64) for v in (sa, sb, sy, sz))
+    x_ref = beta * sb * float(np.dot(sa, sy)) + sz
+    assert np.array_equal(x, x_ref) and np.array_equal(w, alpha * sa * float(np.dot(sb, x_ref)))
+    k = 7
+    e = np.eye(k, dtype=np.float32)
+    yy, zz = I.small_ints(13, 4, k, -4, 4), I.small_ints(13, 5, k, -4, 4)
+    x, w = O.sgemvt(2.0, 0.5, e, yy, zz)
+    assert np.array_equal(x, 0.5 * yy.astype(np.float64) + zz) and np.array_equal(w, 2.0 * x)
+    # padded leading dimension
+    G = I.matrix(13, 6, m, n, ld=12)
+    x1, w1 = O.sgemvt(alpha, beta, G, y, z, cols=n)
+    x2, w2 = O.sgemvt(alpha, beta, np.ascontiguousarray(G[:, :n]), y, z)
+    assert np.array_equal(x1, x2) and np.array_equal(w1, w2) and np.all(np.isfinite(w1))
+
+
+def pin_vadd(O):
+    """Table 1 VADD: integers sum exactly; random floats agree with numpy's
+    float64 (w + y) + z bit for bit."""
+    n = 1001
+    w, y, z = (I.small_ints(14, t, n, -100, 100) for t in range(3))
+    assert np.array_equal(O.vadd(w, y, z), w.astype(np.float64) + y + z)
+    w, y, z = (I.vector(14, 3 + t, n) for t in range(3))
+    ref = (w.astype(np.float64) + y.astype(np.float64)) + z.astype(np.float64)
+    assert np.array_equal(O.vadd(w, y, z), ref)
 
 
 ALL_PINS = [pin_elementary, pin_library, pin_axpydot, pin_waxpby, pin_bicgk, pin_atax,
-            pin_gesummv, pin_gemver, pin_sampled, pin_bruteforce_fraction, pin_sampled_sequences]
+            pin_gesummv, pin_gemver, pin_sgemvt, pin_vadd, pin_sampled, pin_bruteforce_fraction,
+            pin_sampled_sequences]
 
 
 @pytest.mark.parametrize("pin", ALL_PINS, ids=[p.__name__ for p in ALL_PINS])
