@@ -39,6 +39,11 @@ def parse():
                     help="only run the 1 GiB streaming copy (memory-counter calibration)")
     ap.add_argument("--tune", action="store_true",
                     help="grid-search the implementation parameters of every sequence and print them")
+    ap.add_argument("--batched", action="store_true",
+                    help="batched uneven sizes: 4096 BiCGK + 4096 GEMVER, n log-uniform on [32, 2048], "
+                         "one persistent launch vs a loop of per-instance launches")
+    ap.add_argument("--tune-batch", action="store_true",
+                    help="grid-search the rows per work item of every size bucket of the batched launch")
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision suite: BiCGK and GEMVER at n = 32768 with A in FP32, BF16, FP8-E4M3")
     return ap.parse_args()
@@ -116,6 +121,44 @@ def precision_suite(args, torch, kf, S, WL, dev):
                       "n": n, "results": res, "unit": "GB/s", "peak": HBM_PEAK_GBPS}), flush=True)
 
 
+def batched_suite(args, torch, kf, WL, dev):
+    """GB/s of the batched configuration: the persistent launch, the loop of
+    per-instance launches, and graph replays of both (one JSON line; not the
+    headline)."""
+    from paper_1305_1183_amd import batched as B
+    kinds, ns, al, be = B.make_instances(*WL.BATCH_COUNTS, seed=WL.BATCH_SEED)
+    t0 = time.time()
+    bt = B.Batch(kinds, ns, al, be, WL.batch_opts())
+    bt.fill_device(seed=WL.BATCH_SEED)
+    torch.cuda.synchronize()
+    log("batched inputs: %d instances, %.1f s" % (len(ns), time.time() - t0))
+    r, w = bt.bytes()
+    st = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(st):
+        for which, name in ((0, "persistent"), (1, "loop")):
+            us = kf.kf_batch_time(bt.h, which, False, st.cuda_stream, args.warmup, max(3, args.steps // 4))
+            kf.kf_batch_capture(bt.h, which, st.cuda_stream)
+            ug = kf.kf_batch_time(bt.h, which, True, st.cuda_stream, args.warmup, max(3, args.steps // 4))
+            res[name] = {"us": round(us, 1), "gbps": round((r + w) / us / 1e3, 1),
+                         "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+            res[name + "_graph"] = {"us": round(ug, 1), "gbps": round((r + w) / ug / 1e3, 1),
+                                    "pct_peak": round((r + w) / ug / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+            log("batched %s: %.1f us, graph %.1f us" % (name, us, ug))
+        err = kf.kf_batch_error(bt.h, st.cuda_stream)
+    if err:
+        raise RuntimeError("batched launch reported error bits %d" % err)
+    best_loop = min(res["loop"]["us"], res["loop_graph"]["us"])
+    print(json.dumps({"metric": "batched uneven sizes: GB/s and speedup of one persistent launch vs per-instance "
+                                "launches (not the headline)",
+                      "value": res["persistent_graph"]["gbps"], "unit": "GB/s",
+                      "speedup_vs_loop": round(res["loop"]["us"] / res["persistent"]["us"], 2),
+                      "speedup_vs_best_loop": round(best_loop / res["persistent_graph"]["us"], 2),
+                      "bytes": r + w, "results": res, "batch": json.loads(bt.describe()),
+                      "config": {"workload": "%d BiCGK + %d GEMVER, n log-uniform on [32, 2048], FP32 uniform[-1,1)"
+                                             % WL.BATCH_COUNTS}}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -147,6 +190,20 @@ def main():
     n, vec = WL.SUITE_N, WL.SUITE_VEC
     if args.precision:
         precision_suite(args, torch, kf, S, WL, dev)
+        return
+    if args.batched:
+        batched_suite(args, torch, kf, WL, dev)
+        return
+    if args.tune_batch:
+        from paper_1305_1183_amd import batched as B
+        table = {0: [0] * 6, 1: [0] * 6}
+        for kind in (0, 1):
+            for bucket in range(6):
+                best, res = B.autotune(kind, bucket, log=log)
+                table[kind][bucket] = best
+                print(json.dumps({"kind": kind, "bucket": bucket, "n": B.bucket_median(bucket), "best_rows": best,
+                                  "candidates": [[r_, round(u, 1), round(g, 1)] for r_, u, g in res]}), flush=True)
+        print(json.dumps({"batch_tuned": table}), flush=True)
         return
     if args.tune:
         from paper_1305_1183_amd import autotune

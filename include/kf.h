@@ -357,12 +357,100 @@ kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float*
 kf_status kf_jit_release(void);
 kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
 
+/* ---- batched uneven sizes: one persistent launch --------------------------
+ * Many independent BiCGK (q = A p, s = A^T r; Table 1) and GEMVER
+ * (B = A + u1 v1^T + u2 v2^T, x = beta B^T y + z, w = alpha B x; Table 1)
+ * instances, each square with 1 <= n <= 2048, run as one launch of a fixed
+ * grid of workgroups that take work items from a queue: a small instance is
+ * one item (for GEMVER the workgroup completes x and then computes w, so the
+ * global barrier between the two kernels of the fused plan becomes a
+ * workgroup barrier); a larger one is cut into row blocks whose column
+ * partials are added in block order by the last block to finish. This is the
+ * persistent-threads form of fusion that Section 5 leaves open.
+ *
+ * Layout: the library places every operand of every instance in one float
+ * arena that the caller allocates (kf_batch_arena_elems floats, 256-byte
+ * aligned) and fills at the offsets kf_batch_offset reports. Matrices are row
+ * major with row pitch ld = round_up(n, 4); padding columns are never read as
+ * data nor written. Operand ids: 0 = A, 1 = B (GEMVER output), then vectors
+ * 2 + slot, BiCGK slots p, r, q, s and GEMVER slots u1, v1, u2, v2, y, z,
+ * x, w (inputs first, then outputs; each n floats).
+ *
+ * Tile shape: instances fall into six size buckets (n <= 64, 128, 256, 512,
+ * 1024, 2048); opts->rows[kind][bucket] is the number of rows per work item
+ * (a multiple of the bucket's rows per step: 64, 32, 16, 16, 8, 4), an
+ * instance with n <= rows is one item. 0 takes the library default. The
+ * project's autotuner fills these per bucket. opts->grid is the number of
+ * persistent workgroups (0: as many as are resident on the device);
+ * opts->spin_limit bounds the wait of a dependent item (0: default, about a
+ * second); a wait that runs out sets error bit 1 (kf_batch_error) and the
+ * item is skipped.
+ *
+ * Workspace: kf_batch_workspace_bytes bytes, 256-byte aligned, owned by the
+ * caller; kf_batch_bind clears its counters (on `stream`) and the launch
+ * leaves them cleared, so runs and graph replays need no clearing. Two runs
+ * of one batch must not overlap in time. */
+typedef struct kf_batch kf_batch;
+enum { KF_BATCH_BICGK = 0, KF_BATCH_GEMVER = 1 };
+#define KF_BATCH_BUCKETS 6
+typedef struct {
+    int32_t rows[2][KF_BATCH_BUCKETS];
+    int32_t grid;
+    uint32_t spin_limit;
+} kf_batch_opts;
+
+/* kind[i] in {KF_BATCH_BICGK, KF_BATCH_GEMVER}, n[i] in [1, 2048];
+ * alpha/beta per instance (GEMVER; may be NULL for 1.0). Host only: no GPU
+ * call. Errors: KF_ERR_ARG, KF_ERR_UNSUPPORTED (n out of range). */
+kf_status kf_batch_create(int64_t count, const int32_t* kind, const int64_t* n, const float* alpha,
+                          const float* beta, const kf_batch_opts* opts, kf_batch** out);
+void kf_batch_destroy(kf_batch* b);
+kf_status kf_batch_arena_elems(const kf_batch* b, int64_t* elems);
+kf_status kf_batch_workspace_bytes(const kf_batch* b, size_t* bytes);
+/* Arena offset (floats) of one operand of instance i; *ld gets the row pitch
+ * of a matrix or n of a vector. KF_ERR_ARG for an operand the kind lacks. */
+kf_status kf_batch_offset(const kf_batch* b, int64_t i, int32_t operand, int64_t* offset, int64_t* ld);
+/* Algorithmic bytes of the fused plans of all instances (BiCGK: A, p, r read,
+ * q, s written; GEMVER: A, six vectors, then B and x read; B, x, w written). */
+kf_status kf_batch_bytes(const kf_batch* b, int64_t* read, int64_t* written);
+/* JSON summary (instances per bucket, items, split instances, rows, grid). */
+kf_status kf_batch_describe(const kf_batch* b, char* buf, size_t len, size_t* needed);
+/* Work items, which = 0: queue order of the persistent launch, 1: instance
+ * order of the launch loop; arrays of cap entries, *count gets the total. */
+kf_status kf_batch_items(const kf_batch* b, int32_t which, int32_t* inst, int32_t* phase, int32_t* blk,
+                         int64_t cap, int64_t* count);
+/* Device pointers; uploads the item tables (first call) and clears the
+ * counters on `stream`. Errors: KF_ERR_ALIGN, KF_ERR_ALIAS, KF_ERR_HIP. */
+kf_status kf_batch_bind(kf_batch* b, float* arena, void* workspace, void* stream);
+/* which = 0: the persistent launch; 1: the baseline loop, one launch per
+ * instance (and one more for the w rows of a split GEMVER instance). */
+kf_status kf_batch_run(kf_batch* b, int32_t which, void* stream);
+/* Record kf_batch_run(which) on `stream` (not the null stream) into a graph
+ * kept in the batch; kf_batch_graph_launch replays it. kf_batch_bind drops
+ * the graphs. */
+kf_status kf_batch_capture(kf_batch* b, int32_t which, void* stream);
+kf_status kf_batch_graph_launch(kf_batch* b, int32_t which, void* stream);
+/* Median over reps of HIP events around one run (graph != 0: the replay). */
+kf_status kf_batch_time(kf_batch* b, int32_t which, int32_t graph, void* stream, int32_t warmup, int32_t reps,
+                        float* median_us);
+/* Synchronises `stream` and returns the error bits (1: a dependent item's
+ * wait ran out). Bits stay set until the next kf_batch_bind. */
+kf_status kf_batch_error(kf_batch* b, void* stream, uint32_t* bits);
+
 /* ---- measurement helper -------------------------------------------------- */
 /* dst[0..bytes) = src[0..bytes) with a plain streaming kernel (128-bit
  * non-temporal loads and stores) on `stream`; bytes and both pointers must be
  * multiples of 16. Used to calibrate memory-traffic counters against a copy of
  * known size. */
 kf_status kf_util_copy(void* dst, const void* src, size_t bytes, void* stream);
+/* Seeded synthetic inputs on the device: dst[i * ld + j] for i < rows,
+ * j < ld is, for j < cols, the SplitMix64 output number i * cols + j + 1 of
+ * the stream that starts at `key`, mapped to (h >> 40) 2^-23 - 1 (uniform on
+ * [-1, 1), exact in float32), and `pad` for j >= cols. The same values as the
+ * project's host-side generator for the same key, so large inputs need not
+ * cross PCIe. Asynchronous on `stream`. */
+kf_status kf_util_fill_uniform(float* dst, int64_t rows, int64_t cols, int64_t ld, uint64_t key, float pad,
+                               void* stream);
 
 #ifdef __cplusplus
 }

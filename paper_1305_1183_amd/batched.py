@@ -1,0 +1,183 @@
+"""Batched uneven-size BiCGK / GEMVER instances run as one persistent launch.
+
+`make_instances` draws the instance list (kind, n log-uniform, scalars) from a
+seed; `Batch` owns the library batch, the device arena holding every
+operand, and the workspace; inputs are generated on the host per instance
+from counter-based streams (so any instance can be regenerated alone) and
+copied to the device in one transfer.
+"""
+from __future__ import annotations
+
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import kf
+
+BICGK, GEMVER = kf.KF_BATCH_BICGK, kf.KF_BATCH_GEMVER
+INPUTS = {BICGK: ["p", "r"], GEMVER: ["u1", "v1", "u2", "v2", "y", "z"]}
+OUTPUTS = {BICGK: ["q", "s"], GEMVER: ["x", "w"]}
+SLOTS = {BICGK: ["p", "r", "q", "s"], GEMVER: ["u1", "v1", "u2", "v2", "y", "z", "x", "w"]}
+
+
+def make_instances(n_bicgk: int, n_gemver: int, seed: int, lo: int = 32, hi: int = 2048):
+    """Kinds (BiCGK first), sizes log-uniform on [lo, hi], GEMVER scalars
+    uniform on [0.5, 2]; deterministic in seed."""
+    kinds = np.array([BICGK] * n_bicgk + [GEMVER] * n_gemver, dtype=np.int32)
+    ns = I.loguniform_int(seed, 0, len(kinds), lo, hi)
+    alpha = np.array([I.scalar_uniform(seed, 1000 + 2 * i) for i in range(len(kinds))], dtype=np.float32)
+    beta = np.array([I.scalar_uniform(seed, 1001 + 2 * i) for i in range(len(kinds))], dtype=np.float32)
+    alpha[kinds == BICGK] = 1.0
+    beta[kinds == BICGK] = 1.0
+    return kinds, ns, alpha, beta
+
+
+def instance_inputs(seed: int, i: int, kind: int, n: int):
+    """Operands of instance i: A (n x round_up(n, 4), NaN padding) and the
+    input vectors, from the streams (seed * 2^20 + i, tensor id)."""
+    s = int(seed) * (1 << 20) + int(i)
+    out = {"A": I.matrix(s, 0, n, n, ld=I.padded_ld(n))}
+    for t, name in enumerate(INPUTS[kind]):
+        out[name] = I.vector(s, 1 + t, n)
+    return out
+
+
+class Batch:
+    def __init__(self, kinds, ns, alpha=None, beta=None, opts=None, device="cuda"):
+        self.kinds = np.asarray(kinds, dtype=np.int32)
+        self.ns = np.asarray(ns, dtype=np.int64)
+        self.alpha = None if alpha is None else np.asarray(alpha, dtype=np.float32)
+        self.beta = None if beta is None else np.asarray(beta, dtype=np.float32)
+        self.h = kf.kf_batch_create(self.kinds, self.ns, self.alpha, self.beta, opts)
+        self.elems = kf.kf_batch_arena_elems(self.h)
+        self.ws_bytes = kf.kf_batch_workspace_bytes(self.h)
+        self.device = device
+        self.arena = None
+        self.ws = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and kf is not None:
+            kf.kf_batch_destroy(h)
+            self.h = None
+
+    def offset(self, i: int, name: str):
+        kind = int(self.kinds[i])
+        op = 0 if name == "A" else 1 if name == "B" else 2 + SLOTS[kind].index(name)
+        return kf.kf_batch_offset(self.h, i, op)
+
+    def host_arena(self, seed: int, threads: int = 0) -> np.ndarray:
+        """Host copy of the arena with every input filled (outputs NaN)."""
+        host = np.full(self.elems, np.nan, dtype=np.float32)
+
+        def fill(i):
+            n = int(self.ns[i])
+            vals = instance_inputs(seed, i, int(self.kinds[i]), n)
+            off, ld = self.offset(i, "A")
+            host[off:off + n * ld] = vals["A"].ravel()
+            for name in INPUTS[int(self.kinds[i])]:
+                o, _ = self.offset(i, name)
+                host[o:o + n] = vals[name]
+        with ThreadPoolExecutor(threads or I._threads()) as ex:
+            list(ex.map(fill, range(len(self.kinds))))
+        return host
+
+    def upload(self, host: np.ndarray) -> None:
+        """Device arena from a host copy, then bind."""
+        self.arena = torch.from_numpy(host).to(self.device)
+        self._bind()
+
+    def fill_device(self, seed: int) -> None:
+        """Device arena with the same inputs as host_arena(seed), generated on
+        the device (outputs are left unset), then bind."""
+        self.arena = torch.empty(max(1, self.elems), dtype=torch.float32, device=self.device)
+        st = self.stream()
+        base = self.arena.data_ptr()
+        for i in range(len(self.kinds)):
+            n, kind = int(self.ns[i]), int(self.kinds[i])
+            sd = int(seed) * (1 << 20) + i
+            off, ld = self.offset(i, "A")
+            kf.kf_util_fill_uniform(base + 4 * off, n, n, ld, I.stream_key(sd, 0), float("nan"), st)
+            for t, name in enumerate(INPUTS[kind]):
+                o, _ = self.offset(i, name)
+                kf.kf_util_fill_uniform(base + 4 * o, 1, n, n, I.stream_key(sd, 1 + t), 0.0, st)
+        self._bind()
+
+    def _bind(self) -> None:
+        self.ws = torch.empty(max(256, self.ws_bytes), dtype=torch.uint8, device=self.device)
+        kf.kf_batch_bind(self.h, self.arena.data_ptr(), self.ws.data_ptr(), self.stream())
+
+    def stream(self):
+        return torch.cuda.current_stream().cuda_stream
+
+    def run(self, which: int = 0) -> None:
+        kf.kf_batch_run(self.h, which, self.stream())
+
+    def error(self) -> int:
+        return kf.kf_batch_error(self.h, self.stream())
+
+    def outputs(self, host: np.ndarray, i: int) -> dict:
+        """Outputs of instance i from a host copy of the arena."""
+        n = int(self.ns[i])
+        kind = int(self.kinds[i])
+        out = {}
+        for name in OUTPUTS[kind]:
+            o, _ = self.offset(i, name)
+            out[name] = host[o:o + n]
+        if kind == GEMVER:
+            o, ld = self.offset(i, "B")
+            out["B"] = host[o:o + n * ld].reshape(n, ld)
+        return out
+
+    def bytes(self):
+        return kf.kf_batch_bytes(self.h)
+
+    def describe(self) -> str:
+        return kf.kf_batch_describe(self.h)
+
+
+BUCKET_RANGE = [(1, 64), (65, 128), (129, 256), (257, 512), (513, 1024), (1025, 2048)]
+
+
+def bucket_median(bucket: int, lo: int = 32, hi: int = 2048) -> int:
+    """Median size of a log-uniform draw on [lo, hi] that falls in the bucket."""
+    a, b = BUCKET_RANGE[bucket]
+    a, b = max(a, lo), min(b, hi)
+    return int(round(np.sqrt(a * b)))
+
+
+def row_candidates(bucket: int, n: int) -> list:
+    """Rows per item: the bucket's rows per step times powers of two, up to one
+    item per instance."""
+    r = kf.BATCH_ROWS_PER_STEP[bucket]
+    out = []
+    while True:
+        out.append(r)
+        if r >= n:
+            break
+        r *= 2
+    return out
+
+
+def autotune(kind: int, bucket: int, count: int = 683, seed: int = 1, reps: int = 5, log=None):
+    """Grid search of the rows per item for one kind and size bucket on `count`
+    instances of the bucket's median size; returns (best rows, [(rows, us, GB/s)])."""
+    n = bucket_median(bucket)
+    res = []
+    for rows in row_candidates(bucket, n):
+        rt = {0: [0] * 6, 1: [0] * 6}
+        rt[kind][bucket] = rows
+        bt = Batch(np.full(count, kind, np.int32), np.full(count, n), np.full(count, 1.25, np.float32),
+                   np.full(count, 0.75, np.float32), kf.batch_opts(rows=rt))
+        bt.fill_device(seed)
+        us = kf.kf_batch_time(bt.h, 0, False, bt.stream(), 2, reps)
+        r, w = bt.bytes()
+        res.append((rows, us, (r + w) / us / 1e3))
+        if log:
+            log("tune kind %d bucket %d n %d rows %d: %.1f us %.1f GB/s" % (kind, bucket, n, rows, us, res[-1][2]))
+        del bt
+        torch.cuda.empty_cache()
+    best = min(res, key=lambda t: t[1])[0]
+    return best, res

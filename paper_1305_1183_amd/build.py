@@ -26,8 +26,8 @@ COMMON = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-HOST_SOURCES = ["api.cpp", "plan.cpp", "codegen.cpp", "jit.cpp", "search.cpp", "costmodel.cpp"]
-DEVICE_SOURCES = ["device/kf_util.hip", "device/kf_mlp.hip"]
+HOST_SOURCES = ["api.cpp", "plan.cpp", "codegen.cpp", "jit.cpp", "search.cpp", "costmodel.cpp", "batch.cpp"]
+DEVICE_SOURCES = ["device/kf_util.hip", "device/kf_mlp.hip", "device/kf_batch.hip"]
 
 
 def _embed_blocks() -> None:

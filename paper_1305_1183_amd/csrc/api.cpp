@@ -18,6 +18,8 @@ kf_status set_error(kf_status st, const std::string& msg) {
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t launch_fill_uniform(float* dst, long rows, long cols, long ld, unsigned long long key, float pad,
+                               hipStream_t st);
 
 // Loaded kernels, by generated name (a hash of the kernel text). Modules stay
 // loaded for the life of the process so plans can share kernels.
@@ -814,6 +816,14 @@ kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled) {
     std::lock_guard<std::mutex> lock(reg.mu);
     if (modules) *modules = (int64_t)reg.modules.size();
     if (kernels_compiled) *kernels_compiled = (int64_t)reg.compiled.size();
+    return KF_OK;
+}
+
+kf_status kf_util_fill_uniform(float* dst, int64_t rows, int64_t cols, int64_t ld, uint64_t key, float pad,
+                               void* stream) {
+    if (!dst || rows < 0 || cols < 0 || ld < cols) return set_error(KF_ERR_ARG, "bad argument");
+    hipError_t e = launch_fill_uniform(dst, rows, cols, ld, key, pad, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(KF_ERR_HIP, hipGetErrorString(e));
     return KF_OK;
 }
 

@@ -1,0 +1,475 @@
+// kf_batch.hip -- one persistent launch over many uneven-size BiCGK and GEMVER
+// instances.
+//
+// The paper fuses the calls of one script into kernels and notes that the
+// only way to keep data on chip across a global reduction would be persistent
+// threads (Section 5, discussion of ATAX and SGEMVT). Here a fixed grid of
+// workgroups repeatedly takes the next item from a queue in the workspace and
+// processes it with the fused tiles of Algorithm 3 (BiCGK: A read once for
+// A p and A^T r) and of the GEMVER plan {ger, ger, gemtv}{gemv}:
+//
+//   * a whole small instance is one item; for GEMVER the workgroup completes
+//     x = beta B^T y + z itself and then runs w = alpha B x, so the global
+//     barrier between the two kernels of the plan becomes a workgroup barrier;
+//   * a larger instance is cut into row blocks; every block writes a column
+//     partial, the last block to arrive (a per-instance counter) adds the
+//     partials in block order and, for GEMVER, publishes x with a flag;
+//   * the K2 row blocks of split GEMVER instances come after every phase-1
+//     item in the queue. A K2 block waits for its flag, which can only be
+//     held back by phase-1 items already taken by running workgroups, so the
+//     wait always ends; it is bounded all the same and reports an error bit.
+//
+// Every counter is returned to zero by the item or workgroup that uses it
+// last, so the launch can be replayed (e.g. from a graph) without clearing.
+//
+// Tile shape by size bucket: TPR = 2^LTPR lanes share a row (K float4 chunks
+// each), 256 / TPR rows are in flight per workgroup step, G = 2^LG steps are
+// loaded before their row sums are reduced.
+#include <hip/hip_runtime.h>
+
+#include "device/kf_blocks.h"
+#include "kf_batch_defs.h"
+
+namespace {
+
+// Row sums of G = 2^LG partials per lane over groups of TPR = 2^LTPR lanes:
+// a transposing exchange over the top LG bits of the group, then a butterfly
+// over the rest. Lane cl of a group returns the sum of row cl >> (LTPR - LG).
+template <int LTPR, int LG>
+__device__ __forceinline__ float kfb_rows_reduce(float* v) {
+    constexpr int TPR = 1 << LTPR;
+    constexpr int G = 1 << LG;
+    const int lane = __lane_id();
+#pragma unroll
+    for (int t = 0; t < LG; ++t) {
+        const int half = G >> (t + 1);
+        const int mask = (TPR >> 1) >> t;
+        const bool hi = (lane & mask) != 0;
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            const float send = hi ? v[j] : v[j + half];
+            const float keep = hi ? v[j + half] : v[j];
+            v[j] = keep + kf_xor(send, mask);
+        }
+    }
+    float s = v[0];
+#pragma unroll
+    for (int mask = (TPR >> 1) >> LG; mask >= 1; mask >>= 1) s += kf_xor(s, mask);
+    return s;
+}
+
+__device__ __forceinline__ kf_f4 kfb_xor4(kf_f4 v, int m) {
+    kf_f4 r;
+    r.x = kf_xor(v.x, m); r.y = kf_xor(v.y, m); r.z = kf_xor(v.z, m); r.w = kf_xor(v.w, m);
+    return r;
+}
+
+// Column sums of acc[k] over the 256 / TPR row-lanes of the workgroup, in a
+// fixed order (butterfly inside the wave, then waves 0..3). emit(c, v) runs in
+// threads tid < TPR with chunk c = tid + k TPR (columns 4c .. 4c + 3).
+template <int LTPR, int K, typename Emit>
+__device__ __forceinline__ void kfb_colsum(kf_f4* acc, kf_f4* red, Emit emit) {
+    constexpr int TPR = 1 << LTPR;
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int m = TPR; m < 64; m <<= 1) acc[k] += kfb_xor4(acc[k], m);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        __syncthreads();
+        if (lane < TPR) red[wave * TPR + lane] = acc[k];
+        __syncthreads();
+        if (threadIdx.x < TPR) {
+            const int t = threadIdx.x;
+            kf_f4 s = red[t];
+            s += red[TPR + t];
+            s += red[2 * TPR + t];
+            s += red[3 * TPR + t];
+            emit(t + k * TPR, s);
+        }
+    }
+}
+
+// Arrival at a per-instance counter. Returns true in every thread of the
+// workgroup that arrives last; that workgroup then sees the stores every
+// earlier arrival made before arriving, and the counter is back at zero.
+__device__ __forceinline__ bool kfb_arrive(unsigned* counter, unsigned count, int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned old = atomicAdd(counter, 1u);
+        const int last = old == count - 1;
+        if (last) {
+            __threadfence();
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        *s_flag = last;
+    }
+    __syncthreads();
+    const bool last = *s_flag != 0;
+    if (last) __threadfence();
+    return last;
+}
+
+// Chunk k of a thread covers columns col .. col + 3, col = 4 (cl + k TPR).
+// Per chunk the thread keeps the load column clamped into the row (cc) and
+// the number of its columns below n (nv, 0 .. 4), both 32-bit.
+struct kfb_cols {
+    int cc, nv;
+};
+__device__ __forceinline__ kfb_cols kfb_col(int col, int n, int ld) {
+    kfb_cols c;
+    c.cc = col < ld - 4 ? col : ld - 4;
+    const int v = n - col;
+    c.nv = v < 0 ? 0 : (v > 4 ? 4 : v);
+    return c;
+}
+// Row `row` of a matrix block at one chunk, without branches: the address is
+// clamped into the block (row r1 - 1, the row's last chunk) and entries of
+// rows >= r1 or columns >= n are replaced by zero with a select (padding may
+// hold NaN). Clamped loads fall on lines that other lanes fetch anyway.
+__device__ __forceinline__ kf_f4 kfb_ldm(const float* M, long ld, int row, int r1, kfb_cols c) {
+    const long rc = row < r1 ? row : r1 - 1;
+    kf_f4 v = kf_ld4_nt(M + rc * ld + c.cc);
+    const int lim = row < r1 ? c.nv : 0;
+    v.x = lim > 0 ? v.x : 0.f;
+    v.y = lim > 1 ? v.y : 0.f;
+    v.z = lim > 2 ? v.z : 0.f;
+    v.w = lim > 3 ? v.w : 0.f;
+    return v;
+}
+// Vector entries at one chunk (the vector holds exactly n floats; entries
+// at index >= n read as zero). 32-bit index arithmetic throughout.
+__device__ __forceinline__ kf_f4 kfb_ldv(const float* v, int col, int n) {
+    if (col + 4 <= n) return kf_ld4(v + col);
+    kf_f4 r = kf_zero4();
+    if (col + 0 < n) r.x = v[col + 0];
+    if (col + 1 < n) r.y = v[col + 1];
+    if (col + 2 < n) r.z = v[col + 2];
+    return r;
+}
+__device__ __forceinline__ void kfb_stv(float* v, int col, int n, kf_f4 x) {
+    if (col + 4 <= n) { kf_st4(v + col, x); return; }
+    if (col + 0 < n) v[col + 0] = x.x;
+    if (col + 1 < n) v[col + 1] = x.y;
+    if (col + 2 < n) v[col + 2] = x.z;
+}
+__device__ __forceinline__ void kfb_stm(float* row, int col, int n, kf_f4 x) {
+    if (col + 4 <= n) { kf_st4_nt(row + col, x); return; }
+    if (col + 0 < n) row[col + 0] = x.x;
+    if (col + 1 < n) row[col + 1] = x.y;
+    if (col + 2 < n) row[col + 2] = x.z;
+}
+
+// threadIdx.x as an opaque value: per-thread column offsets are then
+// recomputed for every item instead of being hoisted out of the persistent
+// loop, where they would stay live across all buckets.
+__device__ __forceinline__ int kfb_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+
+struct Shared {
+    kf_f4 red[KFB_THREADS];
+    kf_f4 xs[KFB_MAX_N / 4];
+    int flag;
+    int item;
+};
+
+// w rows r0 .. r1 - 1 of alpha B x, x given per thread at its columns.
+template <int LTPR, int K, int LG>
+__device__ __forceinline__ void kfb_gemv_rows(const kfb_inst& I, const float* __restrict__ B,
+                                              float* __restrict__ w, int r0, int r1, const kf_f4* xv) {
+    constexpr int TPR = 1 << LTPR, G = 1 << LG, RL = KFB_THREADS / TPR, RI = RL * G;
+    const int tid = kfb_tid(), cl = tid & (TPR - 1), rl = tid >> LTPR;
+    const int n = I.n;
+    const long ld = I.ld;
+    kfb_cols cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
+#pragma unroll 1
+    for (int i0 = r0; i0 < r1; i0 += RI) {
+        kf_f4 b[G][K];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int row = i0 + g * RL + rl;
+#pragma unroll
+            for (int k = 0; k < K; ++k) b[g][k] = kfb_ldm(B, ld, row, r1, cs[k]);
+        }
+        float wp[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            wp[g] = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) wp[g] = kf_dot4(b[g][k], xv[k], wp[g]);
+        }
+        const float ws = kfb_rows_reduce<LTPR, LG>(wp);
+        const int g = cl >> (LTPR - LG);
+        const int row = i0 + g * RL + rl;
+        if ((cl & ((TPR >> LG) - 1)) == 0 && row < r1) w[row] = I.alpha * ws;
+    }
+}
+
+template <int LTPR, int K, int LG>
+__device__ void kfb_bicgk(const kfb_inst& I, int blk, float* __restrict__ arena, float* __restrict__ ws,
+                          unsigned* sync, Shared& sh) {
+    constexpr int TPR = 1 << LTPR, G = 1 << LG, RL = KFB_THREADS / TPR, RI = RL * G;
+    const int tid = kfb_tid(), cl = tid & (TPR - 1), rl = tid >> LTPR;
+    const int n = I.n;
+    const long ld = I.ld;
+    const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
+    const float* __restrict__ A = arena + I.a;
+    const float* __restrict__ p = arena + I.v[0];
+    const float* __restrict__ r = arena + I.v[1];
+    float* __restrict__ q = arena + I.v[2];
+    float* __restrict__ s = arena + I.v[3];
+    kf_f4 pv[K], acc[K];
+    kfb_cols cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
+        pv[k] = kfb_ldv(p, 4 * (cl + k * TPR), n);
+        acc[k] = kf_zero4();
+    }
+#pragma unroll 1
+    for (int i0 = r0; i0 < r1; i0 += RI) {
+        kf_f4 a[G][K];
+        float rr[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int row = i0 + g * RL + rl;
+            const bool ok = row < r1;
+            rr[g] = r[ok ? row : r1 - 1];
+            rr[g] = ok ? rr[g] : 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) a[g][k] = kfb_ldm(A, ld, row, r1, cs[k]);
+        }
+        float qp[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            qp[g] = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) qp[g] = kf_dot4(a[g][k], pv[k], qp[g]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] = kf_fma4s(rr[g], a[g][k], acc[k]);
+        }
+        const float qs = kfb_rows_reduce<LTPR, LG>(qp);
+        const int g = cl >> (LTPR - LG);
+        const int row = i0 + g * RL + rl;
+        if ((cl & ((TPR >> LG) - 1)) == 0 && row < r1) q[row] = qs;
+    }
+    if (I.nblk == 1) {
+        kfb_colsum<LTPR, K>(acc, sh.red, [&](int c, kf_f4 v) { kfb_stv(s, 4 * c, n, v); });
+        return;
+    }
+    float* part = ws + I.ws + (long)blk * ld;
+    kfb_colsum<LTPR, K>(acc, sh.red, [&](int c, kf_f4 v) {
+        if (4 * c < ld) kf_st4(part + 4 * c, v);
+    });
+    unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
+    if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
+        for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
+            kf_f4 t = kf_zero4();
+            for (int b = 0; b < I.nblk; ++b) t += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
+            kfb_stv(s, 4 * c, n, t);
+        }
+    }
+}
+
+template <int LTPR, int K, int LG>
+__device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ arena, float* __restrict__ ws,
+                              unsigned* sync, Shared& sh) {
+    constexpr int TPR = 1 << LTPR, G = 1 << LG, RL = KFB_THREADS / TPR, RI = RL * G;
+    const int tid = kfb_tid(), cl = tid & (TPR - 1), rl = tid >> LTPR;
+    const int n = I.n;
+    const long ld = I.ld;
+    const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
+    const float* __restrict__ A = arena + I.a;
+    float* __restrict__ B = arena + I.b;
+    const float* __restrict__ u1 = arena + I.v[0];
+    const float* __restrict__ v1 = arena + I.v[1];
+    const float* __restrict__ u2 = arena + I.v[2];
+    const float* __restrict__ v2 = arena + I.v[3];
+    const float* __restrict__ y = arena + I.v[4];
+    const float* __restrict__ z = arena + I.v[5];
+    float* __restrict__ x = arena + I.v[6];
+    float* __restrict__ w = arena + I.v[7];
+    kf_f4 v1c[K], v2c[K], acc[K];
+    kfb_cols cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
+        v1c[k] = kfb_ldv(v1, 4 * (cl + k * TPR), n);
+        v2c[k] = kfb_ldv(v2, 4 * (cl + k * TPR), n);
+        acc[k] = kf_zero4();
+    }
+#pragma unroll 1
+    for (int i0 = r0; i0 < r1; i0 += RI) {
+        kf_f4 a[G][K];
+        float u1r[G], u2r[G], yr[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int row = i0 + g * RL + rl;
+            const bool ok = row < r1;
+            const int rc = ok ? row : r1 - 1;
+            u1r[g] = ok ? u1[rc] : 0.f;
+            u2r[g] = ok ? u2[rc] : 0.f;
+            yr[g] = ok ? y[rc] : 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) a[g][k] = kfb_ldm(A, ld, row, r1, cs[k]);
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int row = i0 + g * RL + rl;
+            float* brow = B + (long)row * ld;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                kf_f4 b = kf_fma4s(u1r[g], v1c[k], a[g][k]);
+                b = kf_fma4s(u2r[g], v2c[k], b);
+                if (row < r1) kfb_stm(brow, 4 * (cl + k * TPR), n, b);
+                acc[k] = kf_fma4s(yr[g], b, acc[k]);
+            }
+        }
+    }
+    if (I.nblk == 1) {
+        // x is complete inside this workgroup: finish it, then run the gemv.
+        kfb_colsum<LTPR, K>(acc, sh.red, [&](int c, kf_f4 v) {
+            const kf_f4 xc = kf_fma4s(I.beta, v, kfb_ldv(z, 4 * c, n));
+            kfb_stv(x, 4 * c, n, xc);
+            sh.xs[c] = xc;
+        });
+        __syncthreads();
+        kf_f4 xv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) xv[k] = sh.xs[cl + k * TPR];
+        kfb_gemv_rows<LTPR, K, LG>(I, B, w, 0, n, xv);
+        return;
+    }
+    float* part = ws + I.ws + (long)blk * ld;
+    kfb_colsum<LTPR, K>(acc, sh.red, [&](int c, kf_f4 v) {
+        if (4 * c < ld) kf_st4(part + 4 * c, v);
+    });
+    unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
+    if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
+        for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
+            kf_f4 t = kf_zero4();
+            for (int b = 0; b < I.nblk; ++b) t += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
+            kfb_stv(x, 4 * c, n, kf_fma4s(I.beta, t, kfb_ldv(z, 4 * c, n)));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            __hip_atomic_store(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <int LTPR, int K, int LG>
+__device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ arena, unsigned* sync,
+                              unsigned spin_limit, Shared& sh) {
+    constexpr int TPR = 1 << LTPR;
+    const int cl = kfb_tid() & (TPR - 1);
+    const int n = I.n;
+    unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            if (++spins > spin_limit) {
+                atomicOr(sync + KFB_SYNC_ERROR, KFB_ERR_SPIN);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        __threadfence();
+        sh.flag = ok;
+    }
+    __syncthreads();
+    const bool ready = sh.flag != 0;
+    __syncthreads();
+    if (!ready) return;
+    const float* __restrict__ B = arena + I.b;
+    const float* __restrict__ x = arena + I.v[6];
+    float* __restrict__ w = arena + I.v[7];
+    kf_f4 xv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) xv[k] = kfb_ldv(x, 4 * (cl + k * TPR), n);
+    const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
+    kfb_gemv_rows<LTPR, K, LG>(I, B, w, r0, r1, xv);
+    // the last K2 block of the instance clears the flag for the next launch
+    if (kfb_arrive(ctr + 2, (unsigned)I.nblk, &sh.flag) && threadIdx.x == 0)
+        __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int LTPR, int K, int LG>
+__device__ __forceinline__ void kfb_item_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
+                                             unsigned* sync, unsigned spin_limit, Shared& sh) {
+    if (phase == KFB_BICGK) kfb_bicgk<LTPR, K, LG>(I, blk, arena, ws, sync, sh);
+    else if (phase == KFB_GEMVER_K1) kfb_gemver_k1<LTPR, K, LG>(I, blk, arena, ws, sync, sh);
+    else kfb_gemver_k2<LTPR, K, LG>(I, blk, arena, sync, spin_limit, sh);
+}
+
+__global__ void __launch_bounds__(KFB_THREADS)
+kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ items, int nitems, int item0,
+           int persistent, float* arena, float* ws, unsigned* sync, unsigned spin_limit) {
+    __shared__ Shared sh;
+    for (;;) {
+        int it;
+        if (persistent) {
+            if (threadIdx.x == 0) sh.item = (int)atomicAdd(sync + KFB_SYNC_QUEUE, 1u);
+            __syncthreads();
+            it = sh.item;
+            __syncthreads();
+            if (it >= nitems) break;
+        } else {
+            it = item0 + (int)blockIdx.x;
+        }
+        const kfb_item item = items[it];
+        const kfb_inst I = insts[item.inst];
+        const int phase = item.phase_blk >> 24;
+        const int blk = item.phase_blk & 0xffffff;
+        switch (I.bucket) {
+        case 0: kfb_item_run<4, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        case 1: kfb_item_run<5, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        case 2: kfb_item_run<6, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        case 3: kfb_item_run<6, 2, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        case 4: kfb_item_run<6, 4, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        default: kfb_item_run<6, 8, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        }
+        if (!persistent) break;
+        __syncthreads();
+    }
+    if (persistent && threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(sync + KFB_SYNC_EXIT, 1u) == gridDim.x - 1) {
+            __hip_atomic_store(sync + KFB_SYNC_QUEUE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(sync + KFB_SYNC_EXIT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+}  // namespace
+
+// Persistent launch (grid workgroups draining the queue) or a direct launch of
+// items item0 .. item0 + grid - 1, one per workgroup.
+hipError_t kfb_launch(const kfb_inst* insts, const kfb_item* items, int nitems, int item0, int grid, int persistent,
+                      float* arena, float* ws, unsigned* sync, unsigned spin_limit, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kfb_kernel, dim3(grid), dim3(KFB_THREADS), 0, st, insts, items, nitems, item0, persistent,
+                       arena, ws, sync, spin_limit);
+    return hipGetLastError();
+}
+
+hipError_t kfb_resident_blocks(int* per_cu, int* cus) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kfb_kernel, KFB_THREADS, 0);
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    return hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev);
+}

@@ -22,6 +22,41 @@ __global__ void __launch_bounds__(256) kf_copy_f4_kernel(f4_t* __restrict__ dst,
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Seeded uniform[-1, 1) input values: element (i, j) of a rows x cols block
+// with row pitch ld is the SplitMix64 output number i * cols + j + 1 of the
+// stream starting at `key` (Steele, Lea and Flood), mapped to
+// (h >> 40) 2^-23 - 1, which is exact in float32; columns >= cols get `pad`.
+__device__ __forceinline__ unsigned long long kf_splitmix(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) kf_fill_uniform_kernel(float* __restrict__ dst, long rows, long cols, long ld,
+                                                              unsigned long long key, float pad) {
+    const long total = rows * ld;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long i = e / ld, j = e - i * ld;
+        float v = pad;
+        if (j < cols) {
+            const unsigned long long c = (unsigned long long)(i * cols + j) + 1ull;
+            const unsigned long long h = kf_splitmix(key + c * 0x9E3779B97F4A7C15ull);
+            v = (float)((long long)(h >> 40) - (1ll << 23)) * 0x1p-23f;
+        }
+        dst[e] = v;
+    }
+}
+
+hipError_t launch_fill_uniform(float* dst, long rows, long cols, long ld, unsigned long long key, float pad,
+                               hipStream_t st) {
+    const long total = rows * ld;
+    if (total <= 0) return hipSuccess;
+    long grid = (total + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL(kf_fill_uniform_kernel, dim3((unsigned)grid), dim3(256), 0, st, dst, rows, cols, ld, key, pad);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(void* p, size_t n, unsigned v, hipStream_t st) {
     if (n == 0) return hipSuccess;
     int grid = (int)((n + 255) / 256);

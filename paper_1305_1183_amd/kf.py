@@ -34,6 +34,7 @@ _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
 _sz = ctypes.c_size_t
 _f32 = ctypes.c_float
 _P = ctypes.POINTER
@@ -117,6 +118,7 @@ _SIGS = {
     "kf_plan_source": ([_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)], _i32),
     "kf_plan_kernel_geometry": ([_vp, _i32, _P(_i32), _P(_i32)], _i32),
     "kf_util_copy": ([_vp, _vp, _sz, _vp], _i32),
+    "kf_util_fill_uniform": ([_vp, _i64, _i64, _i64, _u64, _f32, _vp], _i32),
     "kf_jit_release": ([], _i32),
     "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
     "kf_predict_additive": ([_vp, _P(kf_routine_entry), _i32, _P(_f32)], _i32),
@@ -131,6 +133,20 @@ _SIGS = {
     "kf_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
     "kf_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
     "kf_jit_stats": ([_P(_i64), _P(_i64)], _i32),
+    "kf_batch_create": ([_i64, _P(_i32), _P(_i64), _P(_f32), _P(_f32), _vp, _P(_vp)], _i32),
+    "kf_batch_destroy": ([_vp], None),
+    "kf_batch_arena_elems": ([_vp, _P(_i64)], _i32),
+    "kf_batch_workspace_bytes": ([_vp, _P(_sz)], _i32),
+    "kf_batch_offset": ([_vp, _i64, _i32, _P(_i64), _P(_i64)], _i32),
+    "kf_batch_bytes": ([_vp, _P(_i64), _P(_i64)], _i32),
+    "kf_batch_describe": ([_vp, ctypes.c_char_p, _sz, _P(_sz)], _i32),
+    "kf_batch_items": ([_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _i64, _P(_i64)], _i32),
+    "kf_batch_bind": ([_vp, _vp, _vp, _vp], _i32),
+    "kf_batch_run": ([_vp, _i32, _vp], _i32),
+    "kf_batch_capture": ([_vp, _i32, _vp], _i32),
+    "kf_batch_graph_launch": ([_vp, _i32, _vp], _i32),
+    "kf_batch_time": ([_vp, _i32, _i32, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_batch_error": ([_vp, _vp, _P(_u32)], _i32),
 }
 EXPORTED = sorted(_SIGS)
 
@@ -477,6 +493,118 @@ def kf_jit_stats():
 
 def kf_util_copy(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
     _chk(lib().kf_util_copy(_vp(dst), _vp(src), nbytes, _vp(stream)))
+
+
+# ---- batched uneven sizes ------------------------------------------------------------
+KF_BATCH_BICGK, KF_BATCH_GEMVER = 0, 1
+BATCH_BUCKETS = 6
+BATCH_ROWS_PER_STEP = (64, 32, 16, 16, 8, 4)
+BATCH_OPERANDS = {0: ["A", "B_unused", "p", "r", "q", "s"],
+                  1: ["A", "B", "u1", "v1", "u2", "v2", "y", "z", "x", "w"]}
+
+
+class kf_batch_opts(ctypes.Structure):
+    _fields_ = [("rows", (_i32 * BATCH_BUCKETS) * 2), ("grid", _i32), ("spin_limit", _u32)]
+
+
+def batch_opts(rows=None, grid: int = 0, spin_limit: int = 0):
+    """rows: {kind: [rows per bucket]} (0 = library default)."""
+    o = kf_batch_opts()
+    for k, lst in (rows or {}).items():
+        for j, r in enumerate(lst):
+            o.rows[k][j] = int(r)
+    o.grid = int(grid)
+    o.spin_limit = int(spin_limit)
+    return o
+
+
+def kf_batch_create(kinds, ns, alphas=None, betas=None, opts=None):
+    import numpy as np
+    kinds = np.ascontiguousarray(kinds, dtype=np.int32)
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    cnt = len(kinds)
+    al = None if alphas is None else np.ascontiguousarray(alphas, dtype=np.float32)
+    be = None if betas is None else np.ascontiguousarray(betas, dtype=np.float32)
+    fp = lambda a: None if a is None else a.ctypes.data_as(_P(_f32))
+    b = _vp()
+    _chk(lib().kf_batch_create(cnt, kinds.ctypes.data_as(_P(_i32)), ns.ctypes.data_as(_P(_i64)), fp(al), fp(be),
+                               None if opts is None else ctypes.byref(opts), ctypes.byref(b)))
+    return b
+
+
+def kf_batch_destroy(b) -> None:
+    lib().kf_batch_destroy(b)
+
+
+def kf_batch_arena_elems(b) -> int:
+    v = _i64()
+    _chk(lib().kf_batch_arena_elems(b, ctypes.byref(v)))
+    return v.value
+
+
+def kf_batch_workspace_bytes(b) -> int:
+    v = _sz()
+    _chk(lib().kf_batch_workspace_bytes(b, ctypes.byref(v)))
+    return v.value
+
+
+def kf_batch_offset(b, i: int, operand: int):
+    off, ld = _i64(), _i64()
+    _chk(lib().kf_batch_offset(b, i, operand, ctypes.byref(off), ctypes.byref(ld)))
+    return off.value, ld.value
+
+
+def kf_batch_bytes(b):
+    r, w = _i64(), _i64()
+    _chk(lib().kf_batch_bytes(b, ctypes.byref(r), ctypes.byref(w)))
+    return r.value, w.value
+
+
+def kf_batch_describe(b) -> str:
+    return _text(lib().kf_batch_describe, b)
+
+
+def kf_batch_items(b, which: int):
+    import numpy as np
+    cnt = _i64()
+    _chk(lib().kf_batch_items(b, which, None, None, None, 0, ctypes.byref(cnt)))
+    inst, ph, blk = (np.empty(cnt.value, dtype=np.int32) for _ in range(3))
+    P = lambda a: a.ctypes.data_as(_P(_i32))
+    _chk(lib().kf_batch_items(b, which, P(inst), P(ph), P(blk), cnt.value, ctypes.byref(cnt)))
+    return inst, ph, blk
+
+
+def kf_batch_bind(b, arena: int, workspace: int, stream: int = 0) -> None:
+    _chk(lib().kf_batch_bind(b, _vp(arena), _vp(workspace), _vp(stream)))
+
+
+def kf_batch_run(b, which: int = 0, stream: int = 0) -> None:
+    _chk(lib().kf_batch_run(b, which, _vp(stream)))
+
+
+def kf_batch_capture(b, which: int, stream: int) -> None:
+    _chk(lib().kf_batch_capture(b, which, _vp(stream)))
+
+
+def kf_batch_graph_launch(b, which: int, stream: int = 0) -> None:
+    _chk(lib().kf_batch_graph_launch(b, which, _vp(stream)))
+
+
+def kf_batch_time(b, which: int = 0, graph: bool = False, stream: int = 0, warmup: int = 2, reps: int = 10) -> float:
+    t = _f32()
+    _chk(lib().kf_batch_time(b, which, int(graph), _vp(stream), warmup, reps, ctypes.byref(t)))
+    return t.value
+
+
+def kf_batch_error(b, stream: int = 0) -> int:
+    v = _u32()
+    _chk(lib().kf_batch_error(b, _vp(stream), ctypes.byref(v)))
+    return v.value
+
+
+def kf_util_fill_uniform(dst: int, rows: int, cols: int, ld: int, key: int, pad: float = float("nan"),
+                         stream: int = 0) -> None:
+    _chk(lib().kf_util_fill_uniform(_vp(dst), rows, cols, ld, key, pad, _vp(stream)))
 
 
 # ---- plan ranking ------------------------------------------------------------------

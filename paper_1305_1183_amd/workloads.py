@@ -182,3 +182,16 @@ def precision_arrays(fmt, stored, vecs):
     if fmt != "f32":
         arrays["A_scale"] = sc
     return arrays
+
+
+# ---- batched uneven sizes: 4096 BiCGK + 4096 GEMVER, n log-uniform on [32, 2048]
+BATCH_COUNTS = (4096, 4096)
+BATCH_SEED = 3000
+# rows per work item for (BiCGK, GEMVER) x size bucket (n <= 64, 128, 256,
+# 512, 1024, 2048), from the batch autotuner (0 = library default)
+BATCH_TUNED = {0: [0, 0, 0, 0, 0, 0], 1: [0, 0, 0, 0, 0, 0]}
+
+
+def batch_opts(grid: int = 0):
+    from . import kf
+    return kf.batch_opts(rows=BATCH_TUNED, grid=grid)
