@@ -479,7 +479,7 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
         Space sp = call_space(sc, calls[0]);
         if (sp.mat && (mp.sched == 1 || needs_rowres(sc, calls))) {
             if (sp.b > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
-            if (kernel_unit_elems(sc, calls) != 4)
+            if (kernel_has_quantized(sc, calls))
                 return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule reads FP32 matrices only");
             if (mp.sched == 1 && mp.rows && mp.group && mp.rows % mp.group)
                 return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_group");

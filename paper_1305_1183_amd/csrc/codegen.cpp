@@ -293,7 +293,16 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         for (int v : mat_in) {
             e.l("#pragma unroll");
             const int dt = s.values[v].dtype;
-            if (dt != KF_F32) {
+            if (dt != KF_F32 && E == 4) {
+                // narrow units: four elements (4 or 8 bytes) per float4 group, laid out like FP32
+                const int es = dtype_size(dt);
+                const char* ld4 = dt == KF_BF16 ? "kf_ld4_bf16_nt" : "kf_ld4_fp8_nt";
+                if (!edge)
+                    e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = %s(M%d + (row * LD%d + col[j]) * %d);", v, ld4, v, v, es));
+                else
+                    e.l(F("for (int j = 0; j < K; ++j) L%d[gi][j] = (row < r1 && col[j] < N) ? kf_mask4(%s(M%d + (row * LD%d + col[j]) * %d), col[j], N) : kf_zero4();",
+                          v, ld4, v, v, es));
+            } else if (dt != KF_F32) {
                 // one 16-byte unit per (row, u) decodes into 16/es elements = EQ float4 groups;
                 // a BF16 matrix in a kernel with 16-element units takes two units per span
                 const int es = dtype_size(dt), per = 16 / es, EQ = per / 4;

@@ -93,25 +93,32 @@ __device__ __forceinline__ void kfb_colsum(kf_f4* acc, kf_f4* red, Emit emit) {
     }
 }
 
+// Device-scope release and acquire, separately: a release writes back this
+// XCD's L2 so that other XCDs can read what the workgroup stored; an acquire
+// invalidates the local caches so that this workgroup reads what other XCDs
+// released. A full fence does both, and its invalidation drops lines every
+// other workgroup on the XCD is still using, so each side is used only where
+// it is needed.
+__device__ __forceinline__ void kfb_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void kfb_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Arrival at a per-instance counter. Returns true in every thread of the
 // workgroup that arrives last; that workgroup then sees the stores every
 // earlier arrival made before arriving, and the counter is back at zero.
 __device__ __forceinline__ bool kfb_arrive(unsigned* counter, unsigned count, int* s_flag) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
+        kfb_release();
         const unsigned old = atomicAdd(counter, 1u);
         const int last = old == count - 1;
         if (last) {
-            __threadfence();
+            kfb_acquire();
             __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         *s_flag = last;
     }
     __syncthreads();
-    const bool last = *s_flag != 0;
-    if (last) __threadfence();
-    return last;
+    return *s_flag != 0;
 }
 
 // Chunk k of a thread covers columns col .. col + 3, col = 4 (cl + k TPR).
@@ -173,17 +180,38 @@ __device__ __forceinline__ int kfb_tid() {
     return t;
 }
 
+// Column-indexed vectors (BiCGK p; GEMVER v1, v2, then x) are staged in LDS
+// once per item and read from there at every row step: held in registers
+// they would cost 2 K float4 per lane and halve the occupancy of the
+// largest tiles.
+// A compiler barrier at the top of each row step: the LDS copies of the
+// column vectors are read again at every step instead of being hoisted into
+// registers for the whole item.
+__device__ __forceinline__ void kfb_reload_lds() { asm volatile("" ::: "memory"); }
+
 struct Shared {
     kf_f4 red[KFB_THREADS];
-    kf_f4 xs[KFB_MAX_N / 4];
+    kf_f4 cv[2][KFB_MAX_N / 4];
     int flag;
     int item;
 };
+
+// Chunks 0 .. TPR K - 1 of a column vector into LDS (threads tid < TPR;
+// entries >= n are zero). The caller synchronises before the first read.
+template <int LTPR, int K>
+__device__ __forceinline__ void kfb_stage(kf_f4* dst, const float* v, int n, int tid) {
+    constexpr int TPR = 1 << LTPR;
+    if (tid < TPR) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) dst[tid + k * TPR] = kfb_ldv(v, 4 * (tid + k * TPR), n);
+    }
+}
 
 // w rows r0 .. r1 - 1 of alpha B x, x given per thread at its columns.
 template <int LTPR, int K, int LG>
 __device__ __forceinline__ void kfb_gemv_rows(const kfb_inst& I, const float* __restrict__ B,
                                               float* __restrict__ w, int r0, int r1, const kf_f4* xv) {
+    // xv: x in LDS, chunk c at xv[c]
     constexpr int TPR = 1 << LTPR, G = 1 << LG, RL = KFB_THREADS / TPR, RI = RL * G;
     const int tid = kfb_tid(), cl = tid & (TPR - 1), rl = tid >> LTPR;
     const int n = I.n;
@@ -193,6 +221,7 @@ __device__ __forceinline__ void kfb_gemv_rows(const kfb_inst& I, const float* __
     for (int k = 0; k < K; ++k) cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
 #pragma unroll 1
     for (int i0 = r0; i0 < r1; i0 += RI) {
+        kfb_reload_lds();
         kf_f4 b[G][K];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -205,7 +234,7 @@ __device__ __forceinline__ void kfb_gemv_rows(const kfb_inst& I, const float* __
         for (int g = 0; g < G; ++g) {
             wp[g] = 0.f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) wp[g] = kf_dot4(b[g][k], xv[k], wp[g]);
+            for (int k = 0; k < K; ++k) wp[g] = kf_dot4(b[g][k], xv[cl + k * TPR], wp[g]);
         }
         const float ws = kfb_rows_reduce<LTPR, LG>(wp);
         const int g = cl >> (LTPR - LG);
@@ -227,16 +256,19 @@ __device__ void kfb_bicgk(const kfb_inst& I, int blk, float* __restrict__ arena,
     const float* __restrict__ r = arena + I.v[1];
     float* __restrict__ q = arena + I.v[2];
     float* __restrict__ s = arena + I.v[3];
-    kf_f4 pv[K], acc[K];
+    kf_f4 acc[K];
     kfb_cols cs[K];
+    kfb_stage<LTPR, K>(sh.cv[0], p, n, tid);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
-        pv[k] = kfb_ldv(p, 4 * (cl + k * TPR), n);
         acc[k] = kf_zero4();
     }
+    __syncthreads();
+    const kf_f4* pv = sh.cv[0] + cl;
 #pragma unroll 1
     for (int i0 = r0; i0 < r1; i0 += RI) {
+        kfb_reload_lds();
         kf_f4 a[G][K];
         float rr[G];
 #pragma unroll
@@ -253,7 +285,7 @@ __device__ void kfb_bicgk(const kfb_inst& I, int blk, float* __restrict__ arena,
         for (int g = 0; g < G; ++g) {
             qp[g] = 0.f;
 #pragma unroll
-            for (int k = 0; k < K; ++k) qp[g] = kf_dot4(a[g][k], pv[k], qp[g]);
+            for (int k = 0; k < K; ++k) qp[g] = kf_dot4(a[g][k], pv[k * TPR], qp[g]);
 #pragma unroll
             for (int k = 0; k < K; ++k) acc[k] = kf_fma4s(rr[g], a[g][k], acc[k]);
         }
@@ -298,17 +330,21 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
     const float* __restrict__ z = arena + I.v[5];
     float* __restrict__ x = arena + I.v[6];
     float* __restrict__ w = arena + I.v[7];
-    kf_f4 v1c[K], v2c[K], acc[K];
+    kf_f4 acc[K];
     kfb_cols cs[K];
+    kfb_stage<LTPR, K>(sh.cv[0], v1, n, tid);
+    kfb_stage<LTPR, K>(sh.cv[1], v2, n, tid);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         cs[k] = kfb_col(4 * (cl + k * TPR), n, I.ld);
-        v1c[k] = kfb_ldv(v1, 4 * (cl + k * TPR), n);
-        v2c[k] = kfb_ldv(v2, 4 * (cl + k * TPR), n);
         acc[k] = kf_zero4();
     }
+    __syncthreads();
+    const kf_f4* v1c = sh.cv[0] + cl;
+    const kf_f4* v2c = sh.cv[1] + cl;
 #pragma unroll 1
     for (int i0 = r0; i0 < r1; i0 += RI) {
+        kfb_reload_lds();
         kf_f4 a[G][K];
         float u1r[G], u2r[G], yr[G];
 #pragma unroll
@@ -328,8 +364,8 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
             float* brow = B + (long)row * ld;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                kf_f4 b = kf_fma4s(u1r[g], v1c[k], a[g][k]);
-                b = kf_fma4s(u2r[g], v2c[k], b);
+                kf_f4 b = kf_fma4s(u1r[g], v1c[k * TPR], a[g][k]);
+                b = kf_fma4s(u2r[g], v2c[k * TPR], b);
                 if (row < r1) kfb_stm(brow, 4 * (cl + k * TPR), n, b);
                 acc[k] = kf_fma4s(yr[g], b, acc[k]);
             }
@@ -340,13 +376,10 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
         kfb_colsum<LTPR, K>(acc, sh.red, [&](int c, kf_f4 v) {
             const kf_f4 xc = kf_fma4s(I.beta, v, kfb_ldv(z, 4 * c, n));
             kfb_stv(x, 4 * c, n, xc);
-            sh.xs[c] = xc;
+            sh.cv[0][c] = xc;
         });
         __syncthreads();
-        kf_f4 xv[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) xv[k] = sh.xs[cl + k * TPR];
-        kfb_gemv_rows<LTPR, K, LG>(I, B, w, 0, n, xv);
+        kfb_gemv_rows<LTPR, K, LG>(I, B, w, 0, n, sh.cv[0]);
         return;
     }
     float* part = ws + I.ws + (long)blk * ld;
@@ -362,7 +395,7 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();
+            kfb_release();
             __hip_atomic_store(ctr + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -386,7 +419,7 @@ __device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ ar
             }
             __builtin_amdgcn_s_sleep(8);
         }
-        __threadfence();
+        kfb_acquire();
         sh.flag = ok;
     }
     __syncthreads();
@@ -396,11 +429,10 @@ __device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ ar
     const float* __restrict__ B = arena + I.b;
     const float* __restrict__ x = arena + I.v[6];
     float* __restrict__ w = arena + I.v[7];
-    kf_f4 xv[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) xv[k] = kfb_ldv(x, 4 * (cl + k * TPR), n);
+    kfb_stage<LTPR, K>(sh.cv[0], x, n, kfb_tid());
+    __syncthreads();
     const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
-    kfb_gemv_rows<LTPR, K, LG>(I, B, w, r0, r1, xv);
+    kfb_gemv_rows<LTPR, K, LG>(I, B, w, r0, r1, sh.cv[0]);
     // the last K2 block of the instance clears the flag for the next launch
     if (kfb_arrive(ctr + 2, (unsigned)I.nblk, &sh.flag) && threadIdx.x == 0)
         __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -445,7 +477,6 @@ kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ item
         __syncthreads();
     }
     if (persistent && threadIdx.x == 0) {
-        __threadfence();
         if (atomicAdd(sync + KFB_SYNC_EXIT, 1u) == gridDim.x - 1) {
             __hip_atomic_store(sync + KFB_SYNC_QUEUE, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(sync + KFB_SYNC_EXIT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

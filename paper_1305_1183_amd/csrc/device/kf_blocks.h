@@ -95,6 +95,18 @@ __device__ __forceinline__ void kf_dec_fp8(kf_u4 w, kf_f4* out) {
     out[2] = kf_dec_fp8_word(w.z);
     out[3] = kf_dec_fp8_word(w.w);
 }
+// Four quantised elements (one float4 group) with one 4- or 8-byte load.
+typedef unsigned int kf_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ kf_f4 kf_ld4_fp8_nt(const unsigned char* p) {
+    return kf_dec_fp8_word(__builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(p)));
+}
+__device__ __forceinline__ kf_f4 kf_ld4_bf16_nt(const unsigned char* p) {
+    const kf_u2 w = __builtin_nontemporal_load(reinterpret_cast<const kf_u2*>(p));
+    kf_f4 r;
+    r.x = __uint_as_float(w.x << 16); r.y = __uint_as_float(w.x & 0xffff0000u);
+    r.z = __uint_as_float(w.y << 16); r.w = __uint_as_float(w.y & 0xffff0000u);
+    return r;
+}
 // Zero the components of v at column index >= n (v holds columns col..col+3).
 __device__ __forceinline__ kf_f4 kf_mask4(kf_f4 v, long col, long n) {
     v.x = (col + 0 < n) ? v.x : 0.f;

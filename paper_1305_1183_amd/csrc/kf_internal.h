@@ -83,6 +83,7 @@ int dtype_size(int dtype);
 // Elements per 16-byte unit of the kernel made of `calls` (smallest element size
 // of the matrices it loads).
 int kernel_unit_elems(const Script& s, const std::vector<int>& calls);
+bool kernel_has_quantized(const Script& s, const std::vector<int>& calls);
 VecParams default_vec_params(int64_t n, const VecParams& req);
 
 // ---- code generation (codegen.cpp) --------------------------------------------

@@ -279,11 +279,25 @@ int dtype_size(int dtype) { return dtype == KF_BF16 ? 2 : dtype == KF_FP8_E4M3 ?
 
 int kernel_unit_elems(const Script& s, const std::vector<int>& calls) {
     int es = 4;
+    bool ger_q = false;
     for (int c : calls) {
         const Value& A = s.values[s.calls[c].in[0]];
         if (A.kind == VK::Mat) es = std::min(es, dtype_size(A.dtype));
+        if (A.kind == VK::Mat && A.dtype != KF_F32 && s.calls[c].op == Op::Ger) ger_q = true;
     }
+    // A kernel that expands a quantised matrix into an FP32 one (ger) loads
+    // four elements per lane and unit, so that its FP32 stores stay 16 bytes
+    // per lane and contiguous across the wave.
+    if (ger_q) return 4;
     return 16 / es;
+}
+
+bool kernel_has_quantized(const Script& s, const std::vector<int>& calls) {
+    for (int c : calls) {
+        const Value& A = s.values[s.calls[c].in[0]];
+        if (A.kind == VK::Mat && A.dtype != KF_F32) return true;
+    }
+    return false;
 }
 
 MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req, int e_per_unit) {

@@ -189,9 +189,15 @@ BATCH_COUNTS = (4096, 4096)
 BATCH_SEED = 3000
 # rows per work item for (BiCGK, GEMVER) x size bucket (n <= 64, 128, 256,
 # 512, 1024, 2048), from the batch autotuner (0 = library default)
-BATCH_TUNED = {0: [0, 0, 0, 0, 0, 0], 1: [0, 0, 0, 0, 0, 0]}
+BATCH_TUNED = {0: [64, 128, 256, 512, 512, 1024], 1: [64, 128, 256, 512, 1024, 512]}
 
 
-def batch_opts(grid: int = 0):
+# The per-instance launch loop (the baseline) launches one instance at a time,
+# so it wants many small items per instance to fill the GPU: it keeps the
+# library's default rows per item.
+BATCH_LOOP_ROWS = {0: [0] * 6, 1: [0] * 6}
+
+
+def batch_opts(grid: int = 0, loop: bool = False):
     from . import kf
-    return kf.batch_opts(rows=BATCH_TUNED, grid=grid)
+    return kf.batch_opts(rows=BATCH_LOOP_ROWS if loop else BATCH_TUNED, grid=grid)
