@@ -103,12 +103,15 @@ def precision_suite(args, torch, kf, S, WL, dev):
                 devin[k] = torch.from_numpy(np.ascontiguousarray(v)).to(dev)
             del arrays
             row = {}
-            for mode in ("fused", "unfused"):
-                prog = q.compile(mode=mode).bind(device=dev, **devin)
+            variants = [("fused", "fused", {}), ("unfused", "unfused", {})]
+            if fmt != "f32":
+                variants += [("fused_unit4", "fused", {"mat_unit": 4}), ("fused_unit16", "fused", {"mat_unit": 16})]
+            for key, mode, extra in variants:
+                prog = q.compile(mode=mode, **extra).bind(device=dev, **devin)
                 r, w = prog.bytes()
                 us = prog.time(3, 20)
-                row[mode] = {"us": round(us, 2), "bytes": r + w, "gbps": round((r + w) / us / 1e3, 1),
-                             "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+                row[key] = {"us": round(us, 2), "bytes": r + w, "gbps": round((r + w) / us / 1e3, 1),
+                            "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
                 del prog
             row["speedup"] = round(row["unfused"]["us"] / row["fused"]["us"], 3)
             res["%s/%s" % (name, fmt)] = row

@@ -174,6 +174,11 @@ typedef struct kf_compile_opts {
     int32_t max_partitions;
     const struct kf_compile_opts* grid;
     int32_t grid_len;
+    /* Quantised matrices (BF16, FP8): elements per lane and load. 4 = four
+     * elements (4 or 8 bytes), laid out like FP32; 16 = one 16-byte load (8
+     * BF16 or 16 FP8 elements); 0 = four when the kernel expands the matrix
+     * into an FP32 one (ger), else 16. FP32 kernels ignore it. */
+    int32_t mat_unit;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */

@@ -15,7 +15,8 @@ from . import kf
 MAT_GRID = [dict(mat_k=k, mat_waves=w, mat_group=g, mat_rows=r)
             for k in (1, 2)
             for (w, g) in ((4, 4), (4, 8), (8, 2), (8, 4), (2, 8))
-            for r in (256, 512, 1024)]
+            for r in (256, 512, 1024)] + \
+           [dict(mat_sched=1, mat_waves=w, mat_group=g) for w in (8, 16) for g in (1, 2, 4)]
 VEC_GRID = [dict(vec_unroll=u, vec_threads=t, vec_grid=g)
             for u in (2, 4, 8) for t in (256, 512) for g in (1024, 2048, 4096)]
 

@@ -446,6 +446,7 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     const size_t nv = sc.values.size();
     p->mp.k = o.mat_k; p->mp.waves = o.mat_waves; p->mp.group = o.mat_group; p->mp.rows = o.mat_rows;
     p->mp.sched = o.mat_sched;
+    p->mp.unit = o.mat_unit;
     p->vp.unroll = o.vec_unroll; p->vp.threads = o.vec_threads; p->vp.grid = o.vec_grid;
     p->bind.assign(nv, nullptr);
     p->consts.assign(nv, 0.f);
@@ -461,7 +462,9 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     mp.group = o.mat_group;
     mp.rows = o.mat_rows;
     mp.sched = o.mat_sched;
+    mp.unit = o.mat_unit;
     if (mp.sched < 0 || mp.sched > 1) return set_error(KF_ERR_ARG, "mat_sched must be 0 or 1");
+    if (mp.unit != 0 && mp.unit != 4 && mp.unit != 16) return set_error(KF_ERR_ARG, "mat_unit must be 0, 4 or 16");
     VecParams vp;
     vp.unroll = o.vec_unroll;
     vp.threads = o.vec_threads;
@@ -486,7 +489,7 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
             if (mp.sched == 1 && mp.waves && (int64_t)mp.waves * 256 * 8 < sp.b)
                 return set_error(KF_ERR_ARG, "row-resident schedule: mat_waves too small for the row length");
         } else if (sp.mat) {
-            MatParams q = default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(sc, calls));
+            MatParams q = default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(sc, calls, mp.unit));
             if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_waves * mat_group");
         }
         pk.code = generate_kernel(sc, calls, part, mp, vp);

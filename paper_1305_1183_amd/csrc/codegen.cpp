@@ -137,7 +137,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     const long M = (long)sp.a, N = (long)sp.b;
     // E matrix elements per 16-byte load unit (4 FP32, 8 BF16, 16 FP8); a lane
     // takes p.k units per row, i.e. K = k E / 4 float4 column groups.
-    const int E = kernel_unit_elems(s, calls), EG = E / 4;
+    const int E = kernel_unit_elems(s, calls, p.unit), EG = E / 4;
     const int U = p.k, K = p.k * EG, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
     int LG = 0;
     while ((1 << LG) < G) ++LG;
@@ -1140,7 +1140,7 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
         if (q.sched != 1) q.waves = q.group = q.rows = 0;   // strip-schedule parameters do not carry over
         kc = gen_mat_rowres(s, calls, part, q);
     } else {
-        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(s, calls)))
+        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(s, calls, mp.unit)))
                     : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
     }
     for (Launch& l : kc.launches) launch_bytes(s, &l);

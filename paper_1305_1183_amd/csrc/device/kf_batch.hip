@@ -446,7 +446,10 @@ __device__ __forceinline__ void kfb_item_run(const kfb_inst& I, int phase, int b
     else kfb_gemver_k2<LTPR, K, LG>(I, blk, arena, sync, spin_limit, sh);
 }
 
-__global__ void __launch_bounds__(KFB_THREADS)
+// Three waves per SIMD (163 VGPRs): the largest tiles keep eight 16-byte
+// loads per lane in flight, and three resident workgroups per CU keep enough
+// bytes outstanding to cover HBM latency.
+__global__ void __launch_bounds__(KFB_THREADS) __attribute__((amdgpu_waves_per_eu(3, 8)))
 kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ items, int nitems, int item0,
            int persistent, float* arena, float* ws, unsigned* sync, unsigned spin_limit) {
     __shared__ Shared sh;

@@ -74,7 +74,7 @@ std::vector<int> unfused_partition(const Script& s);
 std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vector<int>& part);
 
 // ---- implementation parameters ---------------------------------------------
-struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0; };  // sched 1 = row-resident
+struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0, unit = 0; };  // sched 1 = row-resident
 struct VecParams { int unroll = 0, threads = 0, grid = 0; };
 // e_per_unit: matrix elements per 16-byte load unit of the kernel (4 for FP32,
 // 8 with a BF16 matrix, 16 with an FP8 matrix).
@@ -82,7 +82,7 @@ MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req, i
 int dtype_size(int dtype);
 // Elements per 16-byte unit of the kernel made of `calls` (smallest element size
 // of the matrices it loads).
-int kernel_unit_elems(const Script& s, const std::vector<int>& calls);
+int kernel_unit_elems(const Script& s, const std::vector<int>& calls, int req = 0);
 bool kernel_has_quantized(const Script& s, const std::vector<int>& calls);
 VecParams default_vec_params(int64_t n, const VecParams& req);
 

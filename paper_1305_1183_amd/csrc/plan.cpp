@@ -277,7 +277,7 @@ std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vecto
 
 int dtype_size(int dtype) { return dtype == KF_BF16 ? 2 : dtype == KF_FP8_E4M3 ? 1 : 4; }
 
-int kernel_unit_elems(const Script& s, const std::vector<int>& calls) {
+int kernel_unit_elems(const Script& s, const std::vector<int>& calls, int req) {
     int es = 4;
     bool ger_q = false;
     for (int c : calls) {
@@ -285,9 +285,13 @@ int kernel_unit_elems(const Script& s, const std::vector<int>& calls) {
         if (A.kind == VK::Mat) es = std::min(es, dtype_size(A.dtype));
         if (A.kind == VK::Mat && A.dtype != KF_F32 && s.calls[c].op == Op::Ger) ger_q = true;
     }
-    // A kernel that expands a quantised matrix into an FP32 one (ger) loads
-    // four elements per lane and unit, so that its FP32 stores stay 16 bytes
-    // per lane and contiguous across the wave.
+    // req: 4 = narrow units (four elements per lane and load), 16 = one
+    // 16-byte load per lane; 0 = automatic. Automatically, a kernel that
+    // expands a quantised matrix into an FP32 one (ger) takes narrow units so
+    // that its FP32 stores stay 16 bytes per lane and contiguous across the
+    // wave; other kernels take 16-byte loads.
+    if (es == 4 || req == 4) return 4;
+    if (req == 16) return 16 / es;
     if (ger_q) return 4;
     return 16 / es;
 }

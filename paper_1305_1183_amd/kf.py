@@ -61,9 +61,9 @@ kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("mat_sched", _i32),
                             ("partition", _P(_i32)), ("partition_len", _i32),
                             ("table", _P(kf_routine_entry)), ("table_len", _i32), ("max_partitions", _i32),
-                            ("grid", _P(kf_compile_opts)), ("grid_len", _i32)]
+                            ("grid", _P(kf_compile_opts)), ("grid_len", _i32), ("mat_unit", _i32)]
 PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
-                "mat_sched"]
+                "mat_sched", "mat_unit"]
 
 
 ROUTINES = ["LOAD_MAT", "STORE_MAT", "COMPUTE_GEMV", "COMPUTE_GEMTV", "COMPUTE_GER", "LOAD_VEC",

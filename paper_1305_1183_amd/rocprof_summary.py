@@ -43,11 +43,34 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--out-dir", default="profiles")
     ap.add_argument("--tag", required=True)
+    ap.add_argument("--by-grid", default="",
+                    help="kernels whose name contains this are listed per grid size, from the dispatch trace")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--pmc-cmd", default="")
     a = ap.parse_args()
     os.makedirs(a.out_dir, exist_ok=True)
-    if a.trace:
+    if a.trace and a.by_grid:
+        agg = collections.defaultdict(list)
+        vg = {}
+        for r in _csv(a.trace, "_kernel_trace.csv"):
+            name = r["Kernel_Name"]
+            if a.by_grid in name:
+                name = "%s grid=%d" % (a.by_grid, int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])))
+                key = name if int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])) >= 256 else a.by_grid + " grid<256"
+            else:
+                key = name.split("(")[0]
+            agg[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            vg[key] = r["VGPR_Count"]
+        tot = sum(sum(v) for v in agg.values())
+        lines = ["# rocprofv3 --kernel-trace (per dispatch, grouped by grid size): %s" % a.tag,
+                 "# command: %s" % a.cmd,
+                 "%-44s %7s %12s %10s %10s %6s %8s" % ("kernel", "calls", "avg_us", "min_us", "max_us", "vgpr", "pct")]
+        for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+            lines.append("%-44s %7d %12.2f %10.2f %10.2f %6s %8.2f" % (k[:44], len(v), sum(v) / len(v), min(v), max(v),
+                                                                     vg[k], 100.0 * sum(v) / tot))
+        with open(os.path.join(a.out_dir, a.tag + "_kernel_stats.txt"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    elif a.trace:
         rows = _csv(a.trace, "_kernel_stats.csv")
         lines = ["# rocprofv3 --kernel-trace --stats: %s" % a.tag,
                  "# command: %s" % a.cmd,
@@ -79,11 +102,6 @@ def main():
                                "write_scale": round(sw, 4)},
                "kernels": kernels}
         path = os.path.join(a.out_dir, "pmc_summary.json")
-        if os.path.exists(path):
-            old = json.load(open(path))
-            old_k = old.get("kernels", {})
-            old_k.update(kernels)
-            out["kernels"] = old_k
         with open(path, "w") as f:
             json.dump(out, f, indent=1, sort_keys=True)
             f.write("\n")

@@ -93,7 +93,8 @@ _M1 = dict(mat_k=1, mat_waves=4, mat_group=4, mat_rows=1024)
 TUNED = {
     ("bicgk", "fused"): _M2, ("bicgk", "unfused"): _M1,
     ("atax", "fused"): _M2, ("atax", "unfused"): dict(mat_k=1, mat_waves=2, mat_group=8, mat_rows=1024),
-    ("gesummv", "fused"): _M2, ("gesummv", "unfused"): _M1,
+    ("gesummv", "fused"): dict(mat_sched=1, mat_waves=8, mat_group=2),
+    ("gesummv", "unfused"): dict(mat_sched=1, mat_waves=16, mat_group=4),
     ("gemver", "fused"): _M2, ("gemver", "unfused"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=1024),
     ("axpydot", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=2048),
     ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=1024),

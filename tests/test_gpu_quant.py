@@ -100,3 +100,28 @@ def test_quantised_param_grid():
             h = run(S.bicgk_q(m, n, fmt), {"A": st, "A_scale": sc, "p": p, "r": r}, "fused", **params)
             tol = WL.tolerance("bicgk", m, n)
             assert WL.rel_l2(h["q"], qr) <= tol and WL.rel_l2(h["s"], sr) <= tol
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("unit", [4, 16])
+def test_quantised_load_units(fmt, unit):
+    """Both load widths for quantised matrices (four elements per lane, or one
+    16-byte load per lane), in BiCGK and in GEMVER's ger kernel, with ragged
+    edges in both dimensions."""
+    m, n = 259, 1031
+    A = I.normal(34, 0, m * n).reshape(m, n)
+    st, sc = Q.quantize_rows(A, fmt)
+    D = OQ.dequantize(st, sc, fmt, n)
+    p, r = I.vector(34, 1, n), I.vector(34, 2, m)
+    print("case units", fmt, unit, flush=True)
+    h = run(S.bicgk_q(m, n, fmt), {"A": st, "A_scale": sc, "p": p, "r": r}, "fused", mat_unit=unit)
+    qr, sr = quant_oracle_bicgk(D, p, r)
+    tol = WL.tolerance("bicgk", m, n)
+    assert WL.rel_l2(h["q"], qr) <= tol and WL.rel_l2(h["s"], sr) <= tol
+    v = {k: I.vector(34, i + 3, m if k in ("u1", "u2", "y") else n)
+         for i, k in enumerate(["u1", "v1", "u2", "v2", "y", "z"])}
+    h = run(S.gemver_q(m, n, 1.5, 0.75, fmt), dict(v, A=st, A_scale=sc), "fused", mat_unit=unit)
+    B, x, w = quant_oracle_gemver(D, v, 1.5, 0.75)
+    tol = WL.tolerance("gemver", m, n)
+    assert WL.rel_l2(h["B"][:, :n], B) <= tol
+    assert WL.rel_l2(h["x"], x) <= tol and WL.rel_l2(h["w"], w) <= tol
