@@ -342,6 +342,27 @@ def main():
            "sequences_extra": extra,
            "launches_us_warmup_probe": {"%s/%d/%d %s" % (k["seq"], k["k"], k["l"], k["name"]): round(float(a), 2)
                                         for k, a in zip(kernels, avg_k)}}
+    # practical ceiling of a read+write stream on this device: a 1 GiB copy
+    # (128-bit non-temporal loads and stores), for the dominant launch, which
+    # also reads one matrix and writes one
+    if not args.only:
+        torch.cuda.empty_cache()
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_(-1, 1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            kf.kf_util_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, st)
+        evc = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for a_, b_ in evc:
+            a_.record(stream)
+            kf.kf_util_copy(dst.data_ptr(), src.data_ptr(), src.numel() * 4, st)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        cus = float(np.median([a_.elapsed_time(b_) for a_, b_ in evc])) * 1e3
+        copy_gbps = 2 * src.numel() * 4 / cus / 1e3
+        out["copy_ceiling"] = {"gbps": round(copy_gbps, 1), "frac_of_peak": round(copy_gbps / HBM_PEAK_GBPS, 4),
+                               "dominant_frac_of_copy": round(achieved / copy_gbps, 4),
+                               "what": "1 GiB device copy, read + write bytes / median time"}
+        del src, dst
     if not args.no_cpu_baseline and not args.only:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -91,8 +91,8 @@ def rel_l2(got, ref) -> float:
 _M2 = dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024)
 _M1 = dict(mat_k=1, mat_waves=4, mat_group=4, mat_rows=1024)
 TUNED = {
-    ("bicgk", "fused"): _M2, ("bicgk", "unfused"): _M1,
-    ("atax", "fused"): _M2, ("atax", "unfused"): dict(mat_k=1, mat_waves=2, mat_group=8, mat_rows=1024),
+    ("bicgk", "fused"): _M1, ("bicgk", "unfused"): _M2,
+    ("atax", "fused"): _M2, ("atax", "unfused"): _M2,
     ("gesummv", "fused"): dict(mat_sched=1, mat_waves=8, mat_group=2),
     ("gesummv", "unfused"): dict(mat_sched=1, mat_waves=16, mat_group=4),
     ("gemver", "fused"): _M2, ("gemver", "unfused"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=1024),
@@ -100,7 +100,7 @@ TUNED = {
     ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=1024),
     ("waxpby", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
     ("waxpby", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
-    ("sgemvt", "fused"): _M1, ("sgemvt", "unfused"): _M1,
+    ("sgemvt", "fused"): _M2, ("sgemvt", "unfused"): dict(mat_k=1, mat_waves=2, mat_group=8, mat_rows=1024),
     ("vadd", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
     ("vadd", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=4096),
 }
