@@ -133,11 +133,12 @@ enum {
     KF_MODE_UNFUSED = 0,      /* one kernel per call                           */
     KF_MODE_FUSED = 1,        /* the legal partition with fewest kernels       */
     KF_MODE_ADDITIVE = 2,     /* best candidate by the additive routine predictor */
-    KF_MODE_LEARNED = 3,      /* best candidate by the learned cost model: needs
-                                 device buffers, ranked with kf_candidates +
-                                 kf_planset_features + kf_mlp_forward          */
-    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate: needs bound buffers,
-                                 kf_candidates + kf_time_plan                  */
+    KF_MODE_LEARNED = 3,      /* best candidate by the learned cost model
+                                 (opts.model); with opts.top_k > 1 the top_k
+                                 predictions are timed (needs opts.bind_*) and
+                                 the fastest is kept                           */
+    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate on opts.stream with the
+                                 buffers of opts.bind_* and keep the fastest   */
     KF_MODE_PARTITION = 5     /* the partition given in opts.partition         */
 };
 enum {
@@ -179,6 +180,18 @@ typedef struct kf_compile_opts {
      * BF16 or 16 FP8 elements); 0 = four when the kernel expands the matrix
      * into an FP32 one (ger), else 16. FP32 kernels ignore it. */
     int32_t mat_unit;
+    /* KF_MODE_LEARNED: the trained model (not owned). KF_MODE_LEARNED with
+     * top_k > 1 and KF_MODE_EXHAUSTIVE time candidates on `stream` with the
+     * caller's device buffers: bind_ptrs[i] is bound to script value
+     * bind_values[i] (every input and output, as for kf_bind; the inputs are
+     * read, the outputs overwritten). The library allocates and frees the
+     * timing workspace itself. */
+    const struct kf_costmodel* model;
+    void* stream;
+    const int32_t* bind_values;
+    void* const* bind_ptrs;
+    int32_t bind_len;
+    int32_t top_k;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
@@ -202,7 +215,9 @@ kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, in
  * the first max_partitions legal partitions crossed with the implementation
  * parameter points grid[0..grid_len) (mode and partition fields ignored; only
  * the fields of the kernel classes present matter, and candidates whose
- * kernels would be identical are listed once). */
+ * kernels would be identical are listed once). grid = NULL takes 24 points:
+ * the shape-dependent defaults, four fixed strip shapes and the row-resident
+ * schedule, crossed with the defaults and three fixed BLAS-1 shapes. */
 kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_compile_opts* grid,
                         int32_t grid_len, kf_planset** out);
 /* Parameters of candidate i (mode = KF_MODE_PARTITION, partition pointing into
@@ -351,6 +366,40 @@ kf_status kf_mlp_loss_grad(const kf_mlp* m, const float* params, const float* X,
 kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float* mstate,
                       float* vstate, int32_t step, float lr, float beta1, float beta2, float eps,
                       void* stream);
+
+/* Cost model for plan ranking: the MLP above over KF_FEATURE_DIM kernel
+ * features, predicting the log of a kernel's run time in microseconds; a
+ * plan's prediction is the sum over its kernels of exp(prediction) plus
+ * launch_us per launch. The object owns its device memory (parameters, Adam
+ * moments, workspace), allocated on the current device at creation and on
+ * first use; all of its work runs on the caller's stream, which is
+ * synchronised before a call returns. */
+typedef struct kf_costmodel kf_costmodel;
+kf_status kf_costmodel_create(int32_t hidden, int32_t layers, uint64_t seed, kf_costmodel** out);
+void kf_costmodel_destroy(kf_costmodel* cm);
+/* Train on n samples: X is n x KF_FEATURE_DIM host floats (row-major),
+ * y_log_us the targets. Features and targets are standardised with the
+ * training data's mean and deviation (kept in the model); MSE on the
+ * standardised log time, Adam (0.9, 0.999, 1e-8) at rate lr, minibatches
+ * of `batch` in an order shuffled per epoch from `seed`. loss_per_epoch
+ * (optional, `epochs` floats) gets the mean minibatch loss of each epoch. */
+kf_status kf_costmodel_train(kf_costmodel* cm, const float* X, const float* y_log_us, int64_t n, int32_t epochs,
+                             int32_t batch, float lr, uint64_t seed, void* stream, float* loss_per_epoch);
+/* log_us[i] = predicted log microseconds of feature row i (host arrays). */
+kf_status kf_costmodel_predict(kf_costmodel* cm, const float* X, int64_t n, float* log_us, void* stream);
+kf_status kf_costmodel_set_launch_us(kf_costmodel* cm, float us);
+/* Host copies of the parameters (kf_costmodel_dims' nparams floats, the
+ * kf_mlp layout), the feature means and deviations (KF_FEATURE_DIM each),
+ * the target mean and deviation (two doubles) and the launch term; any
+ * pointer may be NULL. kf_costmodel_set installs them. */
+kf_status kf_costmodel_get(const kf_costmodel* cm, float* params, float* mu, float* sd, double* y_mu_sd,
+                           float* launch_us);
+kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* mu, const float* sd,
+                           const double* y_mu_sd, float launch_us);
+kf_status kf_costmodel_dims(const kf_costmodel* cm, int32_t* hidden, int32_t* layers, int64_t* nparams);
+/* Binary file of the model ("KFCM", version 1); load creates a new model. */
+kf_status kf_costmodel_save(const kf_costmodel* cm, const char* path);
+kf_status kf_costmodel_load(const char* path, kf_costmodel** out);
 
 /* ---- run-time compilation cache ------------------------------------------ */
 /* Each plan kernel is compiled by hipRTC for gfx950 once per process (keyed

@@ -545,6 +545,10 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
 }
 
 kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
+namespace kf {
+kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
+kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
+}  // namespace kf
 
 extern "C" {
 
@@ -567,10 +571,9 @@ kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** 
             case KF_MODE_ADDITIVE:
                 return compile_additive(s, o, out);
             case KF_MODE_LEARNED:
+                return kf::compile_learned(s, o, out);
             case KF_MODE_EXHAUSTIVE:
-                return set_error(KF_ERR_UNSUPPORTED,
-                                 "learned and exhaustive ranking need device buffers: use kf_candidates, "
-                                 "kf_planset_features / kf_time_plan and compile the chosen candidate");
+                return kf::compile_exhaustive(s, o, out);
             default: return set_error(KF_ERR_ARG, "unknown mode");
         }
         return build_plan(s->s, part, o, out);

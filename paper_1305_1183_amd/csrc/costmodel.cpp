@@ -4,8 +4,12 @@
 // in the kernels of kf_mlp.hip.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <memory>
+#include <new>
 #include <vector>
 
 #include "kf_internal.h"
@@ -181,3 +185,273 @@ kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float*
 }
 
 }  // extern "C"
+
+// ---- the cost model object: network, its device state and the normalisation
+struct kf_costmodel {
+    kf_mlp* m = nullptr;
+    uint64_t seed = 0;
+    float* d_params = nullptr;
+    float* d_grads = nullptr;
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    float* d_ws = nullptr;
+    float* d_x = nullptr;
+    float* d_y = nullptr;
+    float* d_out = nullptr;
+    size_t ws_cap = 0;   // floats of d_ws
+    long rows_cap = 0;   // rows of d_x, d_y, d_out
+    std::vector<float> mu, sd;
+    double y_mu = 0.0, y_sd = 1.0;
+    float launch_us = 0.f;
+    ~kf_costmodel() {
+        for (float* p : {d_params, d_grads, d_m, d_v, d_ws, d_x, d_y, d_out})
+            if (p) hipFree(p);
+        if (m) kf_mlp_destroy(m);
+    }
+};
+
+namespace {
+
+const int kPredictChunk = 8192;
+
+kf_status cm_reserve(kf_costmodel* cm, long rows) {
+    if (rows <= cm->rows_cap) return KF_OK;
+    for (float** p : {&cm->d_ws, &cm->d_x, &cm->d_y, &cm->d_out})
+        if (*p) { hipFree(*p); *p = nullptr; }
+    cm->ws_cap = ws_floats(cm->m, rows);
+    HIPCHK(hipMalloc((void**)&cm->d_ws, cm->ws_cap * sizeof(float)));
+    HIPCHK(hipMalloc((void**)&cm->d_x, (size_t)rows * cm->m->d * sizeof(float)));
+    HIPCHK(hipMalloc((void**)&cm->d_y, (size_t)rows * sizeof(float)));
+    HIPCHK(hipMalloc((void**)&cm->d_out, (size_t)rows * sizeof(float)));
+    cm->rows_cap = rows;
+    return KF_OK;
+}
+
+uint64_t splitmix(uint64_t& state) {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+kf_status kf_costmodel_create(int32_t hidden, int32_t layers, uint64_t seed, kf_costmodel** out) {
+    if (!out) return set_error(KF_ERR_ARG, "null argument");
+    auto* cm = new (std::nothrow) kf_costmodel();
+    if (!cm) return set_error(KF_ERR_NOMEM, "host allocation failed");
+    std::unique_ptr<kf_costmodel> guard(cm);
+    kf_status s = kf_mlp_create(KF_FEATURE_DIM, hidden, layers, &cm->m);
+    if (s != KF_OK) return s;
+    cm->seed = seed;
+    cm->mu.assign(KF_FEATURE_DIM, 0.f);
+    cm->sd.assign(KF_FEATURE_DIM, 1.f);
+    std::vector<float> p((size_t)cm->m->nparams);
+    kf_mlp_init_params(cm->m, seed, p.data());
+    const size_t pb = p.size() * sizeof(float);
+    for (float** d : {&cm->d_params, &cm->d_grads, &cm->d_m, &cm->d_v})
+        HIPCHK(hipMalloc((void**)d, pb));
+    HIPCHK(hipMemcpy(cm->d_params, p.data(), pb, hipMemcpyHostToDevice));
+    *out = guard.release();
+    return KF_OK;
+}
+
+void kf_costmodel_destroy(kf_costmodel* cm) { delete cm; }
+
+kf_status kf_costmodel_train(kf_costmodel* cm, const float* X, const float* y_log_us, int64_t n, int32_t epochs,
+                             int32_t batch, float lr, uint64_t seed, void* stream, float* loss_per_epoch) {
+    if (!cm || !X || !y_log_us || n < 2 || epochs < 1 || batch < 1 || !(lr > 0.f))
+        return set_error(KF_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int d = cm->m->d;
+    // feature and target standardisation from the training data
+    std::vector<double> mu(d, 0.0), var(d, 0.0);
+    double ym = 0.0, yv = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int j = 0; j < d; ++j) mu[j] += X[i * d + j];
+        ym += y_log_us[i];
+    }
+    for (int j = 0; j < d; ++j) mu[j] /= (double)n;
+    ym /= (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int j = 0; j < d; ++j) var[j] += (X[i * d + j] - mu[j]) * (X[i * d + j] - mu[j]);
+        yv += (y_log_us[i] - ym) * (y_log_us[i] - ym);
+    }
+    for (int j = 0; j < d; ++j) {
+        cm->mu[j] = (float)mu[j];
+        cm->sd[j] = (float)std::max(std::sqrt(var[j] / (double)n), 1e-3);
+    }
+    cm->y_mu = ym;
+    cm->y_sd = std::max(std::sqrt(yv / (double)n), 1e-6);
+    kf_status s = cm_reserve(cm, std::max<long>(batch, n));
+    if (s != KF_OK) return s;
+    const size_t pb = (size_t)cm->m->nparams * sizeof(float);
+    HIPCHK(hipMemsetAsync(cm->d_m, 0, pb, st));
+    HIPCHK(hipMemsetAsync(cm->d_v, 0, pb, st));
+    std::vector<int64_t> perm(n);
+    std::vector<float> xs((size_t)n * d), ys(n);
+    uint64_t rng = seed * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL;
+    int step = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int64_t i = 0; i < n; ++i) perm[i] = i;
+        for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(splitmix(rng) % (uint64_t)(i + 1))]);
+        for (int64_t i = 0; i < n; ++i) {
+            const float* src = X + perm[i] * d;
+            for (int j = 0; j < d; ++j) xs[i * d + j] = (src[j] - cm->mu[j]) / cm->sd[j];
+            ys[i] = (float)((y_log_us[perm[i]] - cm->y_mu) / cm->y_sd);
+        }
+        HIPCHK(hipMemcpyAsync(cm->d_x, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(cm->d_y, ys.data(), ys.size() * sizeof(float), hipMemcpyHostToDevice, st));
+        double tot = 0.0;
+        int cnt = 0;
+        for (int64_t b0 = 0; b0 < n; b0 += batch) {
+            const int b = (int)std::min<int64_t>(batch, n - b0);
+            ++step;
+            s = kf_mlp_loss_grad(cm->m, cm->d_params, cm->d_x + b0 * d, cm->d_y + b0, b, cm->d_grads, cm->d_out,
+                                 cm->d_ws, cm->ws_cap * sizeof(float), stream);
+            if (s != KF_OK) return s;
+            s = kf_mlp_adam(cm->m, cm->d_params, cm->d_grads, cm->d_m, cm->d_v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+            if (s != KF_OK) return s;
+            float l = 0.f;
+            HIPCHK(hipMemcpyAsync(&l, cm->d_out, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            tot += l;
+            ++cnt;
+        }
+        if (loss_per_epoch) loss_per_epoch[ep] = (float)(tot / std::max(cnt, 1));
+    }
+    return KF_OK;
+}
+
+kf_status kf_costmodel_predict(kf_costmodel* cm, const float* X, int64_t n, float* log_us, void* stream) {
+    if (!cm || !X || !log_us || n < 0) return set_error(KF_ERR_ARG, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int d = cm->m->d;
+    kf_status s = cm_reserve(cm, kPredictChunk);
+    if (s != KF_OK) return s;
+    std::vector<float> xs((size_t)kPredictChunk * d), out(kPredictChunk);
+    for (int64_t c0 = 0; c0 < n; c0 += kPredictChunk) {
+        const int c = (int)std::min<int64_t>(kPredictChunk, n - c0);
+        for (int64_t i = 0; i < c; ++i)
+            for (int j = 0; j < d; ++j) xs[i * d + j] = (X[(c0 + i) * d + j] - cm->mu[j]) / cm->sd[j];
+        HIPCHK(hipMemcpyAsync(cm->d_x, xs.data(), (size_t)c * d * sizeof(float), hipMemcpyHostToDevice, st));
+        s = kf_mlp_forward(cm->m, cm->d_params, cm->d_x, c, cm->d_out, cm->d_ws, cm->ws_cap * sizeof(float), stream);
+        if (s != KF_OK) return s;
+        HIPCHK(hipMemcpyAsync(out.data(), cm->d_out, (size_t)c * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < c; ++i) log_us[c0 + i] = (float)(out[i] * cm->y_sd + cm->y_mu);
+    }
+    return KF_OK;
+}
+
+kf_status kf_costmodel_set_launch_us(kf_costmodel* cm, float us) {
+    if (!cm || !(us >= 0.f)) return set_error(KF_ERR_ARG, "bad argument");
+    cm->launch_us = us;
+    return KF_OK;
+}
+
+kf_status kf_costmodel_get(const kf_costmodel* cm, float* params, float* mu, float* sd, double* y_mu_sd,
+                           float* launch_us) {
+    if (!cm) return set_error(KF_ERR_ARG, "null model");
+    if (params && hipMemcpy(params, cm->d_params, (size_t)cm->m->nparams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
+        return set_error(KF_ERR_HIP, "reading the model parameters failed");
+    if (mu) std::memcpy(mu, cm->mu.data(), cm->mu.size() * sizeof(float));
+    if (sd) std::memcpy(sd, cm->sd.data(), cm->sd.size() * sizeof(float));
+    if (y_mu_sd) { y_mu_sd[0] = cm->y_mu; y_mu_sd[1] = cm->y_sd; }
+    if (launch_us) *launch_us = cm->launch_us;
+    return KF_OK;
+}
+
+kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* mu, const float* sd,
+                           const double* y_mu_sd, float launch_us) {
+    if (!cm || !params || !mu || !sd || !y_mu_sd || !(y_mu_sd[1] > 0.0)) return set_error(KF_ERR_ARG, "bad argument");
+    for (int j = 0; j < cm->m->d; ++j)
+        if (!(sd[j] > 0.f)) return set_error(KF_ERR_ARG, "feature scales must be positive");
+    if (hipMemcpy(cm->d_params, params, (size_t)cm->m->nparams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return set_error(KF_ERR_HIP, "writing the model parameters failed");
+    cm->mu.assign(mu, mu + cm->m->d);
+    cm->sd.assign(sd, sd + cm->m->d);
+    cm->y_mu = y_mu_sd[0];
+    cm->y_sd = y_mu_sd[1];
+    cm->launch_us = launch_us;
+    return KF_OK;
+}
+
+// File: "KFCM" magic, int32 version 1, int32 feature dim, hidden, layers,
+// int64 parameter count, float mu[d], sd[d], double y_mu, y_sd, float
+// launch_us, float params[]; little-endian, as the host writes them.
+kf_status kf_costmodel_save(const kf_costmodel* cm, const char* path) {
+    if (!cm || !path) return set_error(KF_ERR_ARG, "null argument");
+    std::vector<float> p((size_t)cm->m->nparams);
+    kf_status s = kf_costmodel_get(cm, p.data(), nullptr, nullptr, nullptr, nullptr);
+    if (s != KF_OK) return s;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return set_error(KF_ERR_ARG, std::string("cannot write ") + path);
+    const int32_t hdr[4] = {1, cm->m->d, cm->m->h, cm->m->L};
+    const int64_t np = cm->m->nparams;
+    const double y[2] = {cm->y_mu, cm->y_sd};
+    bool ok = std::fwrite("KFCM", 1, 4, f) == 4 && std::fwrite(hdr, 4, 4, f) == 4 && std::fwrite(&np, 8, 1, f) == 1 &&
+              std::fwrite(cm->mu.data(), 4, cm->mu.size(), f) == cm->mu.size() &&
+              std::fwrite(cm->sd.data(), 4, cm->sd.size(), f) == cm->sd.size() && std::fwrite(y, 8, 2, f) == 2 &&
+              std::fwrite(&cm->launch_us, 4, 1, f) == 1 && std::fwrite(p.data(), 4, p.size(), f) == p.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? KF_OK : set_error(KF_ERR_ARG, std::string("write failed: ") + path);
+}
+
+kf_status kf_costmodel_load(const char* path, kf_costmodel** out) {
+    if (!path || !out) return set_error(KF_ERR_ARG, "null argument");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(KF_ERR_ARG, std::string("cannot read ") + path);
+    char magic[4] = {0};
+    int32_t hdr[4] = {0};
+    int64_t np = 0;
+    bool ok = std::fread(magic, 1, 4, f) == 4 && std::memcmp(magic, "KFCM", 4) == 0 && std::fread(hdr, 4, 4, f) == 4 &&
+              hdr[0] == 1 && hdr[1] == KF_FEATURE_DIM && std::fread(&np, 8, 1, f) == 1;
+    kf_costmodel* cm = nullptr;
+    if (ok && kf_costmodel_create(hdr[2], hdr[3], 0, &cm) != KF_OK) ok = false;
+    std::unique_ptr<kf_costmodel> guard(cm);
+    std::vector<float> mu(KF_FEATURE_DIM), sd(KF_FEATURE_DIM), p;
+    double y[2] = {0, 1};
+    float lu = 0.f;
+    if (ok && np != cm->m->nparams) ok = false;
+    if (ok) {
+        p.resize((size_t)np);
+        ok = std::fread(mu.data(), 4, mu.size(), f) == mu.size() && std::fread(sd.data(), 4, sd.size(), f) == sd.size() &&
+             std::fread(y, 8, 2, f) == 2 && std::fread(&lu, 4, 1, f) == 1 && std::fread(p.data(), 4, p.size(), f) == p.size();
+    }
+    std::fclose(f);
+    if (!ok) return set_error(KF_ERR_ARG, std::string("not a cost-model file of this library: ") + path);
+    kf_status s = kf_costmodel_set(cm, p.data(), mu.data(), sd.data(), y, lu);
+    if (s != KF_OK) return s;
+    *out = guard.release();
+    return KF_OK;
+}
+
+kf_status kf_costmodel_dims(const kf_costmodel* cm, int32_t* hidden, int32_t* layers, int64_t* nparams) {
+    if (!cm) return set_error(KF_ERR_ARG, "null model");
+    if (hidden) *hidden = cm->m->h;
+    if (layers) *layers = cm->m->L;
+    if (nparams) *nparams = cm->m->nparams;
+    return KF_OK;
+}
+
+}  // extern "C"
+
+namespace kf {
+// Predicted times (us) of plans given as per-kernel feature rows: plan i owns
+// rows [start[i], start[i + 1]); time = sum exp(prediction) + launch_us * launches.
+kf_status costmodel_plan_us(kf_costmodel* cm, const std::vector<float>& feats, const std::vector<size_t>& start,
+                            hipStream_t st, std::vector<double>* us) {
+    const size_t rows = feats.size() / KF_FEATURE_DIM;
+    std::vector<float> lg(rows);
+    kf_status s = kf_costmodel_predict(cm, feats.data(), (int64_t)rows, lg.data(), st);
+    if (s != KF_OK) return s;
+    us->assign(start.size() - 1, 0.0);
+    for (size_t i = 0; i + 1 < start.size(); ++i)
+        for (size_t r = start[i]; r < start[i + 1]; ++r)
+            (*us)[i] += std::exp((double)lg[r]) + cm->launch_us * feats[r * KF_FEATURE_DIM + 25];
+    return KF_OK;
+}
+}  // namespace kf

@@ -6,6 +6,7 @@
 #include <array>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <set>
 
 #include "kf_internal.h"
@@ -194,16 +195,18 @@ kf_compile_opts cand_opts(const kf_planset* ps, int i) {
     return o;
 }
 
-// Default parameter points: the autotuner's best points for large shapes.
+// Default parameter points: the library's shape-dependent defaults (all zero),
+// the autotuner's best points for large shapes, and the row-resident schedule.
 std::vector<kf_compile_opts> default_grid() {
     std::vector<kf_compile_opts> g;
-    const int mat[][4] = {{1, 4, 4, 1024}, {2, 8, 2, 1024}, {1, 4, 4, 256}, {2, 4, 4, 512}};
-    const int vec[][3] = {{4, 256, 2048}, {4, 256, 4096}, {2, 256, 1024}};
+    const int mat[][5] = {{0, 0, 0, 0, 0}, {1, 4, 4, 1024, 0}, {2, 8, 2, 1024, 0}, {1, 4, 4, 256, 0},
+                          {2, 4, 4, 512, 0}, {0, 8, 2, 0, 1}};
+    const int vec[][3] = {{0, 0, 0}, {4, 256, 2048}, {4, 256, 4096}, {2, 256, 1024}};
     for (auto& m : mat)
         for (auto& v : vec) {
             kf_compile_opts o;
             kf_compile_opts_init(&o);
-            o.mat_k = m[0]; o.mat_waves = m[1]; o.mat_group = m[2]; o.mat_rows = m[3];
+            o.mat_k = m[0]; o.mat_waves = m[1]; o.mat_group = m[2]; o.mat_rows = m[3]; o.mat_sched = m[4];
             o.vec_unroll = v[0]; o.vec_threads = v[1]; o.vec_grid = v[2];
             g.push_back(o);
         }
@@ -232,7 +235,7 @@ kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_com
         for (const auto& part : parts)
             for (const auto& go : g) {
                 kf_compile_opts o = go;
-                if (!has_mat) o.mat_k = o.mat_waves = o.mat_group = o.mat_rows = 0;
+                if (!has_mat) o.mat_k = o.mat_waves = o.mat_group = o.mat_rows = o.mat_sched = 0;
                 if (!has_vec) o.vec_unroll = o.vec_threads = o.vec_grid = 0;
                 o.mode = KF_MODE_PARTITION;
                 o.partition = part.data();
@@ -355,3 +358,132 @@ kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan
     if (best < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be predicted with this routine table");
     return kf_planset_compile(ps, best, o.flags, out);
 }
+
+// ---- learned and empirical ranking inside kf_compile -------------------------
+namespace kf {
+
+kf_status costmodel_plan_us(kf_costmodel* cm, const std::vector<float>& feats, const std::vector<size_t>& start,
+                            hipStream_t st, std::vector<double>* us);
+
+namespace {
+
+// Times candidates of a planset with the caller's buffers; the workspace is
+// allocated here and grown as candidates need it.
+struct Timer {
+    const kf_planset* ps;
+    const kf_compile_opts& o;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Timer(const kf_planset* p, const kf_compile_opts& opts) : ps(p), o(opts) {}
+    ~Timer() {
+        if (ws) hipFree(ws);
+    }
+    kf_status time(int32_t i, float* us) {
+        kf_plan* p = nullptr;
+        kf_status s = kf_planset_compile(ps, i, 0, &p);
+        if (s != KF_OK) return s;
+        std::unique_ptr<kf_plan, void (*)(kf_plan*)> guard(p, kf_plan_destroy);
+        for (int b = 0; b < o.bind_len; ++b) {
+            s = kf_bind(p, o.bind_values[b], o.bind_ptrs[b]);
+            if (s != KF_OK) return s;
+        }
+        size_t need = 0;
+        kf_plan_workspace_bytes(p, &need);
+        if (need > ws_bytes) {
+            if (ws) hipFree(ws);
+            ws = nullptr;
+            ws_bytes = 0;
+            if (hipMalloc(&ws, need) != hipSuccess) return set_error(KF_ERR_HIP, "hipMalloc of the timing workspace failed");
+            ws_bytes = need;
+        }
+        if (need) {
+            s = kf_bind_workspace(p, ws, ws_bytes);
+            if (s != KF_OK) return s;
+        }
+        return kf_time_plan(p, o.stream, 2, 5, us);
+    }
+};
+
+kf_status candidates_for(const kf_script* s, const kf_compile_opts& o, kf_planset** ps) {
+    return kf_candidates(s, o.max_partitions, o.grid_len > 0 ? o.grid : nullptr, o.grid_len > 0 ? o.grid_len : 0, ps);
+}
+
+// Among `order` (candidate indices), the fastest measured; ties within 0.1%
+// keep the earlier one.
+kf_status fastest_measured(const kf_planset* ps, const kf_compile_opts& o, const std::vector<int32_t>& order,
+                           int32_t* best) {
+    if (!o.bind_values || !o.bind_ptrs || o.bind_len < 1)
+        return set_error(KF_ERR_UNBOUND, "timing candidates needs the buffers of opts.bind_values / bind_ptrs");
+    kf_planset_precompile(ps, order.data(), (int32_t)order.size());
+    Timer t(ps, o);
+    float best_us = 0.f;
+    *best = -1;
+    for (int32_t i : order) {
+        float us = 0.f;
+        kf_status s = t.time(i, &us);
+        if (s == KF_ERR_HIP || s == KF_ERR_UNBOUND || s == KF_ERR_ALIGN || s == KF_ERR_ALIAS) return s;
+        if (s != KF_OK) continue;
+        if (*best < 0 || us < best_us * 0.999f) {
+            *best = i;
+            best_us = us;
+        }
+    }
+    if (*best < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");
+    return KF_OK;
+}
+
+}  // namespace
+
+kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {
+    if (!o.model) return set_error(KF_ERR_ARG, "KF_MODE_LEARNED needs opts.model");
+    kf_planset* ps = nullptr;
+    kf_status st = candidates_for(s, o, &ps);
+    if (st != KF_OK) return st;
+    std::unique_ptr<kf_planset> guard(ps);
+    std::vector<float> feats;
+    std::vector<size_t> start{0};
+    std::vector<int32_t> ok;
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        kf_plan* p = nullptr;
+        if (kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p) != KF_OK) continue;
+        int32_t nk = 0;
+        kf_plan_features(p, nullptr, 0, &nk);
+        const size_t at = feats.size();
+        feats.resize(at + (size_t)nk * KF_FEATURE_DIM);
+        kf_plan_features(p, feats.data() + at, nk, &nk);
+        kf_plan_destroy(p);
+        start.push_back(feats.size() / KF_FEATURE_DIM);
+        ok.push_back((int32_t)i);
+    }
+    if (ok.empty()) return set_error(KF_ERR_UNSUPPORTED, "no candidate plan");
+    std::vector<double> us;
+    st = costmodel_plan_us(const_cast<kf_costmodel*>(o.model), feats, start, (hipStream_t)o.stream, &us);
+    if (st != KF_OK) return st;
+    // stable order by prediction; within 0.1% the earlier (fewer kernels) first
+    std::vector<size_t> order(ok.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return us[a] < us[b] * 0.999; });
+    int32_t best = ok[order[0]];
+    if (o.top_k > 1) {
+        std::vector<int32_t> top;
+        for (size_t j = 0; j < order.size() && (int)j < o.top_k; ++j) top.push_back(ok[order[j]]);
+        st = fastest_measured(ps, o, top, &best);
+        if (st != KF_OK) return st;
+    }
+    return kf_planset_compile(ps, best, o.flags, out);
+}
+
+kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {
+    kf_planset* ps = nullptr;
+    kf_status st = candidates_for(s, o, &ps);
+    if (st != KF_OK) return st;
+    std::unique_ptr<kf_planset> guard(ps);
+    std::vector<int32_t> all(ps->parts.size());
+    std::iota(all.begin(), all.end(), 0);
+    int32_t best = -1;
+    st = fastest_measured(ps, o, all, &best);
+    if (st != KF_OK) return st;
+    return kf_planset_compile(ps, best, o.flags, out);
+}
+
+}  // namespace kf

@@ -61,7 +61,9 @@ kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("mat_sched", _i32),
                             ("partition", _P(_i32)), ("partition_len", _i32),
                             ("table", _P(kf_routine_entry)), ("table_len", _i32), ("max_partitions", _i32),
-                            ("grid", _P(kf_compile_opts)), ("grid_len", _i32), ("mat_unit", _i32)]
+                            ("grid", _P(kf_compile_opts)), ("grid_len", _i32), ("mat_unit", _i32),
+                            ("model", _vp), ("stream", _vp), ("bind_values", _P(_i32)), ("bind_ptrs", _P(_vp)),
+                            ("bind_len", _i32), ("top_k", _i32)]
 PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
                 "mat_sched", "mat_unit"]
 
@@ -133,6 +135,16 @@ _SIGS = {
     "kf_mlp_loss_grad": ([_vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _sz, _vp], _i32),
     "kf_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _vp], _i32),
     "kf_jit_stats": ([_P(_i64), _P(_i64)], _i32),
+    "kf_costmodel_create": ([_i32, _i32, _u64, _P(_vp)], _i32),
+    "kf_costmodel_destroy": ([_vp], None),
+    "kf_costmodel_train": ([_vp, _P(_f32), _P(_f32), _i64, _i32, _i32, _f32, _u64, _vp, _P(_f32)], _i32),
+    "kf_costmodel_predict": ([_vp, _P(_f32), _i64, _P(_f32), _vp], _i32),
+    "kf_costmodel_set_launch_us": ([_vp, _f32], _i32),
+    "kf_costmodel_get": ([_vp, _P(_f32), _P(_f32), _P(_f32), _P(ctypes.c_double), _P(_f32)], _i32),
+    "kf_costmodel_set": ([_vp, _P(_f32), _P(_f32), _P(_f32), _P(ctypes.c_double), _f32], _i32),
+    "kf_costmodel_dims": ([_vp, _P(_i32), _P(_i32), _P(_i64)], _i32),
+    "kf_costmodel_save": ([_vp, ctypes.c_char_p], _i32),
+    "kf_costmodel_load": ([ctypes.c_char_p, _P(_vp)], _i32),
     "kf_batch_create": ([_i64, _P(_i32), _P(_i64), _P(_f32), _P(_f32), _vp, _P(_vp)], _i32),
     "kf_batch_destroy": ([_vp], None),
     "kf_batch_arena_elems": ([_vp, _P(_i64)], _i32),
@@ -281,12 +293,20 @@ def kf_script_call(s, i: int) -> dict:
 
 # ---- compile / enumerate --------------------------------------------------------
 def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid=None, max_partitions=0,
-                         **params) -> kf_compile_opts:
+                         model=None, stream=None, bind=None, top_k=0, **params) -> kf_compile_opts:
+    """bind: {script value handle: device pointer} of every input and output
+    (timing in the learned top-k and exhaustive modes); model: a cost-model
+    handle (kf_costmodel_create / kf_costmodel_load)."""
     o = kf_compile_opts()
     lib().kf_compile_opts_init(ctypes.byref(o))
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.flags = flags
     o.max_partitions = max_partitions
+    o.top_k = int(top_k)
+    if model is not None:
+        o.model = model
+    if stream is not None:
+        o.stream = stream
     for k, v in params.items():
         if k not in PARAM_FIELDS:
             raise TypeError("unknown compile option %s" % k)
@@ -301,12 +321,19 @@ def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid
         o.grid = ctypes.cast(garr, _P(kf_compile_opts))
         o.grid_len = len(garr)
         keep.append(garr)
-    o._keep = keep
+    if bind:
+        vals = (_i32 * len(bind))(*[int(k) for k in bind])
+        ptrs = (_vp * len(bind))(*[int(v) for v in bind.values()])
+        o.bind_values = ctypes.cast(vals, _P(_i32))
+        o.bind_ptrs = ctypes.cast(ptrs, _P(_vp))
+        o.bind_len = len(bind)
+        keep += [vals, ptrs]
     if partition is not None:
         arr = (_i32 * len(partition))(*partition)
         o.partition = ctypes.cast(arr, _P(_i32))
         o.partition_len = len(partition)
-        o._keep = arr  # keep the array alive with the struct
+        keep.append(arr)
+    o._keep = keep  # keep the arrays alive with the struct
     return o
 
 

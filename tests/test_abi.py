@@ -221,3 +221,14 @@ def test_values_written_only_when_needed():
     assert kf.kf_plan_workspace_bytes(pu) >= 64 * 64 * 4
     src = kf.kf_plan_source(pf, 0)
     assert src.count("kf_st4_nt(O") == 1     # only B is stored, not B1
+
+
+def test_ranking_modes_check_their_inputs():
+    """Learned mode without a model and exhaustive mode without buffers are
+    refused before any GPU work."""
+    from paper_1305_1183_amd import sequences as S
+    q = S.bicgk(64, 64)
+    with pytest.raises(kf.KFError, match="KF_ERR_ARG"):
+        kf.kf_compile(q.script, mode="learned")
+    with pytest.raises(kf.KFError, match="KF_ERR_UNBOUND"):
+        kf.kf_compile(q.script, mode="exhaustive")

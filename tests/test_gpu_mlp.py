@@ -82,7 +82,7 @@ def test_training_converges_and_is_deterministic():
     for _ in range(2):
         cm = CostModel(seed=1)
         hist = cm.fit(X, y, epochs=60, batch=256, lr=2e-3, seed=2)
-        runs.append((hist, cm.params.cpu().numpy()))
+        runs.append((hist, cm.state()[0]))
     assert runs[0][0][-1] < 0.1 * runs[0][0][0], runs[0][0][::10]
     assert np.array_equal(runs[0][1], runs[1][1])
     pred = cm.predict_log(X[:256])
