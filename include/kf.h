@@ -186,7 +186,7 @@ typedef struct kf_compile_opts {
      * bind_values[i] (every input and output, as for kf_bind; the inputs are
      * read, the outputs overwritten). The library allocates and frees the
      * timing workspace itself. */
-    const struct kf_costmodel* model;
+    struct kf_costmodel* model;
     void* stream;
     const int32_t* bind_values;
     void* const* bind_ptrs;

@@ -14,24 +14,12 @@ __global__ void kf_fill_u32_kernel(unsigned* __restrict__ p, size_t n, unsigned 
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-// dst[i] = src[i] over n float4 elements: each thread keeps four 16-byte
-// loads in flight (elements i, i + S, i + 2S, i + 3S for a stride S of the
-// whole grid) before storing them, then a grid-stride tail.
+// dst[i] = src[i] over n float4 elements, grid-stride.
 __global__ void __launch_bounds__(256) kf_copy_f4_kernel(f4_t* __restrict__ dst,
                                                          const f4_t* __restrict__ src, size_t n) {
-    const size_t S = (size_t)gridDim.x * blockDim.x;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * S < n; i += 4 * S) {
-        const f4_t a = __builtin_nontemporal_load(src + i);
-        const f4_t b = __builtin_nontemporal_load(src + i + S);
-        const f4_t c = __builtin_nontemporal_load(src + i + 2 * S);
-        const f4_t d = __builtin_nontemporal_load(src + i + 3 * S);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + S);
-        __builtin_nontemporal_store(c, dst + i + 2 * S);
-        __builtin_nontemporal_store(d, dst + i + 3 * S);
-    }
-    for (; i < n; i += S) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // Seeded uniform[-1, 1) input values: element (i, j) of a rows x cols block
@@ -81,7 +69,7 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
     size_t n = bytes / 16;
     if (n == 0) return hipSuccess;
     size_t grid = (n + 255) / 256;
-    if (grid > 4096) grid = 4096;
+    if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(kf_copy_f4_kernel, dim3((unsigned)grid), dim3(256), 0, st, (f4_t*)dst,
                        (const f4_t*)src, n);
     return hipGetLastError();

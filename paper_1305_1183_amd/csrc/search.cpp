@@ -457,7 +457,7 @@ kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan*
     }
     if (ok.empty()) return set_error(KF_ERR_UNSUPPORTED, "no candidate plan");
     std::vector<double> us;
-    st = costmodel_plan_us(const_cast<kf_costmodel*>(o.model), feats, start, (hipStream_t)o.stream, &us);
+    st = costmodel_plan_us(o.model, feats, start, (hipStream_t)o.stream, &us);
     if (st != KF_OK) return st;
     // stable order by prediction; within 0.1% the earlier (fewer kernels) first
     std::vector<size_t> order(ok.size());

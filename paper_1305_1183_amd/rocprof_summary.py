@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=1 << 30)
     ap.add_argument("--out-dir", default="profiles")
     ap.add_argument("--tag", required=True)
+    ap.add_argument("--pmc-out", default="pmc_summary.json")
+    ap.add_argument("--pmc-match", default="kf_", help="kernels whose name contains this are kept")
     ap.add_argument("--by-grid", default="",
                     help="kernels whose name contains this are listed per grid size, from the dispatch trace")
     ap.add_argument("--cmd", default="")
@@ -90,7 +92,7 @@ def main():
         sw = a.copy_bytes / (copy_w * 1024.0)
         kernels = {}
         for (k, c), (v, n) in fe.items():
-            if c != "FETCH_SIZE" or not k.startswith("kf_"):
+            if c != "FETCH_SIZE" or a.pmc_match not in k:
                 continue
             w = wr.get((k, "WRITE_SIZE"), (0.0, 0))[0]
             kernels[k] = {"fetch_kib": round(v, 1), "write_kib": round(w, 1), "dispatches": n,
@@ -101,7 +103,7 @@ def main():
                                "copy_write_kib": round(copy_w, 1), "fetch_scale": round(sf, 4),
                                "write_scale": round(sw, 4)},
                "kernels": kernels}
-        path = os.path.join(a.out_dir, "pmc_summary.json")
+        path = os.path.join(a.out_dir, a.pmc_out)
         with open(path, "w") as f:
             json.dump(out, f, indent=1, sort_keys=True)
             f.write("\n")

@@ -112,18 +112,21 @@ def tuned_params(name: str, m: int, n: int, mode: str = "fused") -> dict:
     return dict(TUNED.get((name, mode), {})) if suite else {}
 
 
-def traffic_from_profiles(profile_dir: str, kernel_name: str):
+def traffic_from_profiles(profile_dir: str, kernel_name: str, batched: bool = False):
     """HBM bytes per launch of `kernel_name` from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by the same counters of
     a streaming copy of known size), or None when the summary does not cover
     this exact kernel text (the name is a hash of it)."""
     import json
     import os
-    path = os.path.join(profile_dir, "pmc_summary.json")
+    path = os.path.join(profile_dir, "pmc_summary_batched.json" if batched else "pmc_summary.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    k = d.get("kernels", {}).get(kernel_name)
+    ks = d.get("kernels", {})
+    k = ks.get(kernel_name)
+    if k is None and batched:       # the batched kernel's record carries its full signature
+        k = next((v for name, v in ks.items() if kernel_name in name), None)
     if not k:
         return None
     return int(round(k["fetch_bytes_scaled"] + k["write_bytes_scaled"]))
@@ -136,6 +139,15 @@ PREC_SEQ = ("bicgk", "gemver")
 
 
 PREC_PANEL = 512
+# tuned fused-plan parameters per (sequence, storage format) at n = 32768
+PREC_TUNED = {
+    ("bicgk", "f32"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+    ("bicgk", "bf16"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+    ("bicgk", "fp8"): dict(mat_k=2, mat_waves=4, mat_group=4, mat_rows=1024),
+    ("gemver", "f32"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+    ("gemver", "bf16"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256),
+    ("gemver", "fp8"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+}
 
 
 def normal_panel(seed: int, n: int, r0: int, panel: int = PREC_PANEL) -> np.ndarray:
