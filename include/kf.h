@@ -397,7 +397,7 @@ kf_status kf_costmodel_get(const kf_costmodel* cm, float* params, float* mu, flo
 kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* mu, const float* sd,
                            const double* y_mu_sd, float launch_us);
 kf_status kf_costmodel_dims(const kf_costmodel* cm, int32_t* hidden, int32_t* layers, int64_t* nparams);
-/* Binary file of the model ("KFCM", version 1); load creates a new model. */
+/* Binary file of the model ("KFCM", version 2, with a checksum); load creates a new model. */
 kf_status kf_costmodel_save(const kf_costmodel* cm, const char* path);
 kf_status kf_costmodel_load(const char* path, kf_costmodel** out);
 

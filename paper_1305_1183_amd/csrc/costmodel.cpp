@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <string>
 #include <new>
 #include <vector>
 
@@ -205,7 +206,7 @@ struct kf_costmodel {
     float launch_us = 0.f;
     ~kf_costmodel() {
         for (float* p : {d_params, d_grads, d_m, d_v, d_ws, d_x, d_y, d_out})
-            if (p) hipFree(p);
+            if (p) (void)hipFree(p);
         if (m) kf_mlp_destroy(m);
     }
 };
@@ -217,7 +218,7 @@ const int kPredictChunk = 8192;
 kf_status cm_reserve(kf_costmodel* cm, long rows) {
     if (rows <= cm->rows_cap) return KF_OK;
     for (float** p : {&cm->d_ws, &cm->d_x, &cm->d_y, &cm->d_out})
-        if (*p) { hipFree(*p); *p = nullptr; }
+        if (*p) { (void)hipFree(*p); *p = nullptr; }
     cm->ws_cap = ws_floats(cm->m, rows);
     HIPCHK(hipMalloc((void**)&cm->d_ws, cm->ws_cap * sizeof(float)));
     HIPCHK(hipMalloc((void**)&cm->d_x, (size_t)rows * cm->m->d * sizeof(float)));
@@ -379,23 +380,44 @@ kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* m
     return KF_OK;
 }
 
-// File: "KFCM" magic, int32 version 1, int32 feature dim, hidden, layers,
+// File: "KFCM" magic, int32 version 2, int32 feature dim, hidden, layers,
 // int64 parameter count, float mu[d], sd[d], double y_mu, y_sd, float
-// launch_us, float params[]; little-endian, as the host writes them.
+// launch_us, float params[], then the FNV-1a 64 hash of everything after the
+// magic; little-endian, as the host writes them. load checks magic, version,
+// sizes and hash before it touches the GPU.
+namespace {
+uint64_t fnv64(const char* p, size_t n) {
+    uint64_t h = 1469598103934665603ULL;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= (unsigned char)p[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+void put_bytes(std::string& b, const void* v, size_t bytes) { b.append(static_cast<const char*>(v), bytes); }
+}  // namespace
+
 kf_status kf_costmodel_save(const kf_costmodel* cm, const char* path) {
     if (!cm || !path) return set_error(KF_ERR_ARG, "null argument");
     std::vector<float> p((size_t)cm->m->nparams);
     kf_status s = kf_costmodel_get(cm, p.data(), nullptr, nullptr, nullptr, nullptr);
     if (s != KF_OK) return s;
-    FILE* f = std::fopen(path, "wb");
-    if (!f) return set_error(KF_ERR_ARG, std::string("cannot write ") + path);
-    const int32_t hdr[4] = {1, cm->m->d, cm->m->h, cm->m->L};
+    std::string b;
+    const int32_t hdr[4] = {2, cm->m->d, cm->m->h, cm->m->L};
     const int64_t np = cm->m->nparams;
     const double y[2] = {cm->y_mu, cm->y_sd};
-    bool ok = std::fwrite("KFCM", 1, 4, f) == 4 && std::fwrite(hdr, 4, 4, f) == 4 && std::fwrite(&np, 8, 1, f) == 1 &&
-              std::fwrite(cm->mu.data(), 4, cm->mu.size(), f) == cm->mu.size() &&
-              std::fwrite(cm->sd.data(), 4, cm->sd.size(), f) == cm->sd.size() && std::fwrite(y, 8, 2, f) == 2 &&
-              std::fwrite(&cm->launch_us, 4, 1, f) == 1 && std::fwrite(p.data(), 4, p.size(), f) == p.size();
+    put_bytes(b, hdr, 16);
+    put_bytes(b, &np, 8);
+    put_bytes(b, cm->mu.data(), 4 * cm->mu.size());
+    put_bytes(b, cm->sd.data(), 4 * cm->sd.size());
+    put_bytes(b, y, 16);
+    put_bytes(b, &cm->launch_us, 4);
+    put_bytes(b, p.data(), 4 * p.size());
+    const uint64_t h = fnv64(b.data(), b.size());
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return set_error(KF_ERR_ARG, std::string("cannot write ") + path);
+    bool ok = std::fwrite("KFCM", 1, 4, f) == 4 && std::fwrite(b.data(), 1, b.size(), f) == b.size() &&
+              std::fwrite(&h, 8, 1, f) == 1;
     ok = (std::fclose(f) == 0) && ok;
     return ok ? KF_OK : set_error(KF_ERR_ARG, std::string("write failed: ") + path);
 }
@@ -404,26 +426,41 @@ kf_status kf_costmodel_load(const char* path, kf_costmodel** out) {
     if (!path || !out) return set_error(KF_ERR_ARG, "null argument");
     FILE* f = std::fopen(path, "rb");
     if (!f) return set_error(KF_ERR_ARG, std::string("cannot read ") + path);
-    char magic[4] = {0};
-    int32_t hdr[4] = {0};
-    int64_t np = 0;
-    bool ok = std::fread(magic, 1, 4, f) == 4 && std::memcmp(magic, "KFCM", 4) == 0 && std::fread(hdr, 4, 4, f) == 4 &&
-              hdr[0] == 1 && hdr[1] == KF_FEATURE_DIM && std::fread(&np, 8, 1, f) == 1;
-    kf_costmodel* cm = nullptr;
-    if (ok && kf_costmodel_create(hdr[2], hdr[3], 0, &cm) != KF_OK) ok = false;
-    std::unique_ptr<kf_costmodel> guard(cm);
-    std::vector<float> mu(KF_FEATURE_DIM), sd(KF_FEATURE_DIM), p;
-    double y[2] = {0, 1};
-    float lu = 0.f;
-    if (ok && np != cm->m->nparams) ok = false;
-    if (ok) {
-        p.resize((size_t)np);
-        ok = std::fread(mu.data(), 4, mu.size(), f) == mu.size() && std::fread(sd.data(), 4, sd.size(), f) == sd.size() &&
-             std::fread(y, 8, 2, f) == 2 && std::fread(&lu, 4, 1, f) == 1 && std::fread(p.data(), 4, p.size(), f) == p.size();
-    }
+    std::string d;
+    char buf[1 << 16];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) d.append(buf, got);
     std::fclose(f);
-    if (!ok) return set_error(KF_ERR_ARG, std::string("not a cost-model file of this library: ") + path);
-    kf_status s = kf_costmodel_set(cm, p.data(), mu.data(), sd.data(), y, lu);
+    const std::string bad = std::string("not a valid cost-model file of this library: ") + path;
+    const size_t head = 4 + 16 + 8;
+    if (d.size() < head + 8 || d.compare(0, 4, "KFCM") != 0) return set_error(KF_ERR_ARG, bad);
+    int32_t hdr[4];
+    int64_t np = 0;
+    std::memcpy(hdr, d.data() + 4, 16);
+    std::memcpy(&np, d.data() + 20, 8);
+    if (hdr[0] != 2 || hdr[1] != KF_FEATURE_DIM || hdr[2] < 1 || hdr[2] > 4096 || hdr[3] < 1 || hdr[3] > 16 ||
+        np < 1 || np > (int64_t)1 << 28)
+        return set_error(KF_ERR_ARG, bad);
+    const size_t body = head + 8 * (size_t)KF_FEATURE_DIM + 16 + 4 + 4 * (size_t)np;
+    if (d.size() != body + 8) return set_error(KF_ERR_ARG, bad);
+    uint64_t h = 0;
+    std::memcpy(&h, d.data() + body, 8);
+    if (fnv64(d.data() + 4, body - 4) != h) return set_error(KF_ERR_ARG, bad + " (checksum)");
+    std::vector<float> mu(KF_FEATURE_DIM), sd(KF_FEATURE_DIM), p((size_t)np);
+    double y[2];
+    float lu = 0.f;
+    size_t o = head;
+    std::memcpy(mu.data(), d.data() + o, 4 * mu.size()); o += 4 * mu.size();
+    std::memcpy(sd.data(), d.data() + o, 4 * sd.size()); o += 4 * sd.size();
+    std::memcpy(y, d.data() + o, 16); o += 16;
+    std::memcpy(&lu, d.data() + o, 4); o += 4;
+    std::memcpy(p.data(), d.data() + o, 4 * p.size());
+    kf_costmodel* cm = nullptr;
+    kf_status s = kf_costmodel_create(hdr[2], hdr[3], 0, &cm);
+    if (s != KF_OK) return s;
+    std::unique_ptr<kf_costmodel> guard(cm);
+    if (cm->m->nparams != np) return set_error(KF_ERR_ARG, bad);
+    s = kf_costmodel_set(cm, p.data(), mu.data(), sd.data(), y, lu);
     if (s != KF_OK) return s;
     *out = guard.release();
     return KF_OK;

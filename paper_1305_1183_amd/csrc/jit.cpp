@@ -11,6 +11,7 @@
 
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <mutex>
 #include <sstream>
@@ -41,7 +42,14 @@ static uint64_t fnv1a64(const std::string& s, uint64_t h = 1469598103934665603UL
     return h;
 }
 
-static std::string unit_text(const KernelCode& k) { return blocks_source() + "\n" + k.source; }
+// KF_JIT_EXTRA_SOURCE (debugging and tests): text appended to every generated
+// translation unit, e.g. instrumentation, or an #error to exercise the
+// compile-failure path. It is part of the text, so it is part of the cache key.
+static std::string unit_text(const KernelCode& k) {
+    std::string t = blocks_source() + "\n" + k.source;
+    if (const char* extra = std::getenv("KF_JIT_EXTRA_SOURCE")) t += std::string("\n") + extra + "\n";
+    return t;
+}
 
 static std::string cache_path(const std::string& text) {
     const char* dir = std::getenv("KF_CACHE_DIR");
@@ -53,13 +61,29 @@ static std::string cache_path(const std::string& text) {
     return std::string(dir) + name;
 }
 
+// Cached code objects are stored as "KFCO", the FNV-1a 64 hash of the code
+// object (8 bytes, host order) and the code object; a file that does not
+// check out (truncated, overwritten) is ignored and rebuilt.
 static bool read_file(const std::string& path, std::string* out) {
     std::ifstream f(path, std::ios::binary);
     if (!f) return false;
     std::ostringstream ss;
     ss << f.rdbuf();
-    *out = ss.str();
-    return !out->empty();
+    const std::string d = ss.str();
+    if (d.size() <= 12 || d.compare(0, 4, "KFCO") != 0) return false;
+    uint64_t h = 0;
+    std::memcpy(&h, d.data() + 4, 8);
+    std::string co = d.substr(12);
+    if (fnv1a64(co) != h) return false;
+    *out = std::move(co);
+    return true;
+}
+
+static std::string with_header(const std::string& co) {
+    const uint64_t h = fnv1a64(co);
+    std::string d = "KFCO";
+    d.append(reinterpret_cast<const char*>(&h), 8);
+    return d + co;
 }
 
 static void write_file_atomic(const std::string& path, const std::string& data) {
@@ -118,7 +142,7 @@ bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string*
     const std::string path = cache_path(text);
     if (!path.empty() && read_file(path, code_object)) return true;
     if (!rtc_compile(text, code_object, log)) return false;
-    if (!path.empty()) write_file_atomic(path, *code_object);
+    if (!path.empty()) write_file_atomic(path, with_header(*code_object));
     return true;
 }
 
@@ -136,8 +160,8 @@ bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log) 
             *log = "KF_CACHE_DIR is not set";
             return false;
         }
-        std::ifstream f(path, std::ios::binary);
-        if (f.good()) continue;
+        std::string have;
+        if (read_file(path, &have)) continue;
         bool dup = false;
         for (const std::string& q : paths)
             if (q == path) dup = true;
@@ -148,14 +172,16 @@ bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log) 
     if (todo.empty()) return true;
     std::string text = blocks_source() + "\n";
     for (const KernelCode* k : todo) text += k->source + "\n";
+    if (const char* extra = std::getenv("KF_JIT_EXTRA_SOURCE")) text += std::string(extra) + "\n";
     std::string co;
     if (!rtc_compile(text, &co, log)) return false;
     // one shared code object; every kernel's cache entry links to it
     std::string batch = paths[0] + ".batch";
-    write_file_atomic(batch, co);
+    const std::string stored = with_header(co);
+    write_file_atomic(batch, stored);
     for (const std::string& q : paths) {
         std::remove(q.c_str());
-        if (::link(batch.c_str(), q.c_str()) != 0) write_file_atomic(q, co);
+        if (::link(batch.c_str(), q.c_str()) != 0) write_file_atomic(q, stored);
     }
     std::remove(batch.c_str());
     return true;
