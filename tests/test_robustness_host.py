@@ -33,7 +33,7 @@ def _fnv(b):
 def test_damaged_cache_entry_is_rebuilt(monkeypatch, tmp_path):
     monkeypatch.setenv("KF_CACHE_DIR", str(tmp_path))
     monkeypatch.delenv("KF_JIT_EXTRA_SOURCE", raising=False)
-    q = S.waxpby(1000, 1.5, 0.5)
+    q = S.waxpby(12347, 1.25, 0.75)
     kf.kf_plan_destroy(kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD))
     files = glob.glob(os.path.join(str(tmp_path), "kf_*.co"))
     assert files
@@ -45,7 +45,7 @@ def test_damaged_cache_entry_is_rebuilt(monkeypatch, tmp_path):
             fh.write(b"\x00garbage\x00")
     # a fresh process (this one remembers what it compiled) finds the damaged entry
     code = ("import sys; sys.path.insert(0, %r); from paper_1305_1183_amd import kf, sequences as S; "
-            "q = S.waxpby(1000, 1.5, 0.5); "
+            "q = S.waxpby(12347, 1.25, 0.75); "
             "kf.kf_plan_destroy(kf.kf_compile(q.script, mode='fused', flags=kf.KF_COMPILE_NO_LOAD))"
             % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     env = dict(os.environ, KF_CACHE_DIR=str(tmp_path))
