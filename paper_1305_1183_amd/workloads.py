@@ -144,7 +144,7 @@ PREC_TUNED = {
     ("bicgk", "f32"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
     ("bicgk", "bf16"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
     ("bicgk", "fp8"): dict(mat_k=2, mat_waves=4, mat_group=4, mat_rows=1024),
-    ("gemver", "f32"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+    ("gemver", "f32"): {},   # the library defaults (k 1, 4 waves, 4 rows per step, 512 rows)
     ("gemver", "bf16"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256),
     ("gemver", "fp8"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
 }
