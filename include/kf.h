@@ -425,7 +425,8 @@ kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
  * Layout: the library places every operand of every instance in one float
  * arena that the caller allocates (kf_batch_arena_elems floats, 256-byte
  * aligned) and fills at the offsets kf_batch_offset reports. Matrices are row
- * major with row pitch ld = round_up(n, 4); padding columns are never read as
+ * major with row pitch ld = round_up(n, 32) (rows start on 128-byte lines);
+ * padding columns are never read as
  * data nor written. Operand ids: 0 = A, 1 = B (GEMVER output), then vectors
  * 2 + slot, BiCGK slots p, r, q, s and GEMVER slots u1, v1, u2, v2, y, z,
  * x, w (inputs first, then outputs; each n floats).

@@ -34,11 +34,12 @@ def make_instances(n_bicgk: int, n_gemver: int, seed: int, lo: int = 32, hi: int
     return kinds, ns, alpha, beta
 
 
-def instance_inputs(seed: int, i: int, kind: int, n: int):
-    """Operands of instance i: A (n x round_up(n, 4), NaN padding) and the
-    input vectors, from the streams (seed * 2^20 + i, tensor id)."""
+def instance_inputs(seed: int, i: int, kind: int, n: int, ld: int = 0):
+    """Operands of instance i: A (n x ld, NaN padding; ld = round_up(n, 32)
+    by default, the batch's row pitch) and the input vectors, from the streams
+    (seed * 2^20 + i, tensor id); values do not depend on ld."""
     s = int(seed) * (1 << 20) + int(i)
-    out = {"A": I.matrix(s, 0, n, n, ld=I.padded_ld(n))}
+    out = {"A": I.matrix(s, 0, n, n, ld=ld or I.padded_ld(n, 32))}
     for t, name in enumerate(INPUTS[kind]):
         out[name] = I.vector(s, 1 + t, n)
     return out
@@ -74,8 +75,8 @@ class Batch:
 
         def fill(i):
             n = int(self.ns[i])
-            vals = instance_inputs(seed, i, int(self.kinds[i]), n)
             off, ld = self.offset(i, "A")
+            vals = instance_inputs(seed, i, int(self.kinds[i]), n, ld)
             host[off:off + n * ld] = vals["A"].ravel()
             for name in INPUTS[int(self.kinds[i])]:
                 o, _ = self.offset(i, name)

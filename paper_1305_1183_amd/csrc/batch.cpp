@@ -119,7 +119,9 @@ kf_status kf_batch_create(int64_t count, const int32_t* kind, const int64_t* n, 
             std::memset(&I, 0, sizeof(I));
             I.kind = kind[i];
             I.n = (int32_t)n[i];
-            I.ld = (int32_t)((n[i] + 3) / 4 * 4);
+            // rows start on 128-byte lines, so no line holds the end of one row and
+            // the start of the next (stores of B and loads of A stay line-aligned)
+            I.ld = (int32_t)((n[i] + 31) / 32 * 32);
             I.bucket = kfb_bucket(I.n);
             I.rows = b->rows[I.kind][I.bucket];
             I.nblk = (I.n + I.rows - 1) / I.rows;

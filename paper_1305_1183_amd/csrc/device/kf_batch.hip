@@ -22,9 +22,12 @@
 // Every counter is returned to zero by the item or workgroup that uses it
 // last, so the launch can be replayed (e.g. from a graph) without clearing.
 //
-// Tile shape by size bucket: TPR = 2^LTPR lanes share a row (K float4 chunks
-// each), 256 / TPR rows are in flight per workgroup step, G = 2^LG steps are
-// loaded before their row sums are reduced.
+// Tile shape by size bucket. Up to n = 512: TPR = 2^LTPR lanes share a row (K
+// float4 chunks each), 256 / TPR rows are in flight per workgroup step, G =
+// 2^LG steps are loaded before their row sums are reduced. Above, BiCGK uses
+// the wide tiles, in which the four waves split the columns of each row
+// (below); GEMVER keeps whole rows per wave group there, which measured faster
+// for its B stores.
 #include <hip/hip_runtime.h>
 
 #include "device/kf_blocks.h"
@@ -192,6 +195,7 @@ __device__ __forceinline__ void kfb_reload_lds() { asm volatile("" ::: "memory")
 struct Shared {
     kf_f4 red[KFB_THREADS];
     kf_f4 cv[2][KFB_MAX_N / 4];
+    float rowp[2][4][16];   // wave partials of row sums, double-buffered (wide tiles)
     int flag;
     int item;
 };
@@ -205,6 +209,29 @@ __device__ __forceinline__ void kfb_stage(kf_f4* dst, const float* v, int n, int
 #pragma unroll
         for (int k = 0; k < K; ++k) dst[tid + k * TPR] = kfb_ldv(v, 4 * (tid + k * TPR), n);
     }
+}
+
+// Wait (thread 0, bounded) until the instance's x is published, then acquire.
+// Returns false in every thread if the wait ran out (error bit set).
+__device__ __forceinline__ bool kfb_wait_x(unsigned* ctr, unsigned* sync, unsigned spin_limit, Shared& sh) {
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
+            if (++spins > spin_limit) {
+                atomicOr(sync + KFB_SYNC_ERROR, KFB_ERR_SPIN);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+        }
+        kfb_acquire();
+        sh.flag = ok;
+    }
+    __syncthreads();
+    const bool ready = sh.flag != 0;
+    __syncthreads();
+    return ready;
 }
 
 // w rows r0 .. r1 - 1 of alpha B x, x given per thread at its columns.
@@ -404,28 +431,9 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
 template <int LTPR, int K, int LG>
 __device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ arena, unsigned* sync,
                               unsigned spin_limit, Shared& sh) {
-    constexpr int TPR = 1 << LTPR;
-    const int cl = kfb_tid() & (TPR - 1);
     const int n = I.n;
     unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
-    if (threadIdx.x == 0) {
-        unsigned spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u) {
-            if (++spins > spin_limit) {
-                atomicOr(sync + KFB_SYNC_ERROR, KFB_ERR_SPIN);
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(8);
-        }
-        kfb_acquire();
-        sh.flag = ok;
-    }
-    __syncthreads();
-    const bool ready = sh.flag != 0;
-    __syncthreads();
-    if (!ready) return;
+    if (!kfb_wait_x(ctr, sync, spin_limit, sh)) return;
     const float* __restrict__ B = arena + I.b;
     const float* __restrict__ x = arena + I.v[6];
     float* __restrict__ w = arena + I.v[7];
@@ -438,6 +446,111 @@ __device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ ar
         __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+
+// ---- wide BiCGK tiles (n > 512): the four waves split each row's columns ---
+// Lane t of the workgroup owns chunks t + 256 k (k < K) of every row of the
+// item, so the column result A^T r needs no cross-lane reduction; G rows
+// are loaded per step, and a row sum is finished by a transposing reduction
+// inside each wave and then the four wave partials, added in wave order after
+// one barrier per step (double-buffered in LDS). This is the row-resident
+// layout of the single-instance kernels at batch-instance size; it keeps the
+// per-lane state small, so more waves are resident.
+
+// Row-indexed scalars of the wide tiles: lanes 0 .. G - 1 load v[i0 + lane]
+// (zero past r1) one step ahead; kfb_row_bcast reads each lane as a
+// wave-uniform value once the load has long completed.
+template <int G>
+__device__ __forceinline__ float kfb_row_fetch(const float* v, int i0, int r1) {
+    const int lane = __lane_id();
+    return (lane < G && i0 + lane < r1) ? v[i0 + lane] : 0.f;
+}
+template <int G>
+__device__ __forceinline__ void kfb_row_bcast(float x, float* out) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) out[g] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), g));
+}
+
+template <int K, int LG>
+__device__ __forceinline__ void kfb_w_rows_sum(const float* qp_in, float* __restrict__ out, float scale, int i0,
+                                               int r1, Shared& sh, int& buf) {
+    constexpr int G = 1 << LG;
+    float qp[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) qp[g] = qp_in[g];
+    const float sw = kfb_rows_reduce<6, LG>(qp);
+    const int lane = __lane_id(), wave = threadIdx.x >> 6;
+    if ((lane & ((64 >> LG) - 1)) == 0) sh.rowp[buf][wave][lane >> (6 - LG)] = sw;
+    __syncthreads();
+    if (threadIdx.x < G && i0 + (int)threadIdx.x < r1) {
+        const int g = threadIdx.x;
+        out[i0 + g] = scale * (((sh.rowp[buf][0][g] + sh.rowp[buf][1][g]) + sh.rowp[buf][2][g]) + sh.rowp[buf][3][g]);
+    }
+    buf ^= 1;
+}
+
+template <int K, int LG>
+__device__ void kfb_w_bicgk(const kfb_inst& I, int blk, float* __restrict__ arena, float* __restrict__ ws,
+                            unsigned* sync, Shared& sh) {
+    constexpr int G = 1 << LG;
+    const int t = kfb_tid();
+    const int n = I.n;
+    const long ld = I.ld;
+    const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
+    const float* __restrict__ A = arena + I.a;
+    const float* __restrict__ r = arena + I.v[1];
+    float* __restrict__ q = arena + I.v[2];
+    float* __restrict__ s = arena + I.v[3];
+    kf_f4 pv[K], acc[K];
+    kfb_cols cs[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cs[k] = kfb_col(4 * (t + 256 * k), n, I.ld);
+        pv[k] = kfb_ldv(arena + I.v[0], 4 * (t + 256 * k), n);
+        acc[k] = kf_zero4();
+    }
+    int buf = 0;
+    float r_next = kfb_row_fetch<G>(r, r0, r1);
+#pragma unroll 1
+    for (int i0 = r0; i0 < r1; i0 += G) {
+        const float r_cur = r_next;
+        kf_f4 a[G][K];
+        float rr[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < K; ++k) a[g][k] = kfb_ldm(A, ld, i0 + g, r1, cs[k]);
+        r_next = kfb_row_fetch<G>(r, i0 + G, r1);     // issued after this step's matrix loads
+        kfb_row_bcast<G>(r_cur, rr);
+        float qp[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            qp[g] = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) qp[g] = kf_dot4(a[g][k], pv[k], qp[g]);
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] = kf_fma4s(rr[g], a[g][k], acc[k]);
+        }
+        kfb_w_rows_sum<K, LG>(qp, q, 1.f, i0, r1, sh, buf);
+    }
+    if (I.nblk == 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) kfb_stv(s, 4 * (t + 256 * k), n, acc[k]);
+        return;
+    }
+    float* part = ws + I.ws + (long)blk * ld;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (4 * (t + 256 * k) < I.ld) kf_st4(part + 4 * (t + 256 * k), acc[k]);
+    unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
+    if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
+        for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
+            kf_f4 sum = kf_zero4();
+            for (int b = 0; b < I.nblk; ++b) sum += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
+            kfb_stv(s, 4 * c, n, sum);
+        }
+    }
+}
+
 template <int LTPR, int K, int LG>
 __device__ __forceinline__ void kfb_item_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
                                              unsigned* sync, unsigned spin_limit, Shared& sh) {
@@ -446,9 +559,8 @@ __device__ __forceinline__ void kfb_item_run(const kfb_inst& I, int phase, int b
     else kfb_gemver_k2<LTPR, K, LG>(I, blk, arena, sync, spin_limit, sh);
 }
 
-// Three waves per SIMD (163 VGPRs): the largest tiles keep eight 16-byte
-// loads per lane in flight, and three resident workgroups per CU keep enough
-// bytes outstanding to cover HBM latency.
+// Three waves per SIMD (168 VGPRs, two of them spilled): the whole-row GEMVER
+// tiles of the largest bucket keep eight 16-byte loads per lane in flight.
 __global__ void __launch_bounds__(KFB_THREADS) __attribute__((amdgpu_waves_per_eu(3, 8)))
 kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ items, int nitems, int item0,
            int persistent, float* arena, float* ws, unsigned* sync, unsigned spin_limit) {
@@ -473,8 +585,16 @@ kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ item
         case 1: kfb_item_run<5, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
         case 2: kfb_item_run<6, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
         case 3: kfb_item_run<6, 2, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        case 4: kfb_item_run<6, 4, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        default: kfb_item_run<6, 8, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+        // BiCGK takes the wide tiles above n = 512; GEMVER keeps whole rows per
+        // wave there, which stores B faster (measured per bucket)
+        case 4:
+            if (phase == KFB_BICGK) kfb_w_bicgk<1, 3>(I, blk, arena, ws, sync, sh);
+            else kfb_item_run<6, 4, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh);
+            break;
+        default:
+            if (phase == KFB_BICGK) kfb_w_bicgk<2, 2>(I, blk, arena, ws, sync, sh);
+            else kfb_item_run<6, 8, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh);
+            break;
         }
         if (!persistent) break;
         __syncthreads();

@@ -34,7 +34,7 @@ def test_layout_and_items(opts):
             off, ld = b.offset(i, name)
             size = n * ld if name in ("A", "B") else n
             if name in ("A", "B"):
-                assert ld == (n + 3) // 4 * 4
+                assert ld == (n + 31) // 32 * 32
             assert off % 64 == 0                      # 256-byte aligned
             spans.append((off, off + size))
     spans.sort()

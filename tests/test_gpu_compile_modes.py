@@ -88,3 +88,10 @@ def test_costmodel_save_load_roundtrip(tmp_path):
     assert cm2.state()[4] == np.float32(0.5)
     for x, y in zip(cm.state()[:3], cm2.state()[:3]):
         assert np.array_equal(x, y)
+
+
+def test_shipped_library_format_model_predicts_like_npz():
+    a = CostModel.load(MODEL)
+    b = CostModel.load(MODEL.replace(".npz", ".kfcm"))
+    X = np.random.default_rng(1).standard_normal((300, kf.FEATURE_DIM)).astype(np.float32)
+    assert np.array_equal(a.predict_log(X), b.predict_log(X))

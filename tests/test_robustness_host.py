@@ -63,3 +63,27 @@ def test_damaged_costmodel_file_refused(tmp_path, content):
     h = kf._vp()
     with pytest.raises(kf.KFError, match="KF_ERR_ARG"):
         kf._chk(kf.lib().kf_costmodel_load(str(p).encode(), kf.ctypes.byref(h)))
+
+
+def test_shipped_costmodel_files_agree():
+    """The library-format model shipped beside the numpy one holds the same
+    numbers, under a valid header and checksum (decoded here field by field)."""
+    import numpy as np
+    data = os.path.join(os.path.dirname(kf.__file__), "data")
+    d = open(os.path.join(data, "plan_cost_model.kfcm"), "rb").read()
+    assert d[:4] == b"KFCM"
+    assert struct.unpack("<Q", d[-8:])[0] == _fnv(d[4:-8])
+    ver, dim, hid, layers, npar = struct.unpack("<4iq", d[4:28])
+    assert ver == 2 and dim == kf.FEATURE_DIM
+    off = 28
+    mu = np.frombuffer(d, np.float32, dim, off); off += 4 * dim
+    sd = np.frombuffer(d, np.float32, dim, off); off += 4 * dim
+    y = np.frombuffer(d, np.float64, 2, off); off += 16
+    lu = np.frombuffer(d, np.float32, 1, off)[0]; off += 4
+    p = np.frombuffer(d, np.float32, npar, off); off += 4 * npar
+    assert off == len(d) - 8
+    z = np.load(os.path.join(data, "plan_cost_model.npz"), allow_pickle=False)
+    assert [int(v) for v in z["dims"][:3]] == [dim, hid, layers]
+    assert np.array_equal(p, z["params"]) and np.array_equal(mu, z["mu"]) and np.array_equal(sd, z["sd"])
+    assert np.array_equal(y, z["y"])
+    assert lu > 0
