@@ -235,11 +235,21 @@ def main():
             q = S.by_name(name, m, nn, scal)
             devin = {k: torch.from_numpy(v).to(dev) for k, v in arrays.items()}
             for mode in ("fused", "unfused"):
-                best, res = autotune.tune(q, devin, mode=mode)
-                res.sort(key=lambda r: r[1])
-                print(json.dumps({"seq": name, "mode": mode, "best": best,
+                # every grid point timed kernel by kernel: the best single point
+                # for the whole plan (least summed time) and the best point per kernel
+                kbest, per = autotune.tune_kernels(q, devin, mode=mode)
+                res = sorted(((per[0][i][0], sum(r[i][1] for r in per)) for i in range(len(per[0]))),
+                             key=lambda r: r[1])
+                uni = q.compile(mode=mode, **res[0][0]).bind(device=dev, **devin)
+                prog = q.compile(mode=mode, kernel_params=kbest).bind(device=dev, **devin)
+                print(json.dumps({"seq": name, "mode": mode, "best": res[0][0],
                                   "top": [[p, round(t, 2)] for p, t in res[:6]],
-                                  "worst": [res[-1][0], round(res[-1][1], 2)]}), flush=True)
+                                  "worst": [res[-1][0], round(res[-1][1], 2)],
+                                  "best_plan_us": round(uni.time(3, 20), 2),
+                                  "kernel_params": kbest,
+                                  "kernel_us": [round(min(t for _, t in r), 2) for r in per],
+                                  "per_kernel_plan_us": round(prog.time(3, 20), 2)}), flush=True)
+                del prog, uni
             del devin
             torch.cuda.empty_cache()
         return

@@ -132,13 +132,20 @@ kf_status kf_script_call(const kf_script* s, int32_t i, int32_t* op, kf_value* a
 enum {
     KF_MODE_UNFUSED = 0,      /* one kernel per call                           */
     KF_MODE_FUSED = 1,        /* the legal partition with fewest kernels       */
-    KF_MODE_ADDITIVE = 2,     /* best candidate by the additive routine predictor */
-    KF_MODE_LEARNED = 3,      /* best candidate by the learned cost model
-                                 (opts.model); with opts.top_k > 1 the top_k
-                                 predictions are timed (needs opts.bind_*) and
-                                 the fastest is kept                           */
-    KF_MODE_EXHAUSTIVE = 4,   /* time every candidate on opts.stream with the
-                                 buffers of opts.bind_* and keep the fastest   */
+    /* The three ranking modes below cost every kernel of every candidate on
+     * its own and combine, per partition, the cheapest implementation of each
+     * kernel (the "combination of fusion implementations" of Section 4.2:
+     * kernels of one plan may use different parameter points); the partition
+     * whose combination costs least wins (ties within 0.1%: fewer kernels). */
+    KF_MODE_ADDITIVE = 2,     /* costs from the additive routine predictor      */
+    KF_MODE_LEARNED = 3,      /* costs from the learned cost model (opts.model);
+                                 with opts.top_k > 1 the top_k candidates by
+                                 predicted plan time, and those of the predicted
+                                 combination, are timed kernel by kernel (needs
+                                 opts.bind_*) and the measured times combined  */
+    KF_MODE_EXHAUSTIVE = 4,   /* every candidate timed kernel by kernel on
+                                 opts.stream with the buffers of opts.bind_*,
+                                 the measured times combined                   */
     KF_MODE_PARTITION = 5     /* the partition given in opts.partition         */
 };
 enum {
@@ -147,6 +154,12 @@ enum {
                                      additive predictions (kf_run is refused) */
 };
 struct kf_routine_entry;
+/* Implementation parameters of one plan kernel (fields as in kf_compile_opts;
+ * 0 = take the value of the enclosing kf_compile_opts). */
+typedef struct kf_impl_params {
+    int32_t mat_k, mat_waves, mat_group, mat_rows, mat_sched, mat_unit;
+    int32_t vec_unroll, vec_threads, vec_grid;
+} kf_impl_params;
 typedef struct kf_compile_opts {
     int32_t mode;            /* KF_MODE_*                                         */
     int32_t flags;           /* KF_COMPILE_*                                      */
@@ -192,6 +205,13 @@ typedef struct kf_compile_opts {
     void* const* bind_ptrs;
     int32_t bind_len;
     int32_t top_k;
+    /* Per-kernel parameters (modes UNFUSED, FUSED, PARTITION): entry i applies
+     * to the i-th kernel of the plan in launch order (the order of
+     * kf_plan_describe); kernels past kernel_params_len, and zero fields, use
+     * the parameters above. KF_ERR_ARG if there are more entries than kernels.
+     * Not owned; read during the call only. */
+    const kf_impl_params* kernel_params;
+    int32_t kernel_params_len;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
@@ -211,13 +231,15 @@ kf_status kf_planset_count(const kf_planset* ps, int32_t* n);
 /* partition[call] = kernel id for plan i (len = number of calls). */
 kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, int32_t len);
 
-/* Candidate plans (Section 4.2, "combinations of fusion implementations"):
- * the first max_partitions legal partitions crossed with the implementation
- * parameter points grid[0..grid_len) (mode and partition fields ignored; only
- * the fields of the kernel classes present matter, and candidates whose
- * kernels would be identical are listed once). grid = NULL takes 24 points:
- * the shape-dependent defaults, four fixed strip shapes and the row-resident
- * schedule, crossed with the defaults and three fixed BLAS-1 shapes. */
+/* Candidate plans (Section 4.2, fusion implementations): the first
+ * max_partitions legal partitions crossed with the implementation parameter
+ * points grid[0..grid_len) (mode and partition fields ignored; only the fields
+ * of the kernel classes present matter, and candidates whose kernels would be
+ * identical are listed once). Each candidate uses one point for all its
+ * kernels; the ranking modes of kf_compile combine, per partition, kernels of
+ * different candidates. grid = NULL takes 32 points: the shape-dependent
+ * defaults, six fixed strip shapes and the row-resident schedule, crossed with
+ * the defaults and three fixed BLAS-1 shapes. */
 kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_compile_opts* grid,
                         int32_t grid_len, kf_planset** out);
 /* Parameters of candidate i (mode = KF_MODE_PARTITION, partition pointing into
@@ -261,6 +283,14 @@ kf_status kf_run_launch(kf_plan* p, int32_t k, int32_t l, void* stream);
  * events; returns the median in microseconds. Synchronises the stream. */
 kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps,
                        float* median_us);
+/* Time each kernel inside whole runs of the plan: `warmup` untimed runs, then
+ * `reps` runs in which HIP events bracket every kernel (all its launches);
+ * us[k] receives the median for plan kernel k (us holds kf_plan_num_kernels
+ * floats). Synchronises the stream. */
+kf_status kf_time_plan_kernels(kf_plan* p, void* stream, int32_t warmup, int32_t reps, float* us);
+/* The implementation parameters kernel k was generated with, after defaults
+ * for its shape were applied (mat_* for BLAS-2 kernels, vec_* for BLAS-1). */
+kf_status kf_plan_kernel_params(const kf_plan* p, int32_t k, kf_impl_params* out);
 
 /* ---- introspection -------------------------------------------------------- */
 /* JSON description (kernels, calls, parameters, grid, bytes). Writes at most

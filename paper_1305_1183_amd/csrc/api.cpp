@@ -419,6 +419,19 @@ static size_t value_bytes(const Value& v) {
     }
 }
 
+static kf_status check_params(const MatParams& mp, const VecParams& vp) {
+    if (mp.sched < 0 || mp.sched > 1) return set_error(KF_ERR_ARG, "mat_sched must be 0 or 1");
+    if (mp.unit != 0 && mp.unit != 4 && mp.unit != 16) return set_error(KF_ERR_ARG, "mat_unit must be 0, 4 or 16");
+    if (mp.k && mp.k != 1 && mp.k != 2 && mp.k != 4) return set_error(KF_ERR_ARG, "mat_k must be 1, 2 or 4");
+    if (mp.waves && (mp.waves < 1 || mp.waves > 16)) return set_error(KF_ERR_ARG, "mat_waves must be 1..16");
+    if (mp.group && (mp.group & (mp.group - 1) || mp.group > 16)) return set_error(KF_ERR_ARG, "mat_group must be 1, 2, 4, 8 or 16");
+    if (mp.rows < 0) return set_error(KF_ERR_ARG, "mat_rows must be >= 0");
+    if (vp.unroll && (vp.unroll < 1 || vp.unroll > 8)) return set_error(KF_ERR_ARG, "vec_unroll must be 1..8");
+    if (vp.threads && (vp.threads < 64 || vp.threads > 1024 || vp.threads % 64)) return set_error(KF_ERR_ARG, "vec_threads must be a multiple of 64 in 64..1024");
+    if (vp.grid < 0) return set_error(KF_ERR_ARG, "vec_grid must be >= 0");
+    return KF_OK;
+}
+
 kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_compile_opts& o,
                             kf_plan** out) {
     const int ncall = (int)sc.calls.size();
@@ -456,29 +469,46 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     for (size_t v = 0; v < nv; ++v)
         if (sc.values[v].kind == VK::Const) p->consts[v] = sc.values[v].cval;
 
-    MatParams mp;
-    mp.k = o.mat_k;
-    mp.waves = o.mat_waves;
-    mp.group = o.mat_group;
-    mp.rows = o.mat_rows;
-    mp.sched = o.mat_sched;
-    mp.unit = o.mat_unit;
-    if (mp.sched < 0 || mp.sched > 1) return set_error(KF_ERR_ARG, "mat_sched must be 0 or 1");
-    if (mp.unit != 0 && mp.unit != 4 && mp.unit != 16) return set_error(KF_ERR_ARG, "mat_unit must be 0, 4 or 16");
-    VecParams vp;
-    vp.unroll = o.vec_unroll;
-    vp.threads = o.vec_threads;
-    vp.grid = o.vec_grid;
-    if (mp.k && mp.k != 1 && mp.k != 2 && mp.k != 4) return set_error(KF_ERR_ARG, "mat_k must be 1, 2 or 4");
-    if (mp.waves && (mp.waves < 1 || mp.waves > 16)) return set_error(KF_ERR_ARG, "mat_waves must be 1..16");
-    if (mp.group && (mp.group & (mp.group - 1) || mp.group > 16)) return set_error(KF_ERR_ARG, "mat_group must be 1, 2, 4, 8 or 16");
-    if (vp.unroll && (vp.unroll < 1 || vp.unroll > 8)) return set_error(KF_ERR_ARG, "vec_unroll must be 1..8");
-    if (vp.threads && (vp.threads < 64 || vp.threads > 1024 || vp.threads % 64)) return set_error(KF_ERR_ARG, "vec_threads must be a multiple of 64 in 64..1024");
-    if (vp.grid < 0) return set_error(KF_ERR_ARG, "vec_grid must be >= 0");
+    MatParams mp0;
+    mp0.k = o.mat_k;
+    mp0.waves = o.mat_waves;
+    mp0.group = o.mat_group;
+    mp0.rows = o.mat_rows;
+    mp0.sched = o.mat_sched;
+    mp0.unit = o.mat_unit;
+    VecParams vp0;
+    vp0.unroll = o.vec_unroll;
+    vp0.threads = o.vec_threads;
+    vp0.grid = o.vec_grid;
+    kf_status pst = check_params(mp0, vp0);
+    if (pst != KF_OK) return pst;
 
     auto order = kernels_in_order(sc, part);
-    for (auto& calls : order) {
+    if (o.kernel_params_len < 0 || (o.kernel_params_len > 0 && !o.kernel_params))
+        return set_error(KF_ERR_ARG, "kernel_params missing or of negative length");
+    if (o.kernel_params_len > (int32_t)order.size())
+        return set_error(KF_ERR_ARG, "more kernel_params entries than kernels in the plan");
+    for (size_t ki = 0; ki < order.size(); ++ki) {
+        const auto& calls = order[ki];
         PlanKernel pk;
+        MatParams mp = mp0;
+        VecParams vp = vp0;
+        if ((int32_t)ki < o.kernel_params_len) {
+            const kf_impl_params& e = o.kernel_params[ki];
+            if (e.mat_k) mp.k = e.mat_k;
+            if (e.mat_waves) mp.waves = e.mat_waves;
+            if (e.mat_group) mp.group = e.mat_group;
+            if (e.mat_rows) mp.rows = e.mat_rows;
+            if (e.mat_sched) mp.sched = e.mat_sched;
+            if (e.mat_unit) mp.unit = e.mat_unit;
+            if (e.vec_unroll) vp.unroll = e.vec_unroll;
+            if (e.vec_threads) vp.threads = e.vec_threads;
+            if (e.vec_grid) vp.grid = e.vec_grid;
+            pst = check_params(mp, vp);
+            if (pst != KF_OK) return pst;
+        }
+        pk.mp = mp;
+        pk.vp = vp;
         Space sp = call_space(sc, calls[0]);
         if (sp.mat && (mp.sched == 1 || needs_rowres(sc, calls))) {
             if (sp.b > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
@@ -734,6 +764,73 @@ kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps, f
     if (st_out != KF_OK) return st_out;
     std::sort(t.begin(), t.end());
     *median_us = t.size() % 2 ? t[t.size() / 2] : 0.5f * (t[t.size() / 2 - 1] + t[t.size() / 2]);
+    return KF_OK;
+}
+
+kf_status kf_time_plan_kernels(kf_plan* p, void* stream, int32_t warmup, int32_t reps, float* us) {
+    if (!p || !us || reps < 1 || warmup < 0) return set_error(KF_ERR_ARG, "bad argument");
+    CHECK(check_runnable(p));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nk = p->ks.size();
+    for (int i = 0; i < warmup; ++i) CHECK(kf_run(p, stream));
+    // events[(rep * nk + k) * 2 + {0, 1}] bracket kernel k of run rep
+    std::vector<hipEvent_t> ev(2 * nk * (size_t)reps, nullptr);
+    kf_status st_out = KF_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            st_out = set_error(KF_ERR_HIP, "hipEventCreate");
+            break;
+        }
+    for (int i = 0; i < reps && st_out == KF_OK; ++i)
+        for (size_t k = 0; k < nk && st_out == KF_OK; ++k) {
+            const size_t at = ((size_t)i * nk + k) * 2;
+            if (hipEventRecord(ev[at], st) != hipSuccess) { st_out = set_error(KF_ERR_HIP, "hipEventRecord"); break; }
+            st_out = launch_kernel(p, p->ks[k], st);
+            if (st_out == KF_OK && hipEventRecord(ev[at + 1], st) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipEventRecord");
+        }
+    std::vector<std::vector<float>> t(nk);
+    if (st_out == KF_OK) {
+        if (hipStreamSynchronize(st) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipStreamSynchronize");
+        for (int i = 0; i < reps && st_out == KF_OK; ++i)
+            for (size_t k = 0; k < nk && st_out == KF_OK; ++k) {
+                const size_t at = ((size_t)i * nk + k) * 2;
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[at], ev[at + 1]) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipEventElapsedTime");
+                t[k].push_back(ms * 1000.f);
+            }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st_out != KF_OK) return st_out;
+    for (size_t k = 0; k < nk; ++k) {
+        auto& v = t[k];
+        std::sort(v.begin(), v.end());
+        us[k] = v.size() % 2 ? v[v.size() / 2] : 0.5f * (v[v.size() / 2 - 1] + v[v.size() / 2]);
+    }
+    return KF_OK;
+}
+
+kf_status kf_plan_kernel_params(const kf_plan* p, int32_t k, kf_impl_params* out) {
+    if (!p || !out) return set_error(KF_ERR_ARG, "null argument");
+    if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
+    const PlanKernel& pk = p->ks[k];
+    const Space sp = call_space(p->s, pk.code.calls[0]);
+    kf_impl_params r;
+    std::memset(&r, 0, sizeof r);
+    if (sp.mat) {
+        const bool rowres = pk.mp.sched == 1 || needs_rowres(p->s, pk.code.calls);
+        MatParams q = rowres ? pk.mp
+                             : default_mat_params(sp.a, sp.b, pk.mp, kernel_unit_elems(p->s, pk.code.calls, pk.mp.unit));
+        if (rowres && pk.mp.sched != 1) q.waves = q.group = q.rows = 0;   // strip parameters do not carry over
+        r.mat_k = q.k; r.mat_waves = q.waves; r.mat_group = q.group; r.mat_rows = q.rows;
+        r.mat_sched = rowres ? 1 : 0;
+        r.mat_unit = q.unit;
+    } else {
+        const VecParams q = default_vec_params(sp.a, pk.vp);
+        r.vec_unroll = q.unroll; r.vec_threads = q.threads; r.vec_grid = q.grid;
+    }
+    *out = r;
     return KF_OK;
 }
 

@@ -144,6 +144,8 @@ kf_status set_error(kf_status st, const std::string& msg);
 // ---- plans -------------------------------------------------------------------
 struct PlanKernel {
     KernelCode code;
+    MatParams mp;             // implementation parameters requested for this kernel
+    VecParams vp;             // (0 = library default for the shape)
     std::vector<void*> fns;   // hipFunction_t per launch
     size_t ws_off = 0;        // bytes from workspace base to this kernel's partial sums
 };
@@ -166,8 +168,8 @@ struct kf_plan {
     std::vector<float> consts;        // per value (kf_const)
     std::vector<size_t> inter_off;    // per value: workspace offset of intermediates, or SIZE_MAX
     std::vector<char> is_read, is_written;
-    kf::MatParams mp;                 // requested parameters (0 = default per shape)
-    kf::VecParams vp;
+    kf::MatParams mp;                 // plan-wide requested parameters (0 = default per shape);
+    kf::VecParams vp;                 // each kernel's own are in ks[k].mp / ks[k].vp
     void* ws = nullptr;
     size_t ws_bound = 0;
     size_t ws_need = 0;

@@ -97,69 +97,88 @@ kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols, const kf_
     return KF_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Additive prediction of one kernel of a plan: max(t_t, t_c) plus the
+// finishing launches (Section 4.2), with the kernel's own parameters.
+kf_status predict_kernel_additive(const kf_plan* p, const PlanKernel& pk, const kf_routine_entry* table, int32_t n,
+                                  double* us) {
+    const KernelCode& kc = pk.code;
+    const Space sp = call_space(p->s, kc.calls[0]);
+    const bool mat = sp.mat;
+    MatParams mp = mat ? default_mat_params(sp.a, sp.b, pk.mp) : MatParams();
+    VecParams vp = mat ? VecParams() : default_vec_params(sp.a, pk.vp);
+    if (!mat && pk.vp.grid > 0) vp.grid = pk.vp.grid;  // the environment is the requested point (grid is capped for short vectors)
+    const bool rowres = mat && (pk.mp.sched == 1 || needs_rowres(p->s, kc.calls));
+    const kf_routine_entry* first_mat = nullptr;
+    for (int i = 0; i < n && rowres && !first_mat; ++i)
+        if (table[i].cls == 1) first_mat = &table[i];
+    auto get = [&](int r) -> const kf_routine_entry* {
+        if (rowres && first_mat) {
+            // row-resident kernels have no probe geometry of their own: they are
+            // priced with the routines of the table's first BLAS-2 environment
+            MatParams e;
+            e.k = first_mat->env[0]; e.waves = first_mat->env[1]; e.group = first_mat->env[2]; e.rows = first_mat->env[3];
+            return find(table, n, true, e, vp, r);
+        }
+        return find(table, n, mat, mp, vp, r);
+    };
+    double tt = 0, tc = 0;
+    // transfers: every operand the kernel's launches move through HBM
+    for (const Launch& l : kc.launches)
+        for (const KArg& a : l.args) {
+            if (a.value < 0) continue;
+            const Value& x = p->s.values[a.value];
+            double elems = x.kind == VK::Mat ? (double)x.rows * x.cols : x.kind == VK::Vec ? (double)x.n
+                                                                          : x.kind == VK::DevScalar ? 1.0 : 0.0;
+            if (elems == 0) continue;
+            bool in = a.kind == ArgKind::MatIn || a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn;
+            bool outk = a.kind == ArgKind::MatOut || a.kind == ArgKind::VecOut || a.kind == ArgKind::DevScalarOut;
+            if (!in && !outk) continue;
+            int r;
+            if (mat) r = in ? KF_ROUTINE_LOAD_MAT : KF_ROUTINE_STORE_MAT;  // vectors priced per element as matrix data
+            else r = in ? KF_ROUTINE_LOAD_VEC : KF_ROUTINE_STORE_VEC;
+            const kf_routine_entry* e = get(r);
+            if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no transfer entry for this environment");
+            tt += elems * e->us_per_unit;
+        }
+    for (int c : kc.calls) {
+        int r = -1;
+        switch (p->s.calls[c].op) {
+            case Op::Scal: r = KF_ROUTINE_COMPUTE_SCAL; break;
+            case Op::Axpy: r = KF_ROUTINE_COMPUTE_AXPY; break;
+            case Op::Dot: r = KF_ROUTINE_COMPUTE_DOT; break;
+            case Op::Gemv: r = KF_ROUTINE_COMPUTE_GEMV; break;
+            case Op::Gemtv: r = KF_ROUTINE_COMPUTE_GEMTV; break;
+            case Op::Ger: r = KF_ROUTINE_COMPUTE_GER; break;
+        }
+        const kf_routine_entry* e = get(r);
+        if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no compute entry for this environment");
+        tc += (mat ? (double)sp.a * sp.b : (double)sp.a) * e->us_per_unit;
+    }
+    double t = std::max(tt, tc);
+    if (kc.launches.size() > 1) {
+        const kf_routine_entry* e = get(KF_ROUTINE_FINISH);
+        if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no FINISH entry for this environment");
+        t += (double)(kc.launches.size() - 1) * e->us_per_unit;
+    }
+    *us = t;
+    return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n, float* us) {
     if (!p || !table || !us || n < 1) return set_error(KF_ERR_ARG, "bad argument");
     double total = 0;
     for (const PlanKernel& pk : p->ks) {
-        const KernelCode& kc = pk.code;
-        const Space sp = call_space(p->s, kc.calls[0]);
-        const bool mat = sp.mat;
-        MatParams mp = mat ? default_mat_params(sp.a, sp.b, p->mp) : MatParams();
-        VecParams vp = mat ? VecParams() : default_vec_params(sp.a, p->vp);
-        if (!mat && p->vp.grid > 0) vp.grid = p->vp.grid;  // the environment is the requested point (grid is capped for short vectors)
-        const bool rowres = mat && (p->mp.sched == 1 || needs_rowres(p->s, kc.calls));
-        const kf_routine_entry* first_mat = nullptr;
-        for (int i = 0; i < n && rowres && !first_mat; ++i)
-            if (table[i].cls == 1) first_mat = &table[i];
-        auto get = [&](int r) -> const kf_routine_entry* {
-            if (rowres && first_mat) {
-                // row-resident kernels have no probe geometry of their own: they are
-                // priced with the routines of the table's first BLAS-2 environment
-                MatParams e;
-                e.k = first_mat->env[0]; e.waves = first_mat->env[1]; e.group = first_mat->env[2]; e.rows = first_mat->env[3];
-                return find(table, n, true, e, vp, r);
-            }
-            return find(table, n, mat, mp, vp, r);
-        };
-        double tt = 0, tc = 0;
-        // transfers: every operand the kernel's launches move through HBM
-        for (const Launch& l : kc.launches)
-            for (const KArg& a : l.args) {
-                if (a.value < 0) continue;
-                const Value& x = p->s.values[a.value];
-                double elems = x.kind == VK::Mat ? (double)x.rows * x.cols : x.kind == VK::Vec ? (double)x.n
-                                                                              : x.kind == VK::DevScalar ? 1.0 : 0.0;
-                if (elems == 0) continue;
-                bool in = a.kind == ArgKind::MatIn || a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn;
-                bool outk = a.kind == ArgKind::MatOut || a.kind == ArgKind::VecOut || a.kind == ArgKind::DevScalarOut;
-                if (!in && !outk) continue;
-                int r;
-                if (mat) r = in ? KF_ROUTINE_LOAD_MAT : KF_ROUTINE_STORE_MAT;  // vectors priced per element as matrix data
-                else r = in ? KF_ROUTINE_LOAD_VEC : KF_ROUTINE_STORE_VEC;
-                const kf_routine_entry* e = get(r);
-                if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no transfer entry for this environment");
-                tt += elems * e->us_per_unit;
-            }
-        for (int c : kc.calls) {
-            int r = -1;
-            switch (p->s.calls[c].op) {
-                case Op::Scal: r = KF_ROUTINE_COMPUTE_SCAL; break;
-                case Op::Axpy: r = KF_ROUTINE_COMPUTE_AXPY; break;
-                case Op::Dot: r = KF_ROUTINE_COMPUTE_DOT; break;
-                case Op::Gemv: r = KF_ROUTINE_COMPUTE_GEMV; break;
-                case Op::Gemtv: r = KF_ROUTINE_COMPUTE_GEMTV; break;
-                case Op::Ger: r = KF_ROUTINE_COMPUTE_GER; break;
-            }
-            const kf_routine_entry* e = get(r);
-            if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no compute entry for this environment");
-            tc += (mat ? (double)sp.a * sp.b : (double)sp.a) * e->us_per_unit;
-        }
-        double t = std::max(tt, tc);
-        if (kc.launches.size() > 1) {
-            const kf_routine_entry* e = get(KF_ROUTINE_FINISH);
-            if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no FINISH entry for this environment");
-            t += (double)(kc.launches.size() - 1) * e->us_per_unit;
-        }
+        double t = 0;
+        kf_status st = predict_kernel_additive(p, pk, table, n, &t);
+        if (st != KF_OK) return st;
         total += t;
     }
     *us = (float)total;
@@ -172,7 +191,7 @@ kf_status kf_plan_features(const kf_plan* p, float* out, int32_t rows, int32_t* 
     if (!out) return KF_OK;
     if (rows < *nk) return set_error(KF_ERR_ARG, "feature buffer has too few rows");
     for (size_t k = 0; k < p->ks.size(); ++k)
-        kernel_features(p->s, p->ks[k].code, p->part, p->mp, p->vp, out + k * KF_FEATURE_DIM);
+        kernel_features(p->s, p->ks[k].code, p->part, p->ks[k].mp, p->ks[k].vp, out + k * KF_FEATURE_DIM);
     return KF_OK;
 }
 
@@ -200,7 +219,7 @@ kf_compile_opts cand_opts(const kf_planset* ps, int i) {
 std::vector<kf_compile_opts> default_grid() {
     std::vector<kf_compile_opts> g;
     const int mat[][5] = {{0, 0, 0, 0, 0}, {1, 4, 4, 1024, 0}, {2, 8, 2, 1024, 0}, {1, 4, 4, 256, 0},
-                          {2, 4, 4, 512, 0}, {0, 8, 2, 0, 1}};
+                          {2, 4, 4, 512, 0}, {1, 4, 2, 1024, 0}, {2, 4, 2, 2048, 0}, {0, 8, 2, 0, 1}};
     const int vec[][3] = {{0, 0, 0}, {4, 256, 2048}, {4, 256, 4096}, {2, 256, 1024}};
     for (auto& m : mat)
         for (auto& v : vec) {
@@ -314,6 +333,80 @@ kf_status kf_planset_predict_additive(const kf_planset* ps, const kf_routine_ent
 
 }  // extern "C"
 
+// ---- combinations of kernel implementations ------------------------------------
+// Candidates that share a partition generate the same kernels in the same order,
+// each with the candidate's parameter point. Because plan costs add over kernels
+// (the predictors are additive; measured kernels run one after another), the
+// cheapest plan for a partition takes, for every kernel, the cheapest point.
+namespace kf {
+namespace {
+
+struct Combination {
+    int first = -1;             // a candidate of the chosen partition (its earliest)
+    std::vector<int32_t> pick;  // candidate whose implementation each kernel takes
+    double total = 0;
+};
+
+// cost[i][k]: cost of kernel k of candidate i; an empty row = not costed.
+Combination best_combination(const kf_planset* ps, const std::vector<std::vector<double>>& cost) {
+    Combination best;
+    std::vector<char> done(ps->parts.size(), 0);
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        if (done[i]) continue;
+        // the group of candidates with this partition, in candidate order
+        std::vector<int32_t> grp;
+        for (size_t j = i; j < ps->parts.size(); ++j)
+            if (!done[j] && ps->parts[j] == ps->parts[i]) {
+                done[j] = 1;
+                if (!cost[j].empty()) grp.push_back((int32_t)j);
+            }
+        if (grp.empty()) continue;
+        const size_t nk = cost[grp[0]].size();
+        Combination c;
+        c.first = grp[0];
+        c.pick.assign(nk, -1);
+        for (size_t k = 0; k < nk; ++k) {
+            for (int32_t j : grp) {
+                if (cost[j].size() != nk) continue;
+                // within 0.1% counts as equal (Table 4): keep the earlier candidate
+                if (c.pick[k] < 0 || cost[j][k] < cost[c.pick[k]][k] * 0.999) c.pick[k] = j;
+            }
+            c.total += cost[c.pick[k]][k];
+        }
+        // partitions come fewest kernels first: a later one must be 0.1% cheaper
+        if (best.first < 0 || c.total < best.total * 0.999) best = c;
+    }
+    return best;
+}
+
+kf_status compile_combination(const kf_planset* ps, const Combination& c, int32_t flags, kf_plan** out) {
+    if (c.first < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be costed");
+    kf_compile_opts o;
+    kf_compile_opts_init(&o);
+    o.mode = KF_MODE_PARTITION;
+    o.flags = flags;
+    o.partition = ps->parts[c.first].data();
+    o.partition_len = (int32_t)ps->parts[c.first].size();
+    std::vector<kf_impl_params> kp(c.pick.size());
+    for (size_t k = 0; k < c.pick.size(); ++k) {
+        const kf_compile_opts& g = ps->params[c.pick[k]];
+        kf_impl_params& e = kp[k];
+        e.mat_k = g.mat_k; e.mat_waves = g.mat_waves; e.mat_group = g.mat_group; e.mat_rows = g.mat_rows;
+        e.mat_sched = g.mat_sched; e.mat_unit = g.mat_unit;
+        e.vec_unroll = g.vec_unroll; e.vec_threads = g.vec_threads; e.vec_grid = g.vec_grid;
+    }
+    o.kernel_params = kp.data();
+    o.kernel_params_len = (int32_t)kp.size();
+    try {
+        return build_plan(ps->s, ps->parts[c.first], o, out);
+    } catch (const std::bad_alloc&) {
+        return set_error(KF_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+}  // namespace
+}  // namespace kf
+
 kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {
     if (!o.table || o.table_len < 1) return set_error(KF_ERR_ARG, "KF_MODE_ADDITIVE needs a routine table");
     std::vector<kf_compile_opts> grid;
@@ -342,21 +435,25 @@ kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan
     kf_status st = kf_candidates(s, o.max_partitions, grid.data(), (int32_t)grid.size(), &ps);
     if (st != KF_OK) return st;
     std::unique_ptr<kf_planset> guard(ps);
-    std::vector<float> pred(ps->parts.size());
-    int best = -1;
+    std::vector<std::vector<double>> cost(ps->parts.size());
     for (size_t i = 0; i < ps->parts.size(); ++i) {
         kf_plan* p = nullptr;
         if (kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p) != KF_OK) continue;
-        float us = 0;
-        kf_status e = kf_predict_additive(p, o.table, o.table_len, &us);
+        std::vector<double> c;
+        for (const PlanKernel& pk : p->ks) {
+            double us = 0;
+            if (predict_kernel_additive(p, pk, o.table, o.table_len, &us) != KF_OK) {
+                c.clear();
+                break;
+            }
+            c.push_back(us);
+        }
         kf_plan_destroy(p);
-        if (e != KF_OK) continue;
-        // within 0.1% counts as equal (Table 4): keep the earlier candidate (fewer kernels first)
-        if (best < 0 || us < pred[best] * 0.999f) best = (int)i;
-        pred[i] = us;
+        cost[i] = std::move(c);
     }
-    if (best < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be predicted with this routine table");
-    return kf_planset_compile(ps, best, o.flags, out);
+    kf::Combination best = kf::best_combination(ps, cost);
+    if (best.first < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be predicted with this routine table");
+    return kf::compile_combination(ps, best, o.flags, out);
 }
 
 // ---- learned and empirical ranking inside kf_compile -------------------------
@@ -367,8 +464,8 @@ kf_status costmodel_plan_us(kf_costmodel* cm, const std::vector<float>& feats, c
 
 namespace {
 
-// Times candidates of a planset with the caller's buffers; the workspace is
-// allocated here and grown as candidates need it.
+// Times candidates of a planset kernel by kernel with the caller's buffers; the
+// workspace is allocated here and grown as candidates need it.
 struct Timer {
     const kf_planset* ps;
     const kf_compile_opts& o;
@@ -376,9 +473,9 @@ struct Timer {
     size_t ws_bytes = 0;
     Timer(const kf_planset* p, const kf_compile_opts& opts) : ps(p), o(opts) {}
     ~Timer() {
-        if (ws) hipFree(ws);
+        if (ws) (void)hipFree(ws);
     }
-    kf_status time(int32_t i, float* us) {
+    kf_status time_kernels(int32_t i, std::vector<double>* us) {
         kf_plan* p = nullptr;
         kf_status s = kf_planset_compile(ps, i, 0, &p);
         if (s != KF_OK) return s;
@@ -390,7 +487,7 @@ struct Timer {
         size_t need = 0;
         kf_plan_workspace_bytes(p, &need);
         if (need > ws_bytes) {
-            if (ws) hipFree(ws);
+            if (ws) (void)hipFree(ws);
             ws = nullptr;
             ws_bytes = 0;
             if (hipMalloc(&ws, need) != hipSuccess) return set_error(KF_ERR_HIP, "hipMalloc of the timing workspace failed");
@@ -400,7 +497,11 @@ struct Timer {
             s = kf_bind_workspace(p, ws, ws_bytes);
             if (s != KF_OK) return s;
         }
-        return kf_time_plan(p, o.stream, 2, 5, us);
+        std::vector<float> t(p->ks.size());
+        s = kf_time_plan_kernels(p, o.stream, 2, 5, t.data());
+        if (s != KF_OK) return s;
+        us->assign(t.begin(), t.end());
+        return KF_OK;
     }
 };
 
@@ -408,27 +509,24 @@ kf_status candidates_for(const kf_script* s, const kf_compile_opts& o, kf_planse
     return kf_candidates(s, o.max_partitions, o.grid_len > 0 ? o.grid : nullptr, o.grid_len > 0 ? o.grid_len : 0, ps);
 }
 
-// Among `order` (candidate indices), the fastest measured; ties within 0.1%
-// keep the earlier one.
-kf_status fastest_measured(const kf_planset* ps, const kf_compile_opts& o, const std::vector<int32_t>& order,
-                           int32_t* best) {
+// Times the candidates of `order` kernel by kernel and returns the cheapest
+// combination of the measured implementations.
+kf_status measured_combination(const kf_planset* ps, const kf_compile_opts& o, const std::vector<int32_t>& order,
+                               Combination* best) {
     if (!o.bind_values || !o.bind_ptrs || o.bind_len < 1)
         return set_error(KF_ERR_UNBOUND, "timing candidates needs the buffers of opts.bind_values / bind_ptrs");
     kf_planset_precompile(ps, order.data(), (int32_t)order.size());
     Timer t(ps, o);
-    float best_us = 0.f;
-    *best = -1;
+    std::vector<std::vector<double>> cost(ps->parts.size());
     for (int32_t i : order) {
-        float us = 0.f;
-        kf_status s = t.time(i, &us);
+        std::vector<double> us;
+        kf_status s = t.time_kernels(i, &us);
         if (s == KF_ERR_HIP || s == KF_ERR_UNBOUND || s == KF_ERR_ALIGN || s == KF_ERR_ALIAS) return s;
         if (s != KF_OK) continue;
-        if (*best < 0 || us < best_us * 0.999f) {
-            *best = i;
-            best_us = us;
-        }
+        cost[i] = std::move(us);
     }
-    if (*best < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");
+    *best = best_combination(ps, cost);
+    if (best->first < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");
     return KF_OK;
 }
 
@@ -441,8 +539,7 @@ kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan*
     if (st != KF_OK) return st;
     std::unique_ptr<kf_planset> guard(ps);
     std::vector<float> feats;
-    std::vector<size_t> start{0};
-    std::vector<int32_t> ok;
+    std::vector<size_t> row_of(ps->parts.size(), SIZE_MAX), nk_of(ps->parts.size(), 0);
     for (size_t i = 0; i < ps->parts.size(); ++i) {
         kf_plan* p = nullptr;
         if (kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p) != KF_OK) continue;
@@ -452,25 +549,42 @@ kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan*
         feats.resize(at + (size_t)nk * KF_FEATURE_DIM);
         kf_plan_features(p, feats.data() + at, nk, &nk);
         kf_plan_destroy(p);
-        start.push_back(feats.size() / KF_FEATURE_DIM);
-        ok.push_back((int32_t)i);
+        row_of[i] = at / KF_FEATURE_DIM;
+        nk_of[i] = (size_t)nk;
     }
-    if (ok.empty()) return set_error(KF_ERR_UNSUPPORTED, "no candidate plan");
-    std::vector<double> us;
-    st = costmodel_plan_us(o.model, feats, start, (hipStream_t)o.stream, &us);
+    const size_t rows = feats.size() / KF_FEATURE_DIM;
+    if (rows == 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate plan");
+    // one prediction per kernel row (its launch term included)
+    std::vector<size_t> start(rows + 1);
+    std::iota(start.begin(), start.end(), 0);
+    std::vector<double> kus;
+    st = costmodel_plan_us(o.model, feats, start, (hipStream_t)o.stream, &kus);
     if (st != KF_OK) return st;
-    // stable order by prediction; within 0.1% the earlier (fewer kernels) first
-    std::vector<size_t> order(ok.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return us[a] < us[b] * 0.999; });
-    int32_t best = ok[order[0]];
+    std::vector<std::vector<double>> cost(ps->parts.size());
+    std::vector<int32_t> ok;
+    std::vector<double> plan_us;
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        if (row_of[i] == SIZE_MAX) continue;
+        cost[i].assign(kus.begin() + row_of[i], kus.begin() + row_of[i] + nk_of[i]);
+        ok.push_back((int32_t)i);
+        plan_us.push_back(std::accumulate(cost[i].begin(), cost[i].end(), 0.0));
+    }
+    Combination best = best_combination(ps, cost);
     if (o.top_k > 1) {
-        std::vector<int32_t> top;
-        for (size_t j = 0; j < order.size() && (int)j < o.top_k; ++j) top.push_back(ok[order[j]]);
-        st = fastest_measured(ps, o, top, &best);
+        // time the top_k candidates by predicted plan time (within 0.1%: the
+        // earlier, fewer kernels, first) and the candidates of the predicted
+        // combination, kernel by kernel; combine the measured implementations
+        std::vector<size_t> order(ok.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return plan_us[a] < plan_us[b] * 0.999; });
+        std::vector<int32_t> timed;
+        for (size_t j = 0; j < order.size() && (int)j < o.top_k; ++j) timed.push_back(ok[order[j]]);
+        for (int32_t i : best.pick)
+            if (std::find(timed.begin(), timed.end(), i) == timed.end()) timed.push_back(i);
+        st = measured_combination(ps, o, timed, &best);
         if (st != KF_OK) return st;
     }
-    return kf_planset_compile(ps, best, o.flags, out);
+    return compile_combination(ps, best, o.flags, out);
 }
 
 kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {
@@ -480,10 +594,10 @@ kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_pl
     std::unique_ptr<kf_planset> guard(ps);
     std::vector<int32_t> all(ps->parts.size());
     std::iota(all.begin(), all.end(), 0);
-    int32_t best = -1;
-    st = fastest_measured(ps, o, all, &best);
+    Combination best;
+    st = measured_combination(ps, o, all, &best);
     if (st != KF_OK) return st;
-    return kf_planset_compile(ps, best, o.flags, out);
+    return compile_combination(ps, best, o.flags, out);
 }
 
 }  // namespace kf

@@ -55,6 +55,14 @@ class kf_compile_opts(ctypes.Structure):
     pass
 
 
+IMPL_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "mat_sched", "mat_unit",
+               "vec_unroll", "vec_threads", "vec_grid"]
+
+
+class kf_impl_params(ctypes.Structure):
+    _fields_ = [(f, _i32) for f in IMPL_FIELDS]
+
+
 kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("mat_k", _i32), ("mat_waves", _i32), ("mat_group", _i32), ("mat_rows", _i32),
                             ("vec_unroll", _i32), ("vec_threads", _i32), ("vec_grid", _i32),
@@ -63,7 +71,8 @@ kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("table", _P(kf_routine_entry)), ("table_len", _i32), ("max_partitions", _i32),
                             ("grid", _P(kf_compile_opts)), ("grid_len", _i32), ("mat_unit", _i32),
                             ("model", _vp), ("stream", _vp), ("bind_values", _P(_i32)), ("bind_ptrs", _P(_vp)),
-                            ("bind_len", _i32), ("top_k", _i32)]
+                            ("bind_len", _i32), ("top_k", _i32),
+                            ("kernel_params", _P(kf_impl_params)), ("kernel_params_len", _i32)]
 PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
                 "mat_sched", "mat_unit"]
 
@@ -114,6 +123,8 @@ _SIGS = {
     "kf_plan_num_launches": ([_vp, _i32, _P(_i32)], _i32),
     "kf_run_launch": ([_vp, _i32, _i32, _vp], _i32),
     "kf_time_plan": ([_vp, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_time_plan_kernels": ([_vp, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_plan_kernel_params": ([_vp, _i32, _P(kf_impl_params)], _i32),
     "kf_plan_describe": ([_vp, ctypes.c_char_p, _sz, _P(_sz)], _i32),
     "kf_plan_bytes": ([_vp, _P(_u64), _P(_u64)], _i32),
     "kf_plan_num_kernels": ([_vp, _P(_i32)], _i32),
@@ -293,10 +304,13 @@ def kf_script_call(s, i: int) -> dict:
 
 # ---- compile / enumerate --------------------------------------------------------
 def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid=None, max_partitions=0,
-                         model=None, stream=None, bind=None, top_k=0, **params) -> kf_compile_opts:
+                         model=None, stream=None, bind=None, top_k=0, kernel_params=None,
+                         **params) -> kf_compile_opts:
     """bind: {script value handle: device pointer} of every input and output
     (timing in the learned top-k and exhaustive modes); model: a cost-model
-    handle (kf_costmodel_create / kf_costmodel_load)."""
+    handle (kf_costmodel_create / kf_costmodel_load); kernel_params: one dict
+    of implementation parameters per plan kernel, in launch order (missing or
+    zero entries take the plan-wide parameters)."""
     o = kf_compile_opts()
     lib().kf_compile_opts_init(ctypes.byref(o))
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -328,6 +342,16 @@ def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid
         o.bind_ptrs = ctypes.cast(ptrs, _P(_vp))
         o.bind_len = len(bind)
         keep += [vals, ptrs]
+    if kernel_params:
+        karr = (kf_impl_params * len(kernel_params))()
+        for i, kp in enumerate(kernel_params):
+            for k, v in (kp or {}).items():
+                if k not in IMPL_FIELDS:
+                    raise TypeError("unknown kernel parameter %s" % k)
+                setattr(karr[i], k, int(v))
+        o.kernel_params = ctypes.cast(karr, _P(kf_impl_params))
+        o.kernel_params_len = len(kernel_params)
+        keep.append(karr)
     if partition is not None:
         arr = (_i32 * len(partition))(*partition)
         o.partition = ctypes.cast(arr, _P(_i32))
@@ -472,6 +496,21 @@ def kf_time_plan(p, stream: int = 0, warmup: int = 3, reps: int = 20) -> float:
     t = _f32()
     _chk(lib().kf_time_plan(p, _vp(stream), warmup, reps, ctypes.byref(t)))
     return t.value
+
+
+def kf_time_plan_kernels(p, stream: int = 0, warmup: int = 2, reps: int = 5) -> list:
+    """Median time (us) of every plan kernel inside whole runs of the plan."""
+    n = kf_plan_num_kernels(p)
+    t = (_f32 * n)()
+    _chk(lib().kf_time_plan_kernels(p, _vp(stream), warmup, reps, t))
+    return [float(x) for x in t]
+
+
+def kf_plan_kernel_params(p, k: int) -> dict:
+    """Implementation parameters of plan kernel k (defaults for its shape applied)."""
+    e = kf_impl_params()
+    _chk(lib().kf_plan_kernel_params(p, k, ctypes.byref(e)))
+    return {f: getattr(e, f) for f in IMPL_FIELDS if getattr(e, f)}
 
 
 def _text(fn, *args) -> str:

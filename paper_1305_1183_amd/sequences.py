@@ -106,6 +106,10 @@ class Program:
     def time(self, warmup=3, reps=20) -> float:
         return kf.kf_time_plan(self.plan, torch.cuda.current_stream().cuda_stream, warmup, reps)
 
+    def time_kernels(self, warmup=2, reps=10) -> list:
+        """Median time (us) of each plan kernel inside whole runs."""
+        return kf.kf_time_plan_kernels(self.plan, torch.cuda.current_stream().cuda_stream, warmup, reps)
+
 
 def _seq(name):
     return Sequence(name=name, script=kf.kf_script_create())

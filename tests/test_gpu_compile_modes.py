@@ -95,3 +95,20 @@ def test_shipped_library_format_model_predicts_like_npz():
     b = CostModel.load(MODEL.replace(".npz", ".kfcm"))
     X = np.random.default_rng(1).standard_normal((300, kf.FEATURE_DIM)).astype(np.float32)
     assert np.array_equal(a.predict_log(X), b.predict_log(X))
+
+
+@pytest.mark.parametrize("name", ["gemver", "atax"])
+def test_per_kernel_parameters_parity(name):
+    """A plan whose kernels use different parameter points computes the same
+    results; per-kernel times add up to about the plan time."""
+    m = n = 3000   # ragged against every strip width and row block
+    q, arrays, scal, dev, outs, bind = bound(name, m, n)
+    kp = [dict(mat_k=2, mat_waves=4, mat_group=2, mat_rows=2048), dict(mat_k=1, mat_waves=4, mat_group=2, mat_rows=1024)]
+    plan = kf.kf_compile(q.script, mode="unfused" if name == "atax" else "fused", kernel_params=kp)
+    assert [kf.kf_plan_kernel_params(plan, k) for k in range(2)] == kp
+    prog, host = run_plan(q, plan, dev)
+    SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))
+    ks = prog.time_kernels(2, 10)
+    assert len(ks) == 2 and all(t > 0 for t in ks)
+    whole = prog.time(2, 10)
+    assert 0.5 * whole < sum(ks) < 1.5 * whole + 20.0
