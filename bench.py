@@ -8,7 +8,7 @@ bytes of the six fused plans (each operand counted once per kernel that moves
 it through HBM, as in the paper's bandwidth figures) divided by the time of a
 step. Per-sequence fused and unfused times give the speedup of fusion.
 
-Prints one JSON line. `--gpus` above 1 is refused: this build runs on one GPU.
+Prints one JSON line. `--gpus` above 1 is refused: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -184,7 +184,7 @@ def batched_suite(args, torch, kf, WL, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+        print("bench.py: the benchmark runs on one GPU only; --gpus %d is not supported" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -48,7 +48,7 @@ enum {
     KF_ERR_COMPILE = -9,     /* hipRTC failed; the log is in kf_last_error  */
     KF_ERR_HIP = -10,        /* a HIP runtime call failed                   */
     KF_ERR_NOMEM = -11,      /* host allocation failed                      */
-    KF_ERR_UNSUPPORTED = -12,/* legal request this build does not handle    */
+    KF_ERR_UNSUPPORTED = -12,/* legal request the library does not handle  */
     KF_ERR_INTERNAL = -13
 };
 

@@ -7,7 +7,7 @@ parameter points (``kf.Candidates``). They are ranked by
   predicted per kernel as max(transfers, compute) and summed (``kf_predict_additive``);
 * the learned cost model: an MLP over kernel features predicting log time, a
   plan being the sum of its kernels plus a per-launch term;
-* exhaustive timing on the GPU, the judge of both.
+* exhaustive timing on the GPU, against which both are scored.
 """
 from __future__ import annotations
 
