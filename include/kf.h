@@ -289,7 +289,9 @@ kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps,
  * floats). Synchronises the stream. */
 kf_status kf_time_plan_kernels(kf_plan* p, void* stream, int32_t warmup, int32_t reps, float* us);
 /* The implementation parameters kernel k was generated with, after defaults
- * for its shape were applied (mat_* for BLAS-2 kernels, vec_* for BLAS-1). */
+ * for its shape were applied (mat_* for BLAS-2 kernels, vec_* for BLAS-1;
+ * mat_unit as requested, and only for kernels that load a BF16 or FP8
+ * matrix). */
 kf_status kf_plan_kernel_params(const kf_plan* p, int32_t k, kf_impl_params* out);
 
 /* ---- introspection -------------------------------------------------------- */

@@ -825,7 +825,7 @@ kf_status kf_plan_kernel_params(const kf_plan* p, int32_t k, kf_impl_params* out
         if (rowres && pk.mp.sched != 1) q.waves = q.group = q.rows = 0;   // strip parameters do not carry over
         r.mat_k = q.k; r.mat_waves = q.waves; r.mat_group = q.group; r.mat_rows = q.rows;
         r.mat_sched = rowres ? 1 : 0;
-        r.mat_unit = q.unit;
+        r.mat_unit = kernel_has_quantized(p->s, pk.code.calls) ? q.unit : 0;   // FP32 kernels have no load unit
     } else {
         const VecParams q = default_vec_params(sp.a, pk.vp);
         r.vec_unroll = q.unroll; r.vec_threads = q.threads; r.vec_grid = q.grid;

@@ -147,15 +147,30 @@ PREC_SEQ = ("bicgk", "gemver")
 
 
 PREC_PANEL = 512
-# tuned fused-plan parameters per (sequence, storage format) at n = 32768
+# tuned fused-plan parameters per (sequence, storage format) at n = 32768: each
+# kernel's point varied with the others fixed, timed kernel by kernel inside
+# whole runs; GEMVER's K2 reads the FP32 B whatever A's format
 PREC_TUNED = {
-    ("bicgk", "f32"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
-    ("bicgk", "bf16"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
-    ("bicgk", "fp8"): dict(mat_k=2, mat_waves=4, mat_group=4, mat_rows=1024),
-    ("gemver", "f32"): {},   # the library defaults (k 1, 4 waves, 4 rows per step, 512 rows)
-    ("gemver", "bf16"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256),
-    ("gemver", "fp8"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+    ("bicgk", "f32"): dict(mat_k=2, mat_waves=4, mat_group=2, mat_rows=2048),
+    ("bicgk", "bf16"): dict(mat_k=2, mat_waves=4, mat_group=2, mat_rows=2048),
+    ("bicgk", "fp8"): dict(mat_k=1, mat_waves=4, mat_group=2, mat_rows=1024),
+    ("gemver", "f32"): dict(kernel_params=[dict(mat_k=1, mat_waves=8, mat_group=2, mat_rows=1024),
+                                           dict(mat_sched=1, mat_waves=16, mat_group=2)]),
+    ("gemver", "bf16"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256,
+                             kernel_params=[{}, dict(mat_k=2, mat_waves=4, mat_group=4, mat_rows=2048)]),
+    ("gemver", "fp8"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024,
+                            kernel_params=[{}, dict(mat_k=2, mat_waves=2, mat_group=4, mat_rows=2048)]),
 }
+
+
+def plan_wide(params: dict) -> dict:
+    """One point for every kernel: the plan-wide fields, with the first
+    kernel's own point on top (for plans whose kernels differ in number)."""
+    out = {k: v for k, v in params.items() if k != "kernel_params"}
+    kp = params.get("kernel_params")
+    if kp:
+        out.update(kp[0] or {})
+    return out
 
 
 def normal_panel(seed: int, n: int, r0: int, panel: int = PREC_PANEL) -> np.ndarray:
