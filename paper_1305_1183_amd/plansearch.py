@@ -4,6 +4,10 @@
     python -m paper_1305_1183_amd.plansearch collect  --seeds 0:50 --out D0.npz
     python -m paper_1305_1183_amd.plansearch evaluate --data D*.npz --table T.json \
         --train 0:150 --eval 150:200 --out report.json --model model.npz
+    python -m paper_1305_1183_amd.plansearch combination --data D*.npz --eval 150:200 --out comb.json
+
+`combination` (host only) compares, on the collected timings, the best
+candidate with the best per-kernel combination of the candidates.
 
 `collect` times every sampled candidate plan of each script on the GPU
 (exhaustive search); `evaluate` trains the cost model on the training scripts
@@ -162,6 +166,22 @@ def cmd_evaluate(a):
     print(json.dumps(summary, indent=1), flush=True)
 
 
+def cmd_combination(a):
+    from . import search as SE
+    files = sorted(sum([glob.glob(p) for p in a.data], []))
+    data = SE.merge([dict(np.load(f, allow_pickle=False)) for f in files])
+    c_launch = SE.fit_launch_term(data, _range(a.train))
+    per = SE.combination_gain(data, _range(a.eval), c_launch, log=lambda s: print(s, flush=True))
+    g = np.array([r["gain"] for r in per])
+    summary = {"scripts": len(per), "launch_term_us": c_launch, "mean_gain": float(g.mean()),
+               "median_gain": float(np.median(g)), "max_gain": float(g.max()),
+               "frac_gain_above_2pct": float(np.mean(g > 0.02))}
+    json.dump({"what": "best per-kernel combination of the measured candidates against the best candidate, "
+                       "both as summed measured kernel times plus the fitted launch term",
+               "summary": summary, "per_script": per}, open(a.out, "w"), indent=1)
+    print(json.dumps(summary, indent=1), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -186,8 +206,14 @@ def main(argv=None):
     e.add_argument("--lr", type=float, default=1e-3)
     e.add_argument("--seed", type=int, default=0)
     e.add_argument("--topk", type=lambda s: [int(x) for x in s.split(",")], default=[1, 3])
+    cb = sub.add_parser("combination")
+    cb.add_argument("--data", nargs="+", required=True)
+    cb.add_argument("--train", default="0:150")
+    cb.add_argument("--eval", default="150:200")
+    cb.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    {"table": cmd_table, "collect": cmd_collect, "evaluate": cmd_evaluate}[a.cmd](a)
+    {"table": cmd_table, "collect": cmd_collect, "evaluate": cmd_evaluate,
+     "combination": cmd_combination}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -323,3 +323,43 @@ def rank_metrics(true_us, pred_us, tie=1e-3):
             "regret_top1": top1 / best - 1.0,
             "regret_top3": float(np.min(true_us[order[:3]])) / best - 1.0,
             "worst_pct_of_best": best / float(np.max(true_us)) * 100.0, "n": int(len(true_us))}
+
+
+def combination_gain(data, seeds, c_launch, log=None):
+    """Per script, the best measured candidate against the best per-kernel
+    combination of the measured candidates (Section 4.2: one implementation
+    per fused kernel), both estimated as the sum of measured kernel times plus
+    c_launch per launch: candidates sharing a partition are grouped, and each
+    kernel takes its fastest timing in the group (host only)."""
+    from . import randscript as R
+    out = []
+    kern_of = {}
+    for r, ci in enumerate(data["kern_cand"]):
+        kern_of.setdefault(int(ci), []).append(r)
+    for seed in seeds:
+        m = np.where(data["cand_seed"] == seed)[0]
+        if len(m) == 0:
+            continue
+        rs = R.random_script(seed)
+        c = kf.Candidates(rs.script, 64, grid_points())
+        groups = {}
+        for ci in m:
+            groups.setdefault(tuple(c.partition(int(data["cand_idx"][ci]))), []).append(int(ci))
+        est = {ci: sum(data["kern_us"][r] for r in kern_of[ci]) + c_launch * data["cand_launches"][ci] for ci in m}
+        uniform = min(est.values())
+        comb = None
+        for cis in groups.values():
+            nk = len(kern_of[cis[0]])
+            t = sum(min(data["kern_us"][kern_of[ci][k]] for ci in cis) for k in range(nk))
+            t += c_launch * data["cand_launches"][cis[0]]
+            comb = t if comb is None else min(comb, t)
+        row = {"seed": int(seed), "candidates": int(len(m)), "partitions": len(groups),
+               "best_measured_plan_us": float(data["plan_us"][m].min()),
+               "uniform_est_us": float(uniform), "combination_est_us": float(comb),
+               "gain": float(1.0 - comb / uniform)}
+        out.append(row)
+        if log:
+            log("script %d: %d candidates in %d partitions, combination %.1f%% below the best candidate" %
+                (seed, len(m), len(groups), row["gain"] * 100))
+        del c, rs
+    return out

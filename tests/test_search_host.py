@@ -108,3 +108,36 @@ def test_features_distinguish_fusion():
     assert ff.shape[0] == 1 and fu.shape[0] == 2
     assert ff[0, 5] > 20 and fu[0, 5] == 0      # bytes saved: log2(4 n^2) vs none
     assert ff[0, 9] == 1 and ff[0, 10] == 1      # one gemv and one gemtv
+
+
+def test_combination_gain_by_hand():
+    """Two measured candidates of one partition: every kernel takes its faster
+    timing; a third candidate of another partition competes as a whole."""
+    seed = 3
+    rs = R.random_script(seed)
+    c = kf.Candidates(rs.script, 64, SE.grid_points())
+    by_part = {}
+    for i in range(len(c)):
+        by_part.setdefault(tuple(c.partition(i)), []).append(i)
+    part, idx = next((p, v) for p, v in by_part.items() if len(v) >= 2 and max(p) >= 1)
+    other = next(v[0] for p, v in by_part.items() if p != part)
+    nk = max(part) + 1
+    k_a = [10.0] * nk
+    k_b = [10.0] * nk
+    k_a[0], k_b[0] = 4.0, 9.0
+    k_a[1], k_b[1] = 8.0, 3.0
+    k_o = [1000.0]
+    cand_idx = [idx[0], idx[1], other]
+    kern_cand, kern_us = [], []
+    for ci, ks in enumerate((k_a, k_b, k_o)):
+        kern_cand += [ci] * len(ks)
+        kern_us += ks
+    data = {"cand_seed": np.array([seed] * 3), "cand_idx": np.array(cand_idx),
+            "cand_launches": np.array([nk, nk, 1]), "plan_us": np.array([sum(k_a), sum(k_b), 1000.0]),
+            "kern_cand": np.array(kern_cand), "kern_us": np.array(kern_us)}
+    r = SE.combination_gain(data, [seed], c_launch=0.5)[0]
+    uniform = min(sum(k_a), sum(k_b)) + 0.5 * nk
+    comb = 4.0 + 3.0 + 10.0 * (nk - 2) + 0.5 * nk
+    assert r["partitions"] == 2 and r["candidates"] == 3
+    assert abs(r["uniform_est_us"] - uniform) < 1e-9 and abs(r["combination_est_us"] - comb) < 1e-9
+    assert abs(r["gain"] - (1 - comb / uniform)) < 1e-12
