@@ -530,6 +530,17 @@ kf_status kf_batch_error(kf_batch* b, void* stream, uint32_t* bits);
  * multiples of 16. Used to calibrate memory-traffic counters against a copy of
  * known size. */
 kf_status kf_util_copy(void* dst, const void* src, size_t bytes, void* stream);
+/* Streaming references for the bandwidth this device attains (no part of any
+ * plan), asynchronous on `stream`, 16-byte aligned pointers.
+ * kind 0, read: streams src[0..bytes) (bytes a multiple of 16) with 16-byte
+ *   non-temporal loads, eight in flight per lane, over 2048 workgroups; dst
+ *   receives each workgroup's sum of its floats (2048 floats, 8 KiB).
+ * kind 1, copy: dst[0..bytes) = src[0..bytes) (bytes a multiple of 64 KiB, no
+ *   overlap) in the layout of the strip kernels: rows of 64 KiB, 2 KiB column
+ *   strips, 2048 rows per workgroup of two waves (one workgroup per CU at
+ *   1 GiB), so few DRAM streams are open at once.
+ * KF_ERR_ARG for other kinds, sizes or alignments; KF_ERR_ALIAS for overlap. */
+kf_status kf_util_stream(int32_t kind, void* dst, const void* src, size_t bytes, void* stream);
 /* Seeded synthetic inputs on the device: dst[i * ld + j] for i < rows,
  * j < ld is, for j < cols, the SplitMix64 output number i * cols + j + 1 of
  * the stream that starts at `key`, mapped to (h >> 40) 2^-23 - 1 (uniform on

@@ -18,6 +18,7 @@ kf_status set_error(kf_status st, const std::string& msg) {
 }
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t launch_stream(int kind, void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_fill_uniform(float* dst, long rows, long cols, long ld, unsigned long long key, float pad,
                                hipStream_t st);
 
@@ -926,6 +927,21 @@ kf_status kf_util_fill_uniform(float* dst, int64_t rows, int64_t cols, int64_t l
                                void* stream) {
     if (!dst || rows < 0 || cols < 0 || ld < cols) return set_error(KF_ERR_ARG, "bad argument");
     hipError_t e = launch_fill_uniform(dst, rows, cols, ld, key, pad, (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(KF_ERR_HIP, hipGetErrorString(e));
+    return KF_OK;
+}
+
+kf_status kf_util_stream(int32_t kind, void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src || (uintptr_t)dst % 16 || (uintptr_t)src % 16) return set_error(KF_ERR_ARG, "null or unaligned buffer");
+    if (kind == 0) {
+        if (bytes % 16) return set_error(KF_ERR_ARG, "read reference needs a multiple of 16 bytes");
+    } else if (kind == 1) {
+        if (bytes % 65536) return set_error(KF_ERR_ARG, "copy reference needs a multiple of 64 KiB");
+        if (overlap(dst, bytes, src, bytes)) return set_error(KF_ERR_ALIAS, "copy reference buffers overlap");
+    } else {
+        return set_error(KF_ERR_ARG, "kind must be 0 (read) or 1 (copy)");
+    }
+    hipError_t e = launch_stream(kind, dst, src, bytes, (hipStream_t)stream);
     if (e != hipSuccess) return set_error(KF_ERR_HIP, hipGetErrorString(e));
     return KF_OK;
 }

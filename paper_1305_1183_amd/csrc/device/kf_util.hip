@@ -1,5 +1,6 @@
-// kf_util.hip -- ahead-of-time kernels of the runtime: counter reset and a
-// plain streaming copy used to calibrate memory counters.
+// kf_util.hip -- ahead-of-time kernels of the runtime: counter reset, a plain
+// streaming copy used to calibrate memory counters, streaming read and copy
+// references for the attainable bandwidth, and seeded input generation.
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -20,6 +21,59 @@ __global__ void __launch_bounds__(256) kf_copy_f4_kernel(f4_t* __restrict__ dst,
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x)
         __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// Streaming read reference: n float4 with non-temporal loads, grid-stride, eight
+// loads in flight per lane; workgroup g writes the sum of its share to sink[g].
+__global__ void __launch_bounds__(256) kf_read_f4_kernel(const f4_t* __restrict__ src, size_t n,
+                                                         float* __restrict__ sink) {
+    __shared__ float part[4];
+    constexpr int U = 8;
+    float acc = 0.f;
+    const size_t step = (size_t)gridDim.x * 256 * U;
+    for (size_t base = (size_t)blockIdx.x * 256 * U + threadIdx.x; base < n; base += step) {
+        f4_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + (size_t)u * 256;
+            v[u] = i < n ? __builtin_nontemporal_load(src + i) : f4_t{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = ((part[0] + part[1]) + part[2]) + part[3];
+}
+
+// Streaming copy reference in the layout of the strip kernels: the buffer is
+// rows of 4096 float4 (64 KiB); workgroup (strip s, block b) copies the 2 KiB
+// column strip s of rows b * 2048 ... with two waves, four rows per wave step.
+__global__ void __launch_bounds__(128) kf_copy_strip_kernel(f4_t* __restrict__ dst, const f4_t* __restrict__ src,
+                                                            long rows) {
+    constexpr int G = 4, W = 2, K = 2, COLS4 = 4096, RPW = 2048, STRIPS = COLS4 / (64 * K);
+    const int s = (int)(blockIdx.x % STRIPS);
+    const long rb = blockIdx.x / STRIPS;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const long r0 = rb * RPW, r1 = r0 + RPW < rows ? r0 + RPW : rows;
+    for (long r = r0 + wave * G; r < r1; r += W * G) {
+        f4_t v[G][K];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const long i = (r + g) * COLS4 + s * 64 * K + k * 64 + lane;
+                v[g][k] = r + g < r1 ? __builtin_nontemporal_load(src + i) : f4_t{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const long i = (r + g) * COLS4 + s * 64 * K + k * 64 + lane;
+                if (r + g < r1) __builtin_nontemporal_store(v[g][k], dst + i);
+            }
+    }
 }
 
 // Seeded uniform[-1, 1) input values: element (i, j) of a rows x cols block
@@ -72,6 +126,20 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
     if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(kf_copy_f4_kernel, dim3((unsigned)grid), dim3(256), 0, st, (f4_t*)dst,
                        (const f4_t*)src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(int kind, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    if (kind == 0) {
+        hipLaunchKernelGGL(kf_read_f4_kernel, dim3(2048), dim3(256), 0, st, (const f4_t*)src, n, (float*)dst);
+    } else {
+        const long rows = (long)(bytes / 65536);
+        const long grid = 32 * ((rows + 2047) / 2048);
+        hipLaunchKernelGGL(kf_copy_strip_kernel, dim3((unsigned)grid), dim3(128), 0, st, (f4_t*)dst,
+                           (const f4_t*)src, rows);
+    }
     return hipGetLastError();
 }
 

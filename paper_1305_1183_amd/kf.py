@@ -131,6 +131,7 @@ _SIGS = {
     "kf_plan_source": ([_vp, _i32, ctypes.c_char_p, _sz, _P(_sz)], _i32),
     "kf_plan_kernel_geometry": ([_vp, _i32, _P(_i32), _P(_i32)], _i32),
     "kf_util_copy": ([_vp, _vp, _sz, _vp], _i32),
+    "kf_util_stream": ([_i32, _vp, _vp, _sz, _vp], _i32),
     "kf_util_fill_uniform": ([_vp, _i64, _i64, _i64, _u64, _f32, _vp], _i32),
     "kf_jit_release": ([], _i32),
     "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
@@ -559,6 +560,12 @@ def kf_jit_stats():
 
 def kf_util_copy(dst: int, src: int, nbytes: int, stream: int = 0) -> None:
     _chk(lib().kf_util_copy(_vp(dst), _vp(src), nbytes, _vp(stream)))
+
+
+def kf_util_stream(kind: int, dst: int, src: int, nbytes: int, stream: int = 0) -> None:
+    """Streaming reference: kind 0 reads src (dst gets 2048 workgroup sums),
+    kind 1 copies src to dst in the strip kernels' layout."""
+    _chk(lib().kf_util_stream(int(kind), _vp(dst), _vp(src), nbytes, _vp(stream)))
 
 
 # ---- batched uneven sizes ------------------------------------------------------------

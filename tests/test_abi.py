@@ -232,3 +232,15 @@ def test_ranking_modes_check_their_inputs():
         kf.kf_compile(q.script, mode="learned")
     with pytest.raises(kf.KFError, match="KF_ERR_UNBOUND"):
         kf.kf_compile(q.script, mode="exhaustive")
+
+
+def test_stream_reference_checks_its_arguments():
+    """Rejected on the host before any device work (runs without a GPU)."""
+    a, b = 1 << 20, 1 << 30                           # 16-byte aligned stand-in addresses
+    for args in [(2, a, b, 65536), (1, a, b, 65536 + 16), (0, a, b, 12), (0, a + 4, b, 64), (1, 0, b, 65536)]:
+        with pytest.raises(kf.KFError) as e:
+            kf.kf_util_stream(*args)
+        assert e.value.name == "KF_ERR_ARG", args
+    with pytest.raises(kf.KFError) as e:
+        kf.kf_util_stream(1, a, a + 65536, 2 * 65536)  # overlapping copy
+    assert e.value.name == "KF_ERR_ALIAS"
