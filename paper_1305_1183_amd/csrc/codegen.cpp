@@ -732,8 +732,11 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
         for (int v : dot_out) { finl.args.push_back({ArgKind::DevScalarOut, v}); fsig.push_back(F("float* __restrict__ Y%d", v)); }
         finl.args.push_back({ArgKind::Workspace, -1});
         fsig.push_back("const float* __restrict__ ws");
-        f.l(F("constexpr int GRID = %d;", GRID));
-        f.l("__shared__ float kf_lds[4];");
+        // FT threads; thread t adds partials t, t + FT, ... in increasing order
+        // (Kahan), loading FU of them ahead of the dependent adds
+        const int FT = GRID >= 4096 ? 1024 : 256, FU = 8;
+        f.l(F("constexpr int GRID = %d, FT = %d, FU = %d;", GRID, FT, FU));
+        f.l("__shared__ float kf_lds[FT / 64];");
         f.l("const int tid = threadIdx.x;");
         for (int i = 0; i < ndot; ++i) {
             int c = dots[i];
@@ -741,15 +744,23 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
             f.l("{");
             f.ind++;
             f.l("float s = 0.f, comp = 0.f;");
-            f.l(F("for (int g = tid; g < GRID; g += 256) { const float y = ws[%dL * GRID + g] - comp; const float t = s + y; comp = (t - s) - y; s = t; }", i));
-            f.l("const float tot = kf_block_sum<4>(s, kf_lds);");
+            f.l("for (int g0 = tid; g0 < GRID; g0 += FT * FU) {");
+            f.ind++;
+            f.l("float yv[FU];");
+            f.l("#pragma unroll");
+            f.l(F("for (int u = 0; u < FU; ++u) yv[u] = g0 + u * FT < GRID ? ws[%dL * GRID + g0 + u * FT] : 0.f;", i));
+            f.l("#pragma unroll");
+            f.l("for (int u = 0; u < FU; ++u) { const float y = yv[u] - comp; const float t = s + y; comp = (t - s) - y; s = t; }");
+            f.ind--;
+            f.l("}");
+            f.l("const float tot = kf_block_sum<FT / 64>(s, kf_lds);");
             if (must_store(s, part, kid, k.out)) f.l(F("if (tid == 0) *Y%d = tot;", k.out));
             else f.l("(void)tot;");
             f.ind--;
             f.l("}");
         }
         finl.grid = 1;
-        finl.block = 256;
+        finl.block = FT;
     }
 
     std::string sigs, fsigs;
@@ -767,7 +778,7 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
     kc.launches.push_back(mainl);
     if (dot_part) {
         finl.name = kc.name + "_fin";
-        src << "extern \"C\" __global__ void __launch_bounds__(256) " << finl.name << "(\n"
+        src << "extern \"C\" __global__ void __launch_bounds__(" << finl.block << ") " << finl.name << "(\n"
             << fsigs << ") {\n" << f.o.str() << "}\n";
         kc.launches.push_back(finl);
     }

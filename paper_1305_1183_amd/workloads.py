@@ -103,8 +103,8 @@ TUNED = {
     ("gemver", "fused"): dict(kernel_params=[_LONG, _R8]),
     # one point for all four kernels: measured faster than the per-kernel choice
     ("gemver", "unfused"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
-    ("axpydot", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=2048),
-    ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=1024),
+    ("axpydot", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
+    ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("waxpby", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("waxpby", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("sgemvt", "fused"): dict(kernel_params=[_S1, dict(mat_sched=1, mat_waves=16, mat_group=4)]),
