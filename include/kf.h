@@ -435,9 +435,11 @@ kf_status kf_costmodel_load(const char* path, kf_costmodel** out);
 
 /* ---- run-time compilation cache ------------------------------------------ */
 /* Each plan kernel is compiled by hipRTC for gfx950 once per process (keyed
- * by a hash of its text); if the environment variable KF_CACHE_DIR names a
- * directory, code objects are also read from and written to it, so several
- * processes can share compilations. kf_jit_release unloads every loaded
+ * by a hash of its text); the kernels of a plan that are not loaded yet are
+ * compiled together in one hipRTC invocation (and, without a disk cache, one
+ * module). If the environment variable KF_CACHE_DIR names a directory, code
+ * objects are also read from and written to it, so several processes can
+ * share compilations. kf_jit_release unloads every loaded
  * module: all plans must have been destroyed before. kf_jit_stats reports the
  * number of loaded modules and of kernels compiled in this process. */
 kf_status kf_jit_release(void);

@@ -68,6 +68,42 @@ static kf_status ensure_loaded_locked(Registry& reg, const KernelCode& kc) {
     return KF_OK;
 }
 
+// Compile the kernels of one plan that are not loaded yet with one compiler
+// invocation (its fixed cost is most of a small kernel's compile time): into
+// the disk cache when one is configured (each kernel is then loaded from its
+// entry), else straight into one module. A failure here is not final: the
+// kernels are then compiled one by one, which names the failing kernel.
+static void load_together_locked(Registry& reg, const std::vector<const KernelCode*>& ks) {
+    std::vector<const KernelCode*> todo;
+    for (const KernelCode* k : ks) {
+        bool have = true;
+        for (const Launch& l : k->launches)
+            if (!reg.funcs.count(l.name)) have = false;
+        bool dup = false;
+        for (const KernelCode* t : todo)
+            if (t->name == k->name) dup = true;
+        if (!have && !dup) todo.push_back(k);
+    }
+    if (todo.size() < 2) return;
+    std::string co, log;
+    if (jit_cache_enabled()) {
+        (void)jit_precompile(todo, &log);
+        return;
+    }
+    if (!jit_compile_together(todo, &co, &log)) return;
+    hipModule_t mod = nullptr;
+    if (hipModuleLoadData(&mod, co.data()) != hipSuccess) return;
+    reg.modules.push_back(mod);
+    for (const KernelCode* k : todo) {
+        for (const Launch& l : k->launches) {
+            hipFunction_t fn = nullptr;
+            if (hipModuleGetFunction(&fn, mod, l.name.c_str()) != hipSuccess) return;
+            reg.funcs[l.name] = fn;
+        }
+        reg.compiled.insert(k->name);
+    }
+}
+
 // Compile (through the caches) and load one kernel; fills fns with one
 // function per launch.
 kf_status load_kernel(const KernelCode& kc, std::vector<void*>* fns) {
@@ -555,6 +591,11 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     Registry& reg = registry();
     std::lock_guard<std::mutex> lock(reg.mu);
     const bool load = !(o.flags & KF_COMPILE_NO_LOAD);
+    if (load) {
+        std::vector<const KernelCode*> all;
+        for (auto& k : p->ks) all.push_back(&k.code);
+        load_together_locked(reg, all);
+    }
     for (auto& k : p->ks) {
         const std::string& nm = k.code.name;
         if (!load) {

@@ -150,6 +150,18 @@ bool jit_compile_one(const KernelCode& k, std::string* code_object, std::string*
 
 namespace kf {
 
+bool jit_compile_together(const std::vector<const KernelCode*>& ks, std::string* code_object, std::string* log) {
+    std::string text = blocks_source() + "\n";
+    for (const KernelCode* k : ks) text += k->source + "\n";
+    if (const char* extra = std::getenv("KF_JIT_EXTRA_SOURCE")) text += std::string(extra) + "\n";
+    return rtc_compile(text, code_object, log);
+}
+
+bool jit_cache_enabled() {
+    const char* dir = std::getenv("KF_CACHE_DIR");
+    return dir && *dir;
+}
+
 bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log) {
     std::vector<const KernelCode*> todo;
     std::vector<std::string> paths;

@@ -154,6 +154,10 @@ kf_status load_kernel(const KernelCode& kc, std::vector<void*>* fns);
 // Compile several kernels as one translation unit into the disk cache (each
 // kernel's cache entry is a link to the shared code object).
 bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log);
+// Compile several kernels (distinct names) as one translation unit, without
+// the disk cache; and whether a disk cache directory is configured.
+bool jit_compile_together(const std::vector<const KernelCode*>& ks, std::string* code_object, std::string* log);
+bool jit_cache_enabled();
 
 }  // namespace kf
 

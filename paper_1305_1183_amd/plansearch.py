@@ -4,9 +4,11 @@
     python -m paper_1305_1183_amd.plansearch collect  --seeds 0:50 --out D0.npz
     python -m paper_1305_1183_amd.plansearch evaluate --data D*.npz --table T.json \
         --train 0:150 --eval 150:200 --out report.json --model model.npz
+    python -m paper_1305_1183_amd.plansearch modes --model M.kfcm --eval 150:160 --out modes.json
     python -m paper_1305_1183_amd.plansearch combination --data D*.npz --eval 150:200 --out comb.json
 
-`combination` (host only) compares, on the collected timings, the best
+`modes` runs kf_compile's learned and exhaustive modes end to end on random
+scripts and times the chosen plans. `combination` (host only) compares, on the collected timings, the best
 candidate with the best per-kernel combination of the candidates.
 
 `collect` times every sampled candidate plan of each script on the GPU
@@ -166,6 +168,65 @@ def cmd_evaluate(a):
     print(json.dumps(summary, indent=1), flush=True)
 
 
+def cmd_modes(a):
+    """kf_compile's ranking modes end to end on random scripts (GPU): the
+    learned mode (top-1 and timed top-k) against the exhaustive mode, both
+    combining kernel implementations; plan time and search time of each."""
+    import torch
+    from . import kf
+    from . import randscript as R
+    from . import search as SE
+    from .costmodel import CostModel
+
+    cm = CostModel.load(a.model)
+    cm.predict_log(np.zeros((1, kf.FEATURE_DIM), np.float32))   # device state of the model set up once
+    st = torch.cuda.current_stream().cuda_stream
+    per = []
+    for seed in _range(a.eval):
+        rs = R.random_script(seed)
+        inst = SE.Instance(rs)
+        bind = {v: t.data_ptr() for v, t in inst.t.items()}
+        row = {"seed": seed, "script": rs.describe()}
+        for key, kw in (("learned_top1", dict(mode="learned", model=cm.handle, top_k=0)),
+                        ("learned_top%d" % a.topk, dict(mode="learned", model=cm.handle, top_k=a.topk, bind=bind)),
+                        ("exhaustive", dict(mode="exhaustive", bind=bind))):
+            # every mode compiles from scratch: its own empty disk cache, no loaded modules
+            os.environ["KF_CACHE_DIR"] = os.path.join(a.cache, "s%d_%s" % (seed, key))
+            os.makedirs(os.environ["KF_CACHE_DIR"], exist_ok=True)
+            kf.kf_jit_release()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = kf.kf_compile(rs.script, stream=st, max_partitions=a.max_partitions, **kw)
+            search_s = time.perf_counter() - t0
+            inst.bind(plan)
+            us = kf.kf_time_plan(plan, st, 3, 20)
+            row[key] = {"plan_us": us, "search_s": search_s, "kernels": kf.kf_plan_num_kernels(plan)}
+            kf.kf_plan_destroy(plan)
+        for key in ("learned_top1", "learned_top%d" % a.topk):
+            row[key]["regret"] = row[key]["plan_us"] / row["exhaustive"]["plan_us"] - 1.0
+        per.append(row)
+        print("script %d: learned %.1f us (%.2f s), top-%d %.1f us (%.2f s), exhaustive %.1f us (%.2f s)" %
+              (seed, row["learned_top1"]["plan_us"], row["learned_top1"]["search_s"], a.topk,
+               row["learned_top%d" % a.topk]["plan_us"], row["learned_top%d" % a.topk]["search_s"],
+               row["exhaustive"]["plan_us"], row["exhaustive"]["search_s"]), flush=True)
+        del inst
+        torch.cuda.empty_cache()
+        kf.kf_jit_release()
+    summary = {}
+    exh_s = sum(r["exhaustive"]["search_s"] for r in per)
+    for key in ("learned_top1", "learned_top%d" % a.topk):
+        rg = np.array([r[key]["regret"] for r in per])
+        summary[key] = {"mean_regret": float(rg.mean()), "median_regret": float(np.median(rg)),
+                        "frac_within_5pct": float(np.mean(rg <= 0.05)),
+                        "search_time_ratio": exh_s / sum(r[key]["search_s"] for r in per),
+                        "plan_time_total_ratio_vs_exhaustive": float(sum(r[key]["plan_us"] for r in per) /
+                                                                      sum(r["exhaustive"]["plan_us"] for r in per))}
+    json.dump({"what": "kf_compile modes on random scripts: plan time (median of 20 runs) and search time "
+                       "(wall clock of kf_compile, compilation included)", "max_partitions": a.max_partitions,
+               "summary": summary, "per_script": per}, open(a.out, "w"), indent=1)
+    print(json.dumps(summary, indent=1), flush=True)
+
+
 def cmd_combination(a):
     from . import search as SE
     files = sorted(sum([glob.glob(p) for p in a.data], []))
@@ -206,13 +267,20 @@ def main(argv=None):
     e.add_argument("--lr", type=float, default=1e-3)
     e.add_argument("--seed", type=int, default=0)
     e.add_argument("--topk", type=lambda s: [int(x) for x in s.split(",")], default=[1, 3])
+    md = sub.add_parser("modes")
+    md.add_argument("--eval", default="150:160")
+    md.add_argument("--model", required=True)
+    md.add_argument("--out", required=True)
+    md.add_argument("--topk", type=int, default=3)
+    md.add_argument("--max-partitions", type=int, default=16)
+    md.add_argument("--cache", default="/tmp/kf_cache_modes", help="a fresh directory per script and mode")
     cb = sub.add_parser("combination")
     cb.add_argument("--data", nargs="+", required=True)
     cb.add_argument("--train", default="0:150")
     cb.add_argument("--eval", default="150:200")
     cb.add_argument("--out", required=True)
     a = ap.parse_args(argv)
-    {"table": cmd_table, "collect": cmd_collect, "evaluate": cmd_evaluate,
+    {"table": cmd_table, "collect": cmd_collect, "evaluate": cmd_evaluate, "modes": cmd_modes,
      "combination": cmd_combination}[a.cmd](a)
 
 

@@ -52,3 +52,19 @@ def test_calibration_copy_and_fill():
     host = I.matrix(seed, tid, rows, cols, ld)        # the host generator, same stream
     assert np.all(np.isnan(got[:, cols:]))
     assert np.array_equal(got[:, :cols], host[:, :cols])
+
+
+def test_plan_kernels_compile_together(monkeypatch):
+    """A plan's new kernels are compiled in one invocation into one module
+    (no disk cache) and still compute the right results."""
+    from paper_1305_1183_amd import workloads as WL
+    from tests import seqcheck as SC
+    monkeypatch.delenv("KF_CACHE_DIR", raising=False)
+    m, n = 999, 1234                                  # shapes no other test compiles
+    arrays, scal = WL.make("gemver", m, n, seed=21)
+    mods0, comp0 = kf.kf_jit_stats()
+    q, prog, host = SC.run_gpu("gemver", m, n, arrays, scal, mode="unfused", mat_rows=64, mat_waves=2, mat_group=4)
+    mods1, comp1 = kf.kf_jit_stats()
+    assert prog.num_kernels == 4
+    assert comp1 - comp0 == 4 and mods1 - mods0 == 1
+    SC.check_against_oracle("gemver", m, n, host, SC.oracle_outputs("gemver", arrays, scal, n))
