@@ -50,7 +50,7 @@ def cmd_collect(a):
     from . import search as SE
     d = SE.collect(_range(a.seeds), max_cands=a.max_cands, cache_dir=a.cache, workers=a.workers, reps=a.reps,
                    log=lambda s: print(s, flush=True),
-                   checkpoint=lambda part: np.savez_compressed(a.out, **part))
+                   checkpoint=lambda part: np.savez_compressed(a.out, **part), grid=a.grid)
     np.savez_compressed(a.out, **d)
     print("saved %d candidate timings, %d kernel timings, %d unique kernels -> %s" %
           (len(d["plan_us"]), len(d["kern_us"]), len(d["uk_seed"]), a.out), flush=True)
@@ -77,8 +77,11 @@ def cmd_evaluate(a):
     train_s = time.perf_counter() - t0
     kpred = np.exp(cm.predict_log(data["uk_feat"]))[data["kern_uk"]]
     c_launch = SE.fit_launch_term(data, train, kpred)
+    cm.set_launch_us(c_launch)            # the per-launch term travels with the model
     if a.model:
         cm.save(a.model)
+        if a.model.endswith(".npz"):
+            cm.save(a.model[:-4] + ".kfcm")
     table = None
     if a.table:
         T = json.load(open(a.table))
@@ -256,6 +259,8 @@ def main(argv=None):
     c.add_argument("--workers", type=int, default=14)
     c.add_argument("--reps", type=int, default=3)
     c.add_argument("--cache", default="/tmp/kf_cache")
+    c.add_argument("--grid", choices=("study", "default"), default="study",
+                   help="parameter points: the study's grid or the library's default candidate grid")
     e = sub.add_parser("evaluate")
     e.add_argument("--data", nargs="+", required=True)
     e.add_argument("--table", default="")

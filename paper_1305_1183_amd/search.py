@@ -100,12 +100,18 @@ def table_array(entries):
 # ---------------------------------------------------------------------------
 # data collection (exhaustive timing of sampled candidates)
 # ---------------------------------------------------------------------------
+def _grid(name: str):
+    """The study's parameter grid ("study") or the library's default candidate
+    grid ("default", None for kf_candidates)."""
+    return grid_points() if name == "study" else None
+
+
 def _precompile_job(args):
-    seed, idx, cache_dir = args
+    seed, idx, cache_dir, grid = args
     os.environ["KF_CACHE_DIR"] = cache_dir
     from . import randscript as R
     rs = R.random_script(seed)
-    c = kf.Candidates(rs.script, 64, grid_points())
+    c = kf.Candidates(rs.script, 64, _grid(grid))
     t0 = time.perf_counter()
     c.precompile(idx)
     dt = time.perf_counter() - t0
@@ -118,15 +124,15 @@ def _precompile_job(args):
     return seed, dt, len(names)
 
 
-def precompile(seeds, max_cands, cache_dir, workers):
+def precompile(seeds, max_cands, cache_dir, workers, grid="study"):
     """Batch-compile the sampled candidates of each script in worker processes."""
     import multiprocessing as mp
     from . import randscript as R
     jobs = []
     for seed in seeds:
         rs = R.random_script(seed)
-        c = kf.Candidates(rs.script, 64, grid_points())
-        jobs.append((seed, sample_candidates(len(c), max_cands, seed), cache_dir))
+        c = kf.Candidates(rs.script, 64, _grid(grid))
+        jobs.append((seed, sample_candidates(len(c), max_cands, seed), cache_dir, grid))
         del c, rs
     ctx = mp.get_context("spawn")
     out = {}
@@ -190,7 +196,8 @@ def _name_hash(name: str) -> int:
     return int(name.split("_")[-1][:15], 16) if "_" in name else 0
 
 
-def collect(seeds, max_cands=512, cache_dir="/tmp/kf_cache", workers=14, reps=3, log=print, checkpoint=None):
+def collect(seeds, max_cands=512, cache_dir="/tmp/kf_cache", workers=14, reps=3, log=print, checkpoint=None,
+            grid="study"):
     """Exhaustively time the candidates of each script (GPU). Kernels shared by
     several candidates are stored once (uk_*); kern_* rows are (candidate,
     kernel) timings."""
@@ -198,7 +205,7 @@ def collect(seeds, max_cands=512, cache_dir="/tmp/kf_cache", workers=14, reps=3,
     from . import randscript as R
     os.makedirs(cache_dir, exist_ok=True)
     os.environ["KF_CACHE_DIR"] = cache_dir
-    comp, chosen = precompile(seeds, max_cands, cache_dir, workers)
+    comp, chosen = precompile(seeds, max_cands, cache_dir, workers, grid)
     rec = {k: [] for k in ("cand_seed", "cand_idx", "plan_us", "cand_nk", "cand_wall", "cand_launches")}
     krec = {k: [] for k in ("kern_cand", "kern_uk", "kern_us")}
     urec = {k: [] for k in ("uk_seed", "uk_hash", "uk_feat")}
@@ -206,7 +213,7 @@ def collect(seeds, max_cands=512, cache_dir="/tmp/kf_cache", workers=14, reps=3,
                             "script_load_s", "script_ncands")}
     for seed in seeds:
         rs = R.random_script(seed)
-        c = kf.Candidates(rs.script, 64, grid_points())
+        c = kf.Candidates(rs.script, 64, _grid(grid))
         idx = chosen[seed]
         t0 = time.perf_counter()
         feats, ukmap = [], {}
