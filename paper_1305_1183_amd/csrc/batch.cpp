@@ -58,12 +58,12 @@ struct kf_batch {
     Graph graphs[2];
     ~kf_batch() {
         for (Graph& g : graphs) {
-            if (g.x) hipGraphExecDestroy(g.x);
-            if (g.g) hipGraphDestroy(g.g);
+            if (g.x) (void)hipGraphExecDestroy(g.x);
+            if (g.g) (void)hipGraphDestroy(g.g);
         }
-        if (d_insts) hipFree(d_insts);
-        if (d_queue) hipFree(d_queue);
-        if (d_by_inst) hipFree(d_by_inst);
+        if (d_insts) (void)hipFree(d_insts);
+        if (d_queue) (void)hipFree(d_queue);
+        if (d_by_inst) (void)hipFree(d_by_inst);
     }
     size_t sync_bytes() const { return (size_t)((sync_words * 4 + 255) / 256 * 256); }
     size_t ws_bytes() const { return sync_bytes() + (size_t)ws_floats * 4; }
@@ -310,8 +310,8 @@ kf_status kf_batch_bind(kf_batch* b, float* arena, void* workspace, void* stream
     }
     hipStream_t st = (hipStream_t)stream;
     for (Graph& g : b->graphs) {
-        if (g.x) hipGraphExecDestroy(g.x);
-        if (g.g) hipGraphDestroy(g.g);
+        if (g.x) (void)hipGraphExecDestroy(g.x);
+        if (g.g) (void)hipGraphDestroy(g.g);
         g = Graph();
     }
     if (!b->d_insts && !b->insts.empty()) {
@@ -367,8 +367,8 @@ kf_status kf_batch_run(kf_batch* b, int32_t which, void* stream) {
 kf_status kf_batch_capture(kf_batch* b, int32_t which, void* stream) {
     if (!b || which < 0 || which > 1 || !stream) return set_error(KF_ERR_ARG, "bad argument (capture needs a non-null stream)");
     Graph& g = b->graphs[which];
-    if (g.x) hipGraphExecDestroy(g.x);
-    if (g.g) hipGraphDestroy(g.g);
+    if (g.x) (void)hipGraphExecDestroy(g.x);
+    if (g.g) (void)hipGraphDestroy(g.g);
     g = Graph();
     hipStream_t st = (hipStream_t)stream;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)

@@ -53,15 +53,6 @@ Space call_space(const Script& s, int c) {
     return sp;
 }
 
-static std::vector<int> call_operands(const Call& c) {
-    std::vector<int> v;
-    if (c.alpha >= 0) v.push_back(c.alpha);
-    if (c.beta >= 0) v.push_back(c.beta);
-    for (int i = 0; i < 3; ++i)
-        if (c.in[i] >= 0) v.push_back(c.in[i]);
-    return v;
-}
-
 // Data values (vectors, matrices) a call touches, inputs and output.
 static std::vector<int> call_data(const Script& s, int ci) {
     std::vector<int> v;
