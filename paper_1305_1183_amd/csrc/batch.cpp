@@ -377,13 +377,13 @@ kf_status kf_batch_capture(kf_batch* b, int32_t which, void* stream) {
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &graph);
     if (s != KF_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return s;
     }
     if (e != hipSuccess || !graph) return set_error(KF_ERR_HIP, "hipStreamEndCapture failed");
     g.g = graph;
     if (hipGraphInstantiate(&g.x, graph, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(graph);
+        (void)hipGraphDestroy(graph);
         g = Graph();
         return set_error(KF_ERR_HIP, "hipGraphInstantiate failed");
     }
@@ -426,7 +426,7 @@ kf_status kf_batch_time(kf_batch* b, int32_t which, int32_t graph, void* stream,
         t.push_back(ms * 1000.f);
     }
     for (auto& e : ev)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     if (out != KF_OK) return out;
     std::sort(t.begin(), t.end());
     *median_us = t[t.size() / 2];
