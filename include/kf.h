@@ -233,9 +233,10 @@ kf_status kf_planset_get(const kf_planset* ps, int32_t i, int32_t* partition, in
 
 /* Candidate plans (Section 4.2, fusion implementations): the first
  * max_partitions legal partitions crossed with the implementation parameter
- * points grid[0..grid_len) (mode and partition fields ignored; only the fields
- * of the kernel classes present matter, and candidates whose kernels would be
- * identical are listed once). Each candidate uses one point for all its
+ * points grid[0..grid_len) (only their implementation parameters are read, as
+ * one point for every kernel of a candidate; kernel_params and the other fields
+ * of the entries are ignored; only the fields of the kernel classes present
+ * matter, and candidates whose kernels would be identical are listed once). Each candidate uses one point for all its
  * kernels; the ranking modes of kf_compile combine, per partition, kernels of
  * different candidates. grid = NULL takes 32 points: the shape-dependent
  * defaults, six fixed strip shapes and the row-resident schedule, crossed with

@@ -260,6 +260,8 @@ kf_status kf_candidates(const kf_script* s, int32_t max_partitions, const kf_com
                 o.partition = part.data();
                 o.partition_len = (int32_t)part.size();
                 o.table = nullptr; o.table_len = 0; o.grid = nullptr; o.grid_len = 0;
+                o.kernel_params = nullptr; o.kernel_params_len = 0;   // a grid point is one point for all kernels
+                o.model = nullptr; o.bind_values = nullptr; o.bind_ptrs = nullptr; o.bind_len = 0;
                 o.flags = KF_COMPILE_CODEGEN_ONLY;
                 kf_plan* p = nullptr;
                 if (build_plan(s->s, part, o, &p) != KF_OK) continue;  // illegal point for this shape
