@@ -212,6 +212,11 @@ typedef struct kf_compile_opts {
      * Not owned; read during the call only. */
     const kf_impl_params* kernel_params;
     int32_t kernel_params_len;
+    /* KF_MODE_EXHAUSTIVE and KF_MODE_LEARNED with top_k > 1: once this many
+     * milliseconds of wall clock have passed since timing began, no further
+     * candidate is timed and those timed so far (at least one) are combined;
+     * 0 = no limit. */
+    int32_t time_budget_ms;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
@@ -444,6 +449,10 @@ kf_status kf_costmodel_load(const char* path, kf_costmodel** out);
  * module: all plans must have been destroyed before. kf_jit_stats reports the
  * number of loaded modules and of kernels compiled in this process. */
 kf_status kf_jit_release(void);
+/* Disk cache directory for later compilations, in place of KF_CACHE_DIR: an
+ * existing directory, "" for no disk cache, or NULL to go back to the
+ * environment variable. KF_ERR_ARG if dir is not a directory. Process-wide. */
+kf_status kf_jit_set_cache_dir(const char* dir);
 kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
 
 /* ---- batched uneven sizes: one persistent launch --------------------------

@@ -6,6 +6,8 @@
 #include <mutex>
 #include <sstream>
 
+#include <sys/stat.h>
+
 #include "kf_internal.h"
 
 namespace kf {
@@ -953,6 +955,15 @@ kf_status kf_jit_release(void) {
     reg.funcs.clear();
     reg.compiled.clear();
     reg.by_ident.clear();
+    return KF_OK;
+}
+
+kf_status kf_jit_set_cache_dir(const char* dir) {
+    if (dir && *dir) {
+        struct stat st;
+        if (::stat(dir, &st) != 0 || !S_ISDIR(st.st_mode)) return set_error(KF_ERR_ARG, std::string("not a directory: ") + dir);
+    }
+    jit_set_cache_dir(dir ? dir : "", dir == nullptr);
     return KF_OK;
 }
 

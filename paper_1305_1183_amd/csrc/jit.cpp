@@ -2,11 +2,12 @@
 //
 // The paper's compiler emits CUDA source and hands it to the vendor compiler
 // (Section 4.3); here every generated kernel is compiled in-process by hipRTC
-// into a gfx950 code object, one translation unit per plan kernel (building
-// blocks + the kernel's launches). Code objects are cached in memory and, when
-// KF_CACHE_DIR names a directory, on disk under a hash of the unit's text and
-// options, so that separate processes can compile candidate plans in parallel
-// and the process that times them only loads the results.
+// into a gfx950 code object: the building blocks plus the launches of one plan
+// kernel, or of all the kernels of a plan not compiled yet. Code objects are
+// cached in memory and, when a cache directory is set (kf_jit_set_cache_dir,
+// else KF_CACHE_DIR), on disk under a hash of the unit's text and options, so
+// that separate processes can compile candidate plans in parallel and the
+// process that times them only loads the results.
 #include <hip/hiprtc.h>
 
 #include <cstdio>
@@ -51,9 +52,30 @@ static std::string unit_text(const KernelCode& k) {
     return t;
 }
 
-static std::string cache_path(const std::string& text) {
+// The disk cache directory: the one set through kf_jit_set_cache_dir, else
+// KF_CACHE_DIR from the environment, else none.
+static std::mutex g_dir_mu;
+static bool g_dir_set = false;
+static std::string g_dir;
+
+static std::string cache_dir() {
+    {
+        std::lock_guard<std::mutex> lock(g_dir_mu);
+        if (g_dir_set) return g_dir;
+    }
     const char* dir = std::getenv("KF_CACHE_DIR");
-    if (!dir || !*dir) return "";
+    return dir ? std::string(dir) : std::string();
+}
+
+void jit_set_cache_dir(const char* dir, bool use_env) {
+    std::lock_guard<std::mutex> lock(g_dir_mu);
+    g_dir_set = !use_env;
+    g_dir = dir ? dir : "";
+}
+
+static std::string cache_path(const std::string& text) {
+    const std::string dir = cache_dir();
+    if (dir.empty()) return "";
     std::string key = text;
     for (const char* o : kOpts) key += std::string("\n") + o;
     char name[64];
@@ -157,10 +179,7 @@ bool jit_compile_together(const std::vector<const KernelCode*>& ks, std::string*
     return rtc_compile(text, code_object, log);
 }
 
-bool jit_cache_enabled() {
-    const char* dir = std::getenv("KF_CACHE_DIR");
-    return dir && *dir;
-}
+bool jit_cache_enabled() { return !cache_dir().empty(); }
 
 bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log) {
     std::vector<const KernelCode*> todo;

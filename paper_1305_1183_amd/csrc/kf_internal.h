@@ -158,6 +158,8 @@ bool jit_precompile(const std::vector<const KernelCode*>& ks, std::string* log);
 // the disk cache; and whether a disk cache directory is configured.
 bool jit_compile_together(const std::vector<const KernelCode*>& ks, std::string* code_object, std::string* log);
 bool jit_cache_enabled();
+// Disk cache directory for later compilations (use_env: back to KF_CACHE_DIR).
+void jit_set_cache_dir(const char* dir, bool use_env);
 
 }  // namespace kf
 

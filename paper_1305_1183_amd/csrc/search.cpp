@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <chrono>
 #include <array>
 #include <cstring>
 #include <memory>
@@ -517,15 +518,22 @@ kf_status measured_combination(const kf_planset* ps, const kf_compile_opts& o, c
                                Combination* best) {
     if (!o.bind_values || !o.bind_ptrs || o.bind_len < 1)
         return set_error(KF_ERR_UNBOUND, "timing candidates needs the buffers of opts.bind_values / bind_ptrs");
+    if (o.time_budget_ms < 0) return set_error(KF_ERR_ARG, "time_budget_ms must be >= 0");
+    const auto t0 = std::chrono::steady_clock::now();
     kf_planset_precompile(ps, order.data(), (int32_t)order.size());
     Timer t(ps, o);
     std::vector<std::vector<double>> cost(ps->parts.size());
+    bool any = false;
     for (int32_t i : order) {
+        if (any && o.time_budget_ms > 0 &&
+            std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(o.time_budget_ms))
+            break;
         std::vector<double> us;
         kf_status s = t.time_kernels(i, &us);
         if (s == KF_ERR_HIP || s == KF_ERR_UNBOUND || s == KF_ERR_ALIGN || s == KF_ERR_ALIAS) return s;
         if (s != KF_OK) continue;
         cost[i] = std::move(us);
+        any = true;
     }
     *best = best_combination(ps, cost);
     if (best->first < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");

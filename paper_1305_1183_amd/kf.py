@@ -72,7 +72,8 @@ kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("grid", _P(kf_compile_opts)), ("grid_len", _i32), ("mat_unit", _i32),
                             ("model", _vp), ("stream", _vp), ("bind_values", _P(_i32)), ("bind_ptrs", _P(_vp)),
                             ("bind_len", _i32), ("top_k", _i32),
-                            ("kernel_params", _P(kf_impl_params)), ("kernel_params_len", _i32)]
+                            ("kernel_params", _P(kf_impl_params)), ("kernel_params_len", _i32),
+                            ("time_budget_ms", _i32)]
 PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
                 "mat_sched", "mat_unit"]
 
@@ -132,6 +133,7 @@ _SIGS = {
     "kf_plan_kernel_geometry": ([_vp, _i32, _P(_i32), _P(_i32)], _i32),
     "kf_util_copy": ([_vp, _vp, _sz, _vp], _i32),
     "kf_util_stream": ([_i32, _vp, _vp, _sz, _vp], _i32),
+    "kf_jit_set_cache_dir": ([ctypes.c_char_p], _i32),
     "kf_util_fill_uniform": ([_vp, _i64, _i64, _i64, _u64, _f32, _vp], _i32),
     "kf_jit_release": ([], _i32),
     "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
@@ -305,7 +307,7 @@ def kf_script_call(s, i: int) -> dict:
 
 # ---- compile / enumerate --------------------------------------------------------
 def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid=None, max_partitions=0,
-                         model=None, stream=None, bind=None, top_k=0, kernel_params=None,
+                         model=None, stream=None, bind=None, top_k=0, kernel_params=None, time_budget_ms=0,
                          **params) -> kf_compile_opts:
     """bind: {script value handle: device pointer} of every input and output
     (timing in the learned top-k and exhaustive modes); model: a cost-model
@@ -318,6 +320,7 @@ def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid
     o.flags = flags
     o.max_partitions = max_partitions
     o.top_k = int(top_k)
+    o.time_budget_ms = int(time_budget_ms)
     if model is not None:
         o.model = model
     if stream is not None:
@@ -550,6 +553,11 @@ def kf_plan_kernel_geometry(p, k: int):
 
 def kf_jit_release() -> None:
     _chk(lib().kf_jit_release())
+
+
+def kf_jit_set_cache_dir(path) -> None:
+    """Disk cache directory for later compilations ("" = none, None = KF_CACHE_DIR)."""
+    _chk(lib().kf_jit_set_cache_dir(None if path is None else str(path).encode()))
 
 
 def kf_jit_stats():

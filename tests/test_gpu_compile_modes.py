@@ -112,3 +112,25 @@ def test_per_kernel_parameters_parity(name):
     assert len(ks) == 2 and all(t > 0 for t in ks)
     whole = prog.time(2, 10)
     assert 0.5 * whole < sum(ks) < 1.5 * whole + 20.0
+
+
+def test_time_budget_stops_timing_early():
+    """With a 1 ms budget the exhaustive mode times one candidate (plus the ones
+    already under way) and still returns a correct plan, sooner than without."""
+    import time
+    name, m, n = "gemver", 2048, 2048
+    q, arrays, scal, dev, outs, bind = bound(name, m, n)
+    st = torch.cuda.current_stream().cuda_stream
+    kf.kf_compile(q.script, mode="exhaustive", bind=bind, stream=st)   # compile caches warm for both runs
+    t0 = time.perf_counter()
+    full = kf.kf_compile(q.script, mode="exhaustive", bind=bind, stream=st)
+    t_full = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = kf.kf_compile(q.script, mode="exhaustive", bind=bind, stream=st, time_budget_ms=1)
+    t_budget = time.perf_counter() - t0
+    kf.kf_plan_destroy(full)
+    prog, host = run_plan(q, plan, dev)
+    SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))
+    assert t_budget < t_full
+    with pytest.raises(kf.KFError):
+        kf.kf_compile(q.script, mode="exhaustive", bind=bind, stream=st, time_budget_ms=-1)

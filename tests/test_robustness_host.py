@@ -87,3 +87,29 @@ def test_shipped_costmodel_files_agree():
     assert np.array_equal(p, z["params"]) and np.array_equal(mu, z["mu"]) and np.array_equal(sd, z["sd"])
     assert np.array_equal(y, z["y"])
     assert lu > 0
+
+
+def test_cache_dir_set_through_the_api(tmp_path, monkeypatch):
+    """kf_jit_set_cache_dir overrides KF_CACHE_DIR: a compile (no device needed)
+    writes its code object there; "" turns the disk cache off; None goes back to
+    the environment. A path that is not a directory is refused."""
+    monkeypatch.delenv("KF_CACHE_DIR", raising=False)
+    d = tmp_path / "cache"
+    d.mkdir()
+    q = S.waxpby(12349, 1.25, 0.75)
+    try:
+        kf.kf_jit_set_cache_dir(str(d))
+        p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+        kf.kf_plan_destroy(p)
+        files = glob.glob(str(d / "kf_*.co"))
+        assert len(files) == 1
+        with pytest.raises(kf.KFError) as e:
+            kf.kf_jit_set_cache_dir(str(d / "missing"))
+        assert e.value.name == "KF_ERR_ARG"
+        kf.kf_jit_set_cache_dir("")
+        q2 = S.waxpby(12351, 1.25, 0.75)
+        p = kf.kf_compile(q2.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+        kf.kf_plan_destroy(p)
+        assert len(glob.glob(str(d / "kf_*.co"))) == 1   # nothing written with the cache off
+    finally:
+        kf.kf_jit_set_cache_dir(None)
