@@ -134,3 +134,24 @@ def test_time_budget_stops_timing_early():
     assert t_budget < t_full
     with pytest.raises(kf.KFError):
         kf.kf_compile(q.script, mode="exhaustive", bind=bind, stream=st, time_budget_ms=-1)
+
+
+def test_blas1_unfused_kernels_with_their_own_parameters():
+    n = (1 << 20) + 3                                 # ragged against every unroll
+    q, arrays, scal, dev, outs, bind = bound("axpydot", n, n)
+    kp = [dict(vec_unroll=8, vec_threads=256, vec_grid=64), dict(vec_unroll=1, vec_threads=1024, vec_grid=4096)]
+    plan = kf.kf_compile(q.script, mode="unfused", kernel_params=kp)
+    got = [kf.kf_plan_kernel_params(plan, k) for k in range(2)]
+    assert got[0]["vec_unroll"] == 8 and got[1]["vec_threads"] == 1024
+    prog, host = run_plan(q, plan, dev)
+    SC.check_against_oracle("axpydot", n, n, host, SC.oracle_outputs("axpydot", arrays, scal, n))
+
+
+def test_learned_top_k_with_a_time_budget():
+    name, m, n = "bicgk", 2048, 2048
+    q, arrays, scal, dev, outs, bind = bound(name, m, n)
+    cm = CostModel.load(MODEL.replace(".npz", ".kfcm"))
+    st = torch.cuda.current_stream().cuda_stream
+    plan = kf.kf_compile(q.script, mode="learned", model=cm.handle, stream=st, top_k=5, bind=bind, time_budget_ms=1)
+    prog, host = run_plan(q, plan, dev)
+    SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))

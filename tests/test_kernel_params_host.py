@@ -108,3 +108,24 @@ def test_additive_mode_picks_the_cheapest_combination():
         assert got < kf.kf_predict_additive(u, T)
         kf.kf_plan_destroy(u)
     kf.kf_plan_destroy(p)
+
+
+def test_mixed_classes_take_their_own_fields():
+    """In a plan with BLAS-1 and BLAS-2 kernels, each kernel reads only the
+    fields of its class from its entry."""
+    import paper_1305_1183_amd.randscript as R
+    rs = next(r for r in (R.random_script(s) for s in range(40))
+              if {"dot", "gemv"} <= set(r.calls) or {"axpy", "gemv"} <= set(r.calls))
+    p = kf.kf_compile(rs.script, mode="unfused", flags=CG)
+    nk = kf.kf_plan_num_kernels(p)
+    d = json.loads(kf.kf_plan_describe(p))
+    kf.kf_plan_destroy(p)
+    entry = dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024, vec_unroll=2, vec_threads=512, vec_grid=64)
+    p = kf.kf_compile(rs.script, mode="unfused", flags=CG, kernel_params=[entry] * nk)
+    for k, kd in enumerate(d["kernels"]):
+        got = kf.kf_plan_kernel_params(p, k)
+        if kd["class"] == "blas2":
+            assert got == dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024), got
+        else:
+            assert got["vec_unroll"] == 2 and got["vec_threads"] == 512 and "mat_k" not in got, got
+    kf.kf_plan_destroy(p)
