@@ -124,6 +124,22 @@ __device__ __forceinline__ bool kfb_arrive(unsigned* counter, unsigned count, in
     return *s_flag != 0;
 }
 
+// Arrival that publishes nothing (only counts): no fences. The K2 blocks of a
+// split GEMVER instance use it to find the last one, which clears the
+// instance's flag for the next launch; every block has passed its wait on the
+// flag before it arrives, and the next launch starts after this one ends.
+__device__ __forceinline__ bool kfb_count(unsigned* counter, unsigned count, int* s_flag) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned old = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int last = old == count - 1;
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_flag = last;
+    }
+    __syncthreads();
+    return *s_flag != 0;
+}
+
 // Chunk k of a thread covers columns col .. col + 3, col = 4 (cl + k TPR).
 // Per chunk the thread keeps the load column clamped into the row (cc) and
 // the number of its columns below n (nv, 0 .. 4), both 32-bit.
@@ -442,7 +458,7 @@ __device__ void kfb_gemver_k2(const kfb_inst& I, int blk, float* __restrict__ ar
     const int r0 = blk * I.rows, r1 = min(n, r0 + I.rows);
     kfb_gemv_rows<LTPR, K, LG>(I, B, w, r0, r1, sh.cv[0]);
     // the last K2 block of the instance clears the flag for the next launch
-    if (kfb_arrive(ctr + 2, (unsigned)I.nblk, &sh.flag) && threadIdx.x == 0)
+    if (kfb_count(ctr + 2, (unsigned)I.nblk, &sh.flag) && threadIdx.x == 0)
         __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
