@@ -156,10 +156,12 @@ PREC_TUNED = {
     ("bicgk", "fp8"): dict(mat_k=1, mat_waves=4, mat_group=2, mat_rows=1024),
     ("gemver", "f32"): dict(kernel_params=[dict(mat_k=1, mat_waves=8, mat_group=2, mat_rows=1024),
                                            dict(mat_sched=1, mat_waves=16, mat_group=2)]),
-    ("gemver", "bf16"): dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256,
-                             kernel_params=[{}, dict(mat_k=2, mat_waves=4, mat_group=4, mat_rows=2048)]),
-    ("gemver", "fp8"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024,
-                            kernel_params=[{}, dict(mat_k=2, mat_waves=2, mat_group=4, mat_rows=2048)]),
+    # per-kernel points only: a plan-wide mat_rows would also set the rows per
+    # workgroup of the row-resident K2
+    ("gemver", "bf16"): dict(kernel_params=[dict(mat_k=1, mat_waves=8, mat_group=4, mat_rows=256),
+                                            dict(mat_sched=1, mat_waves=16, mat_group=2, mat_rows=128)]),
+    ("gemver", "fp8"): dict(kernel_params=[dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
+                                           dict(mat_sched=1, mat_waves=16, mat_group=2, mat_rows=128)]),
 }
 
 
