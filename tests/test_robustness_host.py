@@ -86,7 +86,7 @@ def test_shipped_costmodel_files_agree():
     assert [int(v) for v in z["dims"][:3]] == [dim, hid, layers]
     assert np.array_equal(p, z["params"]) and np.array_equal(mu, z["mu"]) and np.array_equal(sd, z["sd"])
     assert np.array_equal(y, z["y"])
-    assert lu > 0
+    assert lu >= 0 and ('launch_us' not in z.files or np.float32(z['launch_us']) == lu)
 
 
 def test_cache_dir_set_through_the_api(tmp_path, monkeypatch):
