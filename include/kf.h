@@ -180,9 +180,11 @@ typedef struct kf_compile_opts {
      * recording order), ids 0..K-1. */
     const int32_t* partition;
     int32_t partition_len;
-    /* KF_MODE_ADDITIVE: the routine table, the number of partitions considered
-     * (0 = 64) and the implementation-parameter points to cross them with
-     * (NULL = every environment present in the table). */
+    /* Ranking modes: the number of partitions considered (0 = 64) and the
+     * implementation-parameter points to cross them with (NULL: every
+     * environment present in the routine table for KF_MODE_ADDITIVE, the
+     * default grid of kf_candidates for the other two). KF_MODE_ADDITIVE: the
+     * routine table. */
     const struct kf_routine_entry* table;
     int32_t table_len;
     int32_t max_partitions;
@@ -208,8 +210,10 @@ typedef struct kf_compile_opts {
     /* Per-kernel parameters (modes UNFUSED, FUSED, PARTITION): entry i applies
      * to the i-th kernel of the plan in launch order (the order of
      * kf_plan_describe); kernels past kernel_params_len, and zero fields, use
-     * the parameters above. KF_ERR_ARG if there are more entries than kernels.
-     * Not owned; read during the call only. */
+     * the parameters above (mat_rows is the rows per workgroup in both
+     * schedules, so a plan-wide value reaches row-resident kernels too).
+     * KF_ERR_ARG if there are more entries than kernels. Not owned; read
+     * during the call only. */
     const kf_impl_params* kernel_params;
     int32_t kernel_params_len;
     /* KF_MODE_EXHAUSTIVE and KF_MODE_LEARNED with top_k > 1: once this many
