@@ -46,6 +46,8 @@ def parse():
                     help="with --batched: time only the persistent launch (for counter runs)")
     ap.add_argument("--tune-batch", action="store_true",
                     help="grid-search the rows per work item of every size bucket of the batched launch")
+    ap.add_argument("--layout", action="store_true",
+                    help="row- vs column-major A: fused BiCGK, ATAX, SGEMVT, GEMVER at n = 16384")
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision suite: BiCGK and GEMVER at n = 32768 with A in FP32, BF16, FP8-E4M3")
     return ap.parse_args()
@@ -141,6 +143,40 @@ def precision_suite(args, torch, kf, S, WL, dev):
                       "n": n, "results": res, "unit": "GB/s", "peak": HBM_PEAK_GBPS}), flush=True)
 
 
+def layout_suite(args, torch, kf, S, WL, dev):
+    """Fused plans of BiCGK, ATAX, SGEMVT and GEMVER at n = 16384 with A
+    row-major and column-major (one JSON line; not the headline). The layout
+    moves the dependence that blocks fusion, so the kernel counts differ."""
+    n = WL.SUITE_N
+    scal = {"alpha": 1.5, "beta": 0.75}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5150)
+    res = {}
+    for name in WL.LAYOUT_SEQ:
+        row = {}
+        for key, layout, params in (("row", kf.KF_ROW_MAJOR, WL.TUNED.get((name, "fused"), {})),
+                                    ("col", kf.KF_COL_MAJOR, WL.LAYOUT_TUNED[name])):
+            q = S.by_name(name, n, n, scal, layout=layout)
+            devin = {k: torch.empty(q.shapes[k], dtype=torch.float32, device=dev).uniform_(-1, 1, generator=gen)
+                     for k in q.inputs}
+            prog = q.compile(mode="fused", **params).bind(device=dev, **devin)
+            r, w = prog.bytes()
+            us = prog.time(3, 20)
+            row[key] = {"us": round(us, 2), "kernels": prog.num_kernels, "bytes": r + w,
+                        "gbps": round((r + w) / us / 1e3, 1),
+                        "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+            del prog, devin
+            torch.cuda.empty_cache()
+        row["col_speedup"] = round(row["row"]["us"] / row["col"]["us"], 3)
+        res[name] = row
+        log("layout %s: row %.1f us (%d kernels), col %.1f us (%d kernels)" %
+            (name, row["row"]["us"], row["row"]["kernels"], row["col"]["us"], row["col"]["kernels"]))
+    print(json.dumps({"metric": "fused plans, row- vs column-major A: time, kernels, GB/s (not the headline)",
+                      "n": n, "results": res, "unit": "GB/s", "peak": HBM_PEAK_GBPS,
+                      "config": {"workload": "BiCGK/ATAX/SGEMVT/GEMVER, A 16384 x 16384 FP32 uniform[-1, 1)"}}),
+          flush=True)
+
+
 def batched_suite(args, torch, kf, WL, dev):
     """GB/s of the batched configuration: the persistent launch, the loop of
     per-instance launches, and graph replays of both (one JSON line; not the
@@ -221,6 +257,9 @@ def main():
     n, vec = WL.SUITE_N, WL.SUITE_VEC
     if args.precision:
         precision_suite(args, torch, kf, S, WL, dev)
+        return
+    if args.layout:
+        layout_suite(args, torch, kf, S, WL, dev)
         return
     if args.batched:
         batched_suite(args, torch, kf, WL, dev)

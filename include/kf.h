@@ -85,6 +85,21 @@ enum { KF_F32 = 0, KF_BF16 = 1, KF_FP8_E4M3 = 2 };
  * with kf_set_const); kf_scalar is an FP32 scalar in device memory. */
 kf_status kf_vector(kf_script* s, int64_t n, kf_value* out);
 kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_value* out);
+/* A matrix in either layout (Section 3.3: a matrix is a list of rows or a list
+ * of columns, and transposed operations are expressed the same way).
+ * layout KF_ROW_MAJOR is kf_matrix. KF_COL_MAJOR: element (i, j) at
+ * ptr[j * ld + i], ld >= rows and a multiple of 4 (0 = rows rounded up to a
+ * multiple of 4); the bound buffer holds cols * ld floats. The column-major
+ * rows x cols matrix is the same memory as the row-major cols x rows matrix
+ * A^T, so calls are recorded on that storage: gemv on A becomes gemtv on A^T
+ * and the reverse, and ger(A, u, v) becomes ger(A^T, v, u) (kf_script_call
+ * reports these storage-form calls). A ger result keeps the layout of its
+ * input: a column-major B with ld = rows rounded up to a multiple of 4.
+ * kf_value_info reports the declared rows and cols. FP32 only; KF_ERR_ARG for
+ * an unknown layout, KF_ERR_SHAPE / KF_ERR_ALIGN as kf_matrix. */
+enum { KF_ROW_MAJOR = 0, KF_COL_MAJOR = 1 };
+kf_status kf_matrix_layout(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t layout,
+                           kf_value* out);
 /* A quantised matrix (dtype KF_BF16 or KF_FP8_E4M3; KF_F32 is kf_matrix with
  * scale KF_NONE) with its row-scale vector `scale` (an input vector of rows
  * entries). ld 0 = cols rounded up to a 16-byte row. */
@@ -121,6 +136,9 @@ kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value 
  * d2 = ld in elements), 2 const scalar, 3 device scalar. */
 kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* d0,
                         int64_t* d1, int64_t* d2);
+/* Layout of matrix value v (KF_ROW_MAJOR or KF_COL_MAJOR); KF_ERR_DTYPE if v
+ * is not a matrix. */
+kf_status kf_value_layout(const kf_script* s, kf_value v, int32_t* layout);
 kf_status kf_script_num_calls(const kf_script* s, int32_t* n);
 /* Call i of the script: op (0 scal, 1 axpy, 2 dot, 3 gemv, 4 gemtv, 5 ger),
  * scalar operands alpha and beta, operands in[0..2] as documented for the

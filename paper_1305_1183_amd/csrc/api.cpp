@@ -180,6 +180,23 @@ kf_status kf_matrix(kf_script* s, int64_t rows, int64_t cols, int64_t ld, kf_val
     return add_value(s, v, out);
 }
 
+kf_status kf_matrix_layout(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t layout, kf_value* out) {
+    if (layout == KF_ROW_MAJOR) return kf_matrix(s, rows, cols, ld, out);
+    if (layout != KF_COL_MAJOR) return set_error(KF_ERR_ARG, "layout must be KF_ROW_MAJOR or KF_COL_MAJOR");
+    if (rows < 1 || cols < 1) return set_error(KF_ERR_SHAPE, "matrix dimensions must be >= 1");
+    if (ld == 0) ld = (rows + 3) / 4 * 4;
+    if (ld < rows) return set_error(KF_ERR_SHAPE, "ld < rows (column-major)");
+    if (ld % 4) return set_error(KF_ERR_ALIGN, "ld must be a multiple of 4 floats");
+    // column j of the declared matrix is row j of its row-major transpose
+    Value v;
+    v.kind = VK::Mat;
+    v.rows = cols;
+    v.cols = rows;
+    v.ld = ld;
+    v.colmajor = true;
+    return add_value(s, v, out);
+}
+
 kf_status kf_matrix_q(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t dtype, kf_value scale,
                       kf_value* out) {
     if (dtype == KF_F32) {
@@ -324,6 +341,8 @@ static kf_status rec_gemv(kf_script* s, bool trans, kf_value alpha, kf_value A, 
     CHECK(need(s, A, VK::Mat, "A"));
     CHECK(need(s, x, VK::Vec, "x"));
     const Value& Av = s->s.values[A];
+    // A x with A column-major is (storage)^T x, and A^T x is (storage) x
+    if (Av.colmajor) trans = !trans;
     int64_t nin = trans ? Av.rows : Av.cols, nout = trans ? Av.cols : Av.rows;
     if (s->s.values[x].n != nin) return set_error(KF_ERR_SHAPE, "gemv: x length does not match A");
     if (y0 != KF_NONE) {
@@ -362,6 +381,8 @@ kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value 
     CHECK(need(s, u, VK::Vec, "u"));
     CHECK(need(s, v, VK::Vec, "v"));
     const Value& Av = s->s.values[A];
+    // on column-major storage S = A^T the update is S + alpha v u^T: u and v swap
+    if (Av.colmajor) std::swap(u, v);
     if (s->s.values[u].n != Av.rows || s->s.values[v].n != Av.cols)
         return set_error(KF_ERR_SHAPE, "ger: u/v lengths do not match A");
     Call c;
@@ -375,6 +396,7 @@ kf_status kf_ger(kf_script* s, kf_value alpha, kf_value A, kf_value u, kf_value 
     o.rows = Av.rows;
     o.cols = Av.cols;
     o.ld = (Av.cols + 3) / 4 * 4;
+    o.colmajor = Av.colmajor;   // B keeps A's layout
     return record(s, c, o, B);
 }
 
@@ -383,9 +405,17 @@ kf_status kf_value_info(const kf_script* s, kf_value v, int32_t* kind, int64_t* 
     if (!valid_value(s, v)) return set_error(KF_ERR_ARG, "bad value handle");
     const Value& x = s->s.values[v];
     if (kind) *kind = (int32_t)x.kind;
-    if (d0) *d0 = x.kind == VK::Mat ? x.rows : x.n;
-    if (d1) *d1 = x.cols;
+    if (d0) *d0 = x.kind == VK::Mat ? (x.colmajor ? x.cols : x.rows) : x.n;
+    if (d1) *d1 = x.colmajor ? x.rows : x.cols;
     if (d2) *d2 = x.ld;
+    return KF_OK;
+}
+
+kf_status kf_value_layout(const kf_script* s, kf_value v, int32_t* layout) {
+    if (!valid_value(s, v) || !layout) return set_error(KF_ERR_ARG, "bad argument");
+    const Value& x = s->s.values[v];
+    if (x.kind != VK::Mat) return set_error(KF_ERR_DTYPE, "not a matrix");
+    *layout = x.colmajor ? KF_COL_MAJOR : KF_ROW_MAJOR;
     return KF_OK;
 }
 

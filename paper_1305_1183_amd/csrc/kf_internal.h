@@ -21,6 +21,9 @@ struct Value {
     int64_t rows = 0, cols = 0, ld = 0;
     int dtype = 0;                 // matrices: KF_F32, KF_BF16, KF_FP8_E4M3
     int scale = -1;                // quantised matrices: value id of the row-scale vector
+    // Matrices declared column-major: rows/cols/ld describe the storage, the
+    // row-major transpose of the declared matrix; calls are recorded on it.
+    bool colmajor = false;
     float cval = 0.f;              // kf_const value
     int producer = -1;             // call index, -1 for declared values
     bool input = false, output = false;

@@ -90,6 +90,8 @@ _SIGS = {
     "kf_vector": ([_vp, _i64, _P(_i32)], _i32),
     "kf_matrix": ([_vp, _i64, _i64, _i64, _P(_i32)], _i32),
     "kf_matrix_q": ([_vp, _i64, _i64, _i64, _i32, _i32, _P(_i32)], _i32),
+    "kf_matrix_layout": ([_vp, _i64, _i64, _i64, _i32, _P(_i32)], _i32),
+    "kf_value_layout": ([_vp, _i32, _P(_i32)], _i32),
     "kf_const": ([_vp, _f32, _P(_i32)], _i32),
     "kf_scalar": ([_vp, _P(_i32)], _i32),
     "kf_input": ([_vp, _i32], _i32),
@@ -231,6 +233,18 @@ def kf_vector(s, n: int) -> int:
 
 def kf_matrix(s, rows: int, cols: int, ld: int = 0) -> int:
     return _new(lib().kf_matrix, s, rows, cols, ld)
+
+
+KF_ROW_MAJOR, KF_COL_MAJOR = 0, 1
+
+
+def kf_matrix_layout(s, rows: int, cols: int, layout: int, ld: int = 0) -> int:
+    """Matrix in either layout; KF_COL_MAJOR stores element (i, j) at j * ld + i."""
+    return _new(lib().kf_matrix_layout, s, rows, cols, ld, layout)
+
+
+def kf_value_layout(s, v: int) -> int:
+    return _new(lib().kf_value_layout, s, v)
 
 
 KF_F32, KF_BF16, KF_FP8_E4M3 = 0, 1, 2

@@ -124,13 +124,14 @@ def _vec(q, name, n):
     return v
 
 
-def _mat(q, name, rows, cols, ld=0):
-    v = kf.kf_matrix(q.script, rows, cols, ld)
+def _mat(q, name, rows, cols, ld=0, layout=kf.KF_ROW_MAJOR):
+    """Input matrix; a column-major one is bound as its (cols, ld) storage."""
+    v = kf.kf_matrix_layout(q.script, rows, cols, layout, ld)
     kf.kf_input(q.script, v)
     ld = kf.kf_value_info(q.script, v)[3]
     q.values[name] = v
     q.inputs.append(name)
-    q.shapes[name] = (rows, ld)
+    q.shapes[name] = (cols, ld) if layout == kf.KF_COL_MAJOR else (rows, ld)
     return v
 
 
@@ -145,6 +146,8 @@ def _out(q, name, v):
     q.values[name] = v
     q.outputs.append(name)
     kind, d0, d1, d2 = kf.kf_value_info(q.script, v)
+    if kind == 1 and kf.kf_value_layout(q.script, v) == kf.KF_COL_MAJOR:
+        d0 = d1   # column-major storage: cols x ld
     q.shapes[name] = {0: (d0,), 1: (d0, d2), 3: (1,)}[kind]
     return v
 
@@ -170,9 +173,9 @@ def waxpby(n: int, alpha: float, beta: float) -> Sequence:
     return q
 
 
-def bicgk(m: int, n: int, ld: int = 0) -> Sequence:
+def bicgk(m: int, n: int, ld: int = 0, layout: int = kf.KF_ROW_MAJOR) -> Sequence:
     q = _seq("bicgk")
-    A = _mat(q, "A", m, n, ld)
+    A = _mat(q, "A", m, n, ld, layout)
     p, r = _vec(q, "p", n), _vec(q, "r", m)
     one = _const(q, "one", 1.0)
     qq = kf.kf_gemv(q.script, one, A, p)
@@ -182,9 +185,9 @@ def bicgk(m: int, n: int, ld: int = 0) -> Sequence:
     return q
 
 
-def atax(m: int, n: int, ld: int = 0) -> Sequence:
+def atax(m: int, n: int, ld: int = 0, layout: int = kf.KF_ROW_MAJOR) -> Sequence:
     q = _seq("atax")
-    A = _mat(q, "A", m, n, ld)
+    A = _mat(q, "A", m, n, ld, layout)
     x = _vec(q, "x", n)
     one = _const(q, "one", 1.0)
     t = kf.kf_gemv(q.script, one, A, x)
@@ -193,10 +196,11 @@ def atax(m: int, n: int, ld: int = 0) -> Sequence:
     return q
 
 
-def gesummv(m: int, n: int, alpha: float, beta: float, lda: int = 0, ldb: int = 0) -> Sequence:
+def gesummv(m: int, n: int, alpha: float, beta: float, lda: int = 0, ldb: int = 0,
+            layout: int = kf.KF_ROW_MAJOR) -> Sequence:
     q = _seq("gesummv")
-    A = _mat(q, "A", m, n, lda)
-    B = _mat(q, "B", m, n, ldb)
+    A = _mat(q, "A", m, n, lda, layout)
+    B = _mat(q, "B", m, n, ldb, layout)
     x = _vec(q, "x", n)
     a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
     t = kf.kf_gemv(q.script, a, A, x)
@@ -205,9 +209,10 @@ def gesummv(m: int, n: int, alpha: float, beta: float, lda: int = 0, ldb: int = 
     return q
 
 
-def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
+def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0,
+           layout: int = kf.KF_ROW_MAJOR) -> Sequence:
     q = _seq("gemver")
-    A = _mat(q, "A", m, n, ld)
+    A = _mat(q, "A", m, n, ld, layout)
     u1, v1 = _vec(q, "u1", m), _vec(q, "v1", n)
     u2, v2 = _vec(q, "u2", m), _vec(q, "v2", n)
     y, z = _vec(q, "y", m), _vec(q, "z", n)
@@ -222,11 +227,12 @@ def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
     return q
 
 
-def sgemvt(m: int, n: int, alpha: float, beta: float, ld: int = 0) -> Sequence:
+def sgemvt(m: int, n: int, alpha: float, beta: float, ld: int = 0,
+           layout: int = kf.KF_ROW_MAJOR) -> Sequence:
     """x = beta A^T y + z; w = alpha A x (the gemv needs all of x: two kernels
     under the strip rules)."""
     q = _seq("sgemvt")
-    A = _mat(q, "A", m, n, ld)
+    A = _mat(q, "A", m, n, ld, layout)
     y, z = _vec(q, "y", m), _vec(q, "z", n)
     a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
     x = kf.kf_gemtv(q.script, b, A, y, one, z)
@@ -251,24 +257,24 @@ BUILDERS = {"axpydot": axpydot, "waxpby": waxpby, "bicgk": bicgk, "atax": atax,
             "gesummv": gesummv, "gemver": gemver, "sgemvt": sgemvt, "vadd": vadd}
 
 
-def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0) -> Sequence:
-    """Sequence `name` on an m x n matrix (BLAS-2) or n-entry vectors (BLAS-1)."""
+def by_name(name: str, m: int, n: int, scal: dict, ld: int = 0, layout: int = kf.KF_ROW_MAJOR) -> Sequence:
+    """Sequence `name` on an m x n matrix (BLAS-2, in `layout`) or n-entry vectors (BLAS-1)."""
     if name == "axpydot":
         return axpydot(n, scal["alpha"])
     if name == "waxpby":
         return waxpby(n, scal["alpha"], scal["beta"])
     if name == "bicgk":
-        return bicgk(m, n, ld)
+        return bicgk(m, n, ld, layout=layout)
     if name == "atax":
-        return atax(m, n, ld)
+        return atax(m, n, ld, layout=layout)
     if name == "gesummv":
-        return gesummv(m, n, scal["alpha"], scal["beta"], ld, ld)
+        return gesummv(m, n, scal["alpha"], scal["beta"], ld, ld, layout=layout)
     if name == "sgemvt":
-        return sgemvt(m, n, scal["alpha"], scal["beta"], ld)
+        return sgemvt(m, n, scal["alpha"], scal["beta"], ld, layout=layout)
     if name == "vadd":
         return vadd(n)
     if name == "gemver":
-        return gemver(m, n, scal["alpha"], scal["beta"], ld)
+        return gemver(m, n, scal["alpha"], scal["beta"], ld, layout=layout)
     raise KeyError(name)
 
 

@@ -114,6 +114,22 @@ TUNED = {
 }
 
 
+# Fused plans of column-major A at the suite shape. The calls run on the
+# row-major storage of A^T with gemv and gemtv swapped, so each sequence takes
+# the point of the row-major plan of the same kernel structure: BiCGK keeps
+# its strip point, column-major ATAX is row-major SGEMVT's two kernels,
+# column-major SGEMVT is row-major ATAX's one row-resident kernel. Column-major
+# GEMVER is one row-resident kernel {ger, ger, gemv, gemtv} (grid search over
+# waves 4/8/16, rows per reduction 1/2/4, rows per block 0/32/128).
+LAYOUT_TUNED = {
+    "bicgk": _S1,
+    "atax": TUNED[("sgemvt", "fused")],
+    "sgemvt": TUNED[("atax", "fused")],
+    "gemver": dict(mat_sched=1, mat_waves=16, mat_group=1, mat_rows=32),
+}
+LAYOUT_SEQ = ["bicgk", "atax", "sgemvt", "gemver"]
+
+
 def tuned_params(name: str, m: int, n: int, mode: str = "fused") -> dict:
     """Tuned parameters for the suite shapes; library defaults elsewhere."""
     suite = (m, n) == ((SUITE_VEC, SUITE_VEC) if name in BLAS1 else (SUITE_N, SUITE_N))

@@ -46,11 +46,14 @@ static kf_value cst(kf_script* s, float x) {
     return v;
 }
 
-// GEMVER (ger, ger, gemtv, gemv) on an m x n matrix
-static kf_script* gemver(int64_t m, int64_t n) {
+// GEMVER (ger, ger, gemtv, gemv) on an m x n matrix in either layout
+static kf_script* gemver(int64_t m, int64_t n, int32_t layout = KF_ROW_MAJOR) {
     kf_script* s = nullptr;
     EXPECT(kf_script_create(&s) == KF_OK);
-    kf_value A = mat(s, m, n), u1 = vec(s, m), v1 = vec(s, n), u2 = vec(s, m), v2 = vec(s, n);
+    kf_value A = -1;
+    EXPECT(kf_matrix_layout(s, m, n, 0, layout, &A) == KF_OK);
+    EXPECT(kf_input(s, A) == KF_OK);
+    kf_value u1 = vec(s, m), v1 = vec(s, n), u2 = vec(s, m), v2 = vec(s, n);
     kf_value y = vec(s, m), z = vec(s, n);
     kf_value one = cst(s, 1.f), a = cst(s, 1.5f), b = cst(s, 0.75f);
     kf_value B1, B, x, w;
@@ -278,6 +281,11 @@ int main() {
             kf_plan_destroy(p);
         }
         kf_planset_destroy(ps);
+        kf_script_destroy(s);
+    }
+    for (auto& sh : shapes) {
+        kf_script* s = gemver(sh[0], sh[1], KF_COL_MAJOR);
+        all_candidates(s, 0);
         kf_script_destroy(s);
     }
     for (int32_t dt : {KF_BF16, KF_FP8_E4M3})
