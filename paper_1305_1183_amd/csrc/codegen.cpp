@@ -124,6 +124,33 @@ void kernel_bytes(const Script& s, const std::vector<int>& calls, const std::vec
     *wr = w;
 }
 
+// Finishing launch of column partials (both BLAS-2 schedules): for columns
+// cc .. cc + 3, wave `wave` of FW adds row blocks wave, wave + FW, ... of each
+// gemtv call's partials, compensated; the FW wave pairs are merged in wave
+// order through LDS (one buffer, reused call by call) and wave 0 ends with
+// sum<c> (zero in the other waves). Expects lane, wave, cc, N, NB, NP, FW
+// and ws in scope; every barrier is outside divergent code.
+static void emit_colpart_finish(Emitter& f, const std::vector<int>& gemtv_calls,
+                                const std::map<int, size_t>& ws_off) {
+    f.l("__shared__ kf_f4 kf_fr[2][FW][64];");
+    bool first = true;
+    for (int c : gemtv_calls) {
+        const size_t off = ws_off.at(c);
+        f.l(F("kf_cs4 pc%d = kf_cs4_init(kf_zero4());", c));
+        f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) pc%d = kf_cs4_add(pc%d, kf_ld4(ws + %zuL + b * NP + cc));", c, c, off));
+        if (!first) f.l("__syncthreads();");
+        first = false;
+        f.l(F("kf_fr[0][wave][lane] = pc%d.s; kf_fr[1][wave][lane] = pc%d.c;", c, c));
+        f.l("__syncthreads();");
+        f.l(F("kf_f4 sum%d = kf_zero4();", c));
+        f.l("if (wave == 0) {");
+        f.l("  kf_cs4 t = {kf_fr[0][0][lane], kf_fr[1][0][lane]};");
+        f.l("  for (int w = 1; w < FW; ++w) { const kf_cs4 o = {kf_fr[0][w][lane], kf_fr[1][w][lane]}; t = kf_cs4_merge(t, o); }");
+        f.l(F("  sum%d = kf_cs4_value(t);", c));
+        f.l("}");
+    }
+}
+
 // ============================================================================
 // BLAS-2 kernels
 // ============================================================================
@@ -421,8 +448,9 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         e.l("const long cc = c0 + 4L * q;");
         for (int i = 0; i < ngt; ++i) {
             int c = gemtv_calls[i];
-            e.l(F("kf_f4 sum%d = kf_red[%d][q];", c, i));
-            e.l(F("for (int w = 1; w < W; ++w) sum%d += kf_red[%d][w * (C / 4) + q];", c, i));
+            e.l(F("kf_cs4 cs%d = kf_cs4_init(kf_red[%d][q]);", c, i));
+            e.l(F("for (int w = 1; w < W; ++w) cs%d = kf_cs4_add(cs%d, kf_red[%d][w * (C / 4) + q]);", c, c, i));
+            e.l(F("const kf_f4 sum%d = kf_cs4_value(cs%d);", c, c));
         }
         if (!col_part) {
             e.l("if (cc < N) {");
@@ -491,8 +519,9 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.l("if (row < M) {");
             f.ind++;
             for (int c : gemv_calls) {
-                f.l(F("float sum%d = 0.f;", c));
-                f.l(F("for (long si = 0; si < S; ++si) sum%d += ws[%zuL + si * M + row];", c, ws_off[c]));
+                f.l(F("kf_cs cs%d = kf_cs_init(ws[%zuL + row]);", c, ws_off[c]));
+                f.l(F("for (long si = 1; si < S; ++si) cs%d = kf_cs_add(cs%d, ws[%zuL + si * M + row]);", c, c, ws_off[c]));
+                f.l(F("const float sum%d = kf_cs_value(cs%d);", c, c));
             }
             for (int c : gemv_calls) {
                 const Call& k = s.calls[c];
@@ -512,27 +541,17 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.l("}");
         }
         if (col_part) {
-            // 64 float4 columns per workgroup; the 4 waves split the row blocks
-            // (wave w adds blocks w, w + 4, ...) and are merged in wave order.
+            // 64 float4 columns per workgroup; the FW waves split the row blocks
+            // (wave w adds blocks w, w + FW, ...) and are merged in wave order,
+            // all of it compensated.
             f.l("if (blockIdx.x >= RBK) {");
             f.ind++;
+            // the S strip partials of a row, compensated, in strip order
             f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
             f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 64 + lane);");
-            f.l(F("__shared__ kf_f4 kf_fr[%d][FW][64];", (int)gemtv_calls.size()));
-            for (size_t i = 0; i < gemtv_calls.size(); ++i) {
-                int c = gemtv_calls[i];
-                f.l(F("kf_f4 part%d = kf_zero4();", c));
-                f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
-                f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
-            }
-            f.l("__syncthreads();");
+            emit_colpart_finish(f, gemtv_calls, ws_off);
             f.l("if (wave == 0 && cc < N) {");
             f.ind++;
-            for (size_t i = 0; i < gemtv_calls.size(); ++i) {
-                int c = gemtv_calls[i];
-                f.l(F("kf_f4 sum%d = kf_fr[%zu][0][lane];", c, i));
-                f.l(F("for (int w = 1; w < FW; ++w) sum%d += kf_fr[%zu][w][lane];", c, i));
-            }
             for (int c : gemtv_calls) {
                 const Call& k = s.calls[c];
                 std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
@@ -639,7 +658,7 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
     e.l(F("constexpr int U = %d, NT = %d, GRID = %d, NW = %d;", U, NT, GRID, NW));
     e.l("constexpr long STEP = (long)NT * U;");
     e.l("const int tid = threadIdx.x;");
-    e.l("__shared__ float kf_lds[NW];");
+    e.l("__shared__ float kf_lds[2 * NW];");
     e.l("(void)kf_lds; (void)ws;");
     for (int v : scalars) {
         if (s.values[v].kind == VK::Const) e.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
@@ -718,7 +737,7 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
     for (int i = 0; i < ndot; ++i) {
         int c = dots[i];
         const Call& k = s.calls[c];
-        e.l(F("const float bs%d = kf_block_sum<NW>(dacc%d, kf_lds);", c, c));
+        e.l(F("const float bs%d = kf_block_sum_cs<NW>(kf_cs_init(dacc%d), kf_lds);", c, c));
         if (!dot_part) {
             if (must_store(s, part, kid, k.out)) e.l(F("if (tid == 0) *Y%d = bs%d;", k.out, c));
         } else {
@@ -732,28 +751,31 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
         for (int v : dot_out) { finl.args.push_back({ArgKind::DevScalarOut, v}); fsig.push_back(F("float* __restrict__ Y%d", v)); }
         finl.args.push_back({ArgKind::Workspace, -1});
         fsig.push_back("const float* __restrict__ ws");
-        // FT threads; thread t adds partials t, t + FT, ... in increasing order
-        // (Kahan), loading FU of them ahead of the dependent adds
+        // FT threads; thread t adds partials t, t + FT, ... in increasing order,
+        // loading FU of them ahead of the dependent adds; the (sum, error)
+        // pairs of the threads are then merged through the wave butterfly and
+        // the waves in wave order, so the whole cross-workgroup sum is
+        // compensated
         const int FT = GRID >= 4096 ? 1024 : 256, FU = 8;
         f.l(F("constexpr int GRID = %d, FT = %d, FU = %d;", GRID, FT, FU));
-        f.l("__shared__ float kf_lds[FT / 64];");
+        f.l("__shared__ float kf_lds[2 * (FT / 64)];");
         f.l("const int tid = threadIdx.x;");
         for (int i = 0; i < ndot; ++i) {
             int c = dots[i];
             const Call& k = s.calls[c];
             f.l("{");
             f.ind++;
-            f.l("float s = 0.f, comp = 0.f;");
+            f.l("kf_cs acc = kf_cs_init(0.f);");
             f.l("for (int g0 = tid; g0 < GRID; g0 += FT * FU) {");
             f.ind++;
             f.l("float yv[FU];");
             f.l("#pragma unroll");
             f.l(F("for (int u = 0; u < FU; ++u) yv[u] = g0 + u * FT < GRID ? ws[%dL * GRID + g0 + u * FT] : 0.f;", i));
             f.l("#pragma unroll");
-            f.l("for (int u = 0; u < FU; ++u) { const float y = yv[u] - comp; const float t = s + y; comp = (t - s) - y; s = t; }");
+            f.l("for (int u = 0; u < FU; ++u) acc = kf_cs_add(acc, yv[u]);");
             f.ind--;
             f.l("}");
-            f.l("const float tot = kf_block_sum<FT / 64>(s, kf_lds);");
+            f.l("const float tot = kf_block_sum_cs<FT / 64>(acc, kf_lds);");
             if (must_store(s, part, kid, k.out)) f.l(F("if (tid == 0) *Y%d = tot;", k.out));
             else f.l("(void)tot;");
             f.ind--;
@@ -783,7 +805,7 @@ static KernelCode gen_vec(const Script& s, const std::vector<int>& calls,
         kc.launches.push_back(finl);
     }
     kc.source = src.str();
-    kc.lds_bytes = 16 + (size_t)NW * 4;
+    kc.lds_bytes = 16 + (size_t)NW * 8;
     kc.params_json = F("{\"unroll\": %d, \"threads\": %d, \"grid\": %d}", U, NT, GRID);
     kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
     return kc;
@@ -970,8 +992,9 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         e.l("const long row = g0 + gi; const int rl = (int)(row - r0); (void)rl;");
         for (int i = 0; i < ngv; ++i) {
             int c = gemv_calls[i];
-            e.l(F("float sum%d = 0.f;", c));
-            e.l(F("for (int w = 0; w < W; ++w) sum%d += kf_part[slot][%d][gi][w];", c, i));
+            e.l(F("kf_cs cs%d = kf_cs_init(kf_part[slot][%d][gi][0]);", c, i));
+            e.l(F("for (int w = 1; w < W; ++w) cs%d = kf_cs_add(cs%d, kf_part[slot][%d][gi][w]);", c, c, i));
+            e.l(F("const float sum%d = kf_cs_value(cs%d);", c, c));
         }
         for (int c : calls) {
             const Call& k = s.calls[c];
@@ -1068,21 +1091,12 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         f.l(F("constexpr int FW = %d;", FW));
         f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
         f.l("const long cc = 4L * ((long)blockIdx.x * 64 + lane);");
-        f.l(F("__shared__ kf_f4 kf_fr[%d][FW][64];", (int)gemtv_calls.size()));
-        for (size_t i = 0; i < gemtv_calls.size(); ++i) {
-            int c = gemtv_calls[i];
-            f.l(F("kf_f4 part%d = kf_zero4();", c));
-            f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) part%d += kf_ld4(ws + %zuL + b * NP + cc);", c, ws_off[c]));
-            f.l(F("kf_fr[%zu][wave][lane] = part%d;", i, c));
-        }
-        f.l("__syncthreads();");
+        emit_colpart_finish(f, gemtv_calls, ws_off);
         f.l("if (wave == 0 && cc < N) {");
         f.ind++;
         for (size_t i = 0; i < gemtv_calls.size(); ++i) {
             int c = gemtv_calls[i];
             const Call& k = s.calls[c];
-            f.l(F("kf_f4 sum%d = kf_fr[%zu][0][lane];", c, i));
-            f.l(F("for (int w = 1; w < FW; ++w) sum%d += kf_fr[%zu][w][lane];", c, i));
             std::string val = F("kf_mul4s(%s, sum%d)", scal_name(k.alpha).c_str(), c);
             if (k.in[2] >= 0) {
                 std::string y0 = produced_in(s, part, kid, k.in[2]) ? F("f%d", s.values[k.in[2]].producer)

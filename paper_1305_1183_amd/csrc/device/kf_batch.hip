@@ -67,8 +67,17 @@ __device__ __forceinline__ kf_f4 kfb_xor4(kf_f4 v, int m) {
     return r;
 }
 
+// Sum of the column partials of a split instance's row blocks 0 .. nblk - 1
+// (p points at block 0's chunk, blocks ld floats apart), compensated, in
+// block order.
+__device__ __forceinline__ kf_f4 kfb_block_partials(const float* p, long ld, int nblk) {
+    kf_cs4 t = kf_cs4_init(kf_zero4());
+    for (int b = 0; b < nblk; ++b) t = kf_cs4_add(t, kf_ld4(p + (long)b * ld));
+    return kf_cs4_value(t);
+}
+
 // Column sums of acc[k] over the 256 / TPR row-lanes of the workgroup, in a
-// fixed order (butterfly inside the wave, then waves 0..3). emit(c, v) runs in
+// fixed order (butterfly inside the wave, then waves 0..3, compensated). emit(c, v) runs in
 // threads tid < TPR with chunk c = tid + k TPR (columns 4c .. 4c + 3).
 template <int LTPR, int K, typename Emit>
 __device__ __forceinline__ void kfb_colsum(kf_f4* acc, kf_f4* red, Emit emit) {
@@ -87,11 +96,11 @@ __device__ __forceinline__ void kfb_colsum(kf_f4* acc, kf_f4* red, Emit emit) {
         __syncthreads();
         if (threadIdx.x < TPR) {
             const int t = threadIdx.x;
-            kf_f4 s = red[t];
-            s += red[TPR + t];
-            s += red[2 * TPR + t];
-            s += red[3 * TPR + t];
-            emit(t + k * TPR, s);
+            kf_cs4 s = kf_cs4_init(red[t]);
+            s = kf_cs4_add(s, red[TPR + t]);
+            s = kf_cs4_add(s, red[2 * TPR + t]);
+            s = kf_cs4_add(s, red[3 * TPR + t]);
+            emit(t + k * TPR, kf_cs4_value(s));
         }
     }
 }
@@ -348,9 +357,7 @@ __device__ void kfb_bicgk(const kfb_inst& I, int blk, float* __restrict__ arena,
     unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
     if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
         for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
-            kf_f4 t = kf_zero4();
-            for (int b = 0; b < I.nblk; ++b) t += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
-            kfb_stv(s, 4 * c, n, t);
+            kfb_stv(s, 4 * c, n, kfb_block_partials(ws + I.ws + 4 * c, ld, I.nblk));
         }
     }
 }
@@ -432,8 +439,7 @@ __device__ void kfb_gemver_k1(const kfb_inst& I, int blk, float* __restrict__ ar
     unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
     if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
         for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
-            kf_f4 t = kf_zero4();
-            for (int b = 0; b < I.nblk; ++b) t += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
+            const kf_f4 t = kfb_block_partials(ws + I.ws + 4 * c, ld, I.nblk);
             kfb_stv(x, 4 * c, n, kf_fma4s(I.beta, t, kfb_ldv(z, 4 * c, n)));
         }
         __syncthreads();
@@ -499,7 +505,11 @@ __device__ __forceinline__ void kfb_w_rows_sum(const float* qp_in, float* __rest
     __syncthreads();
     if (threadIdx.x < G && i0 + (int)threadIdx.x < r1) {
         const int g = threadIdx.x;
-        out[i0 + g] = scale * (((sh.rowp[buf][0][g] + sh.rowp[buf][1][g]) + sh.rowp[buf][2][g]) + sh.rowp[buf][3][g]);
+        kf_cs t = kf_cs_init(sh.rowp[buf][0][g]);
+        t = kf_cs_add(t, sh.rowp[buf][1][g]);
+        t = kf_cs_add(t, sh.rowp[buf][2][g]);
+        t = kf_cs_add(t, sh.rowp[buf][3][g]);
+        out[i0 + g] = scale * kf_cs_value(t);
     }
     buf ^= 1;
 }
@@ -560,9 +570,7 @@ __device__ void kfb_w_bicgk(const kfb_inst& I, int blk, float* __restrict__ aren
     unsigned* ctr = sync + KFB_SYNC_HEADER + KFB_SYNC_PER_INST * I.sync;
     if (kfb_arrive(ctr, (unsigned)I.nblk, &sh.flag)) {
         for (int c = threadIdx.x; 4 * c < n; c += KFB_THREADS) {
-            kf_f4 sum = kf_zero4();
-            for (int b = 0; b < I.nblk; ++b) sum += kf_ld4(ws + I.ws + (long)b * ld + 4 * c);
-            kfb_stv(s, 4 * c, n, sum);
+            kfb_stv(s, 4 * c, n, kfb_block_partials(ws + I.ws + 4 * c, ld, I.nblk));
         }
     }
 }

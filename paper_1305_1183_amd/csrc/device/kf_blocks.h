@@ -203,3 +203,96 @@ __device__ __forceinline__ float kf_block_sum(float v, float* lds) {
     }
     return s;
 }
+
+// ---- B7: compensated summation of partial sums ---------------------------------
+// A partial sum travels as a pair (s, c): s is the rounded running sum and c
+// collects the rounding errors of the additions that formed it. Each addition
+// is Knuth's TwoSum, which gives the exact error of fl(a + b) for any a and b
+// without a branch (six additions; it relies on strict IEEE evaluation, so no
+// reassociation -- the kernels are built without fast-math). Two pairs merge
+// with TwoSum of their leading parts, and the value of a pair is s + c. The
+// merge is symmetric in its arguments (the error term is exact), so a
+// butterfly leaves every lane with the same pair. Every final reduction that
+// combines partial sums of different waves or workgroups goes through these,
+// in a fixed order, so results stay bit-reproducible; sums whose partials
+// cancel keep the small remainder that plain FP32 addition would round away.
+struct kf_cs { float s, c; };
+struct kf_cs4 { kf_f4 s, c; };
+__device__ __forceinline__ void kf_two_sum(float a, float b, float* s, float* e) {
+    const float t = a + b;
+    const float z = t - a;
+    *e = (a - (t - z)) + (b - z);
+    *s = t;
+}
+__device__ __forceinline__ kf_cs kf_cs_init(float x) { kf_cs r = {x, 0.f}; return r; }
+__device__ __forceinline__ kf_cs kf_cs_add(kf_cs a, float x) {
+    float t, e;
+    kf_two_sum(a.s, x, &t, &e);
+    kf_cs r = {t, a.c + e};
+    return r;
+}
+__device__ __forceinline__ kf_cs kf_cs_merge(kf_cs a, kf_cs b) {
+    float t, e;
+    kf_two_sum(a.s, b.s, &t, &e);
+    kf_cs r = {t, (a.c + b.c) + e};
+    return r;
+}
+__device__ __forceinline__ float kf_cs_value(kf_cs a) { return a.s + a.c; }
+
+__device__ __forceinline__ kf_cs4 kf_cs4_init(kf_f4 x) { kf_cs4 r = {x, kf_zero4()}; return r; }
+__device__ __forceinline__ kf_cs4 kf_cs4_pack(kf_cs x, kf_cs y, kf_cs z, kf_cs w) {
+    kf_cs4 r;
+    r.s.x = x.s; r.s.y = y.s; r.s.z = z.s; r.s.w = w.s;
+    r.c.x = x.c; r.c.y = y.c; r.c.z = z.c; r.c.w = w.c;
+    return r;
+}
+__device__ __forceinline__ kf_cs4 kf_cs4_add(kf_cs4 a, kf_f4 v) {
+    return kf_cs4_pack(kf_cs_add(kf_cs{a.s.x, a.c.x}, v.x), kf_cs_add(kf_cs{a.s.y, a.c.y}, v.y),
+                       kf_cs_add(kf_cs{a.s.z, a.c.z}, v.z), kf_cs_add(kf_cs{a.s.w, a.c.w}, v.w));
+}
+__device__ __forceinline__ kf_cs4 kf_cs4_merge(kf_cs4 a, kf_cs4 b) {
+    return kf_cs4_pack(kf_cs_merge(kf_cs{a.s.x, a.c.x}, kf_cs{b.s.x, b.c.x}),
+                       kf_cs_merge(kf_cs{a.s.y, a.c.y}, kf_cs{b.s.y, b.c.y}),
+                       kf_cs_merge(kf_cs{a.s.z, a.c.z}, kf_cs{b.s.z, b.c.z}),
+                       kf_cs_merge(kf_cs{a.s.w, a.c.w}, kf_cs{b.s.w, b.c.w}));
+}
+__device__ __forceinline__ kf_f4 kf_cs4_value(kf_cs4 a) {
+    kf_f4 r;
+    r.x = a.s.x + a.c.x; r.y = a.s.y + a.c.y; r.z = a.s.z + a.c.z; r.w = a.s.w + a.c.w;
+    return r;
+}
+
+// Butterfly over the 64 lanes on pairs: every lane ends with the same pair.
+__device__ __forceinline__ kf_cs kf_wave_sum_cs(kf_cs v) {
+#pragma unroll
+    for (int mask = 32; mask >= 1; mask >>= 1) {
+        kf_cs o;
+        o.s = kf_xor(v.s, mask);
+        o.c = kf_xor(v.c, mask);
+        v = kf_cs_merge(v, o);
+    }
+    return v;
+}
+// Workgroup sum of one float per thread, compensated from the wave level on:
+// the wave pairs are merged in wave order by thread 0, which gets the value
+// (other threads get an unspecified value). lds holds 2 NW floats.
+template <int NW>
+__device__ __forceinline__ float kf_block_sum_cs(kf_cs v, float* lds) {
+    v = kf_wave_sum_cs(v);
+    const int lane = __lane_id();
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { lds[2 * wave] = v.s; lds[2 * wave + 1] = v.c; }
+    __syncthreads();
+    float r = 0.f;
+    if (threadIdx.x == 0) {
+        kf_cs t = {lds[0], lds[1]};
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            kf_cs o = {lds[2 * w], lds[2 * w + 1]};
+            t = kf_cs_merge(t, o);
+        }
+        r = kf_cs_value(t);
+    }
+    return r;
+}
