@@ -213,12 +213,12 @@ typedef struct kf_compile_opts {
      * BF16 or 16 FP8 elements); 0 = four when the kernel expands the matrix
      * into an FP32 one (ger), else 16. FP32 kernels ignore it. */
     int32_t mat_unit;
-    /* KF_MODE_LEARNED: the trained model (not owned). KF_MODE_LEARNED with
-     * top_k > 1 and KF_MODE_EXHAUSTIVE time candidates on `stream` with the
-     * caller's device buffers: bind_ptrs[i] is bound to script value
-     * bind_values[i] (every input and output, as for kf_bind; the inputs are
-     * read, the outputs overwritten). The library allocates and frees the
-     * timing workspace itself. */
+    /* KF_MODE_LEARNED: the trained model (not owned, with bound memory).
+     * KF_MODE_LEARNED with top_k > 1 and KF_MODE_EXHAUSTIVE time candidates on
+     * `stream` with the caller's device buffers: bind_ptrs[i] is bound to
+     * script value bind_values[i] (every input and output, as for kf_bind; the
+     * inputs are read, the outputs overwritten), and the plans' workspace is
+     * opts.workspace (below). */
     struct kf_costmodel* model;
     void* stream;
     const int32_t* bind_values;
@@ -239,12 +239,22 @@ typedef struct kf_compile_opts {
      * candidate is timed and those timed so far (at least one) are combined;
      * 0 = no limit. */
     int32_t time_budget_ms;
+    /* The timed modes' plan workspace: caller device memory, 256-byte aligned,
+     * workspace_bytes long (kf_compile_workspace_bytes gives the size every
+     * candidate fits in). A candidate that needs more is not timed;
+     * KF_ERR_WORKSPACE if none fits. */
+    void* workspace;
+    size_t workspace_bytes;
 } kf_compile_opts;
 
 /* Fill opts with defaults (mode KF_MODE_FUSED, all parameters 0). */
 void kf_compile_opts_init(kf_compile_opts* o);
 /* Compile a plan. The plan deep-copies what it needs from the script. */
 kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** out);
+/* The largest kf_plan_workspace_bytes among the candidates that the timed
+ * modes of kf_compile would time with these opts (partitions and grid as in
+ * KF_MODE_EXHAUSTIVE); code generation only, no GPU needed. */
+kf_status kf_compile_workspace_bytes(const kf_script* s, const kf_compile_opts* opts, size_t* bytes);
 void kf_plan_destroy(kf_plan* p);
 
 /* ---- plan-space enumeration (Section 4.2) ------------------------------- */
@@ -430,28 +440,54 @@ kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float*
 /* Cost model for plan ranking: the MLP above over KF_FEATURE_DIM kernel
  * features, predicting the log of a kernel's run time in microseconds; a
  * plan's prediction is the sum over its kernels of exp(prediction) plus
- * launch_us per launch. The object owns its device memory (parameters, Adam
- * moments, workspace), allocated on the current device at creation and on
- * first use; all of its work runs on the caller's stream, which is
- * synchronised before a call returns. */
+ * launch_us per launch (feature 25 counts launches). The object holds the
+ * network's shape, the feature and target standardisation and, until device
+ * memory is bound, the parameters on the host; it allocates no device memory.
+ * Training and prediction need kf_costmodel_bind. Every kernel runs on the
+ * caller's stream. */
 typedef struct kf_costmodel kf_costmodel;
 kf_status kf_costmodel_create(int32_t hidden, int32_t layers, uint64_t seed, kf_costmodel** out);
 void kf_costmodel_destroy(kf_costmodel* cm);
-/* Train on n samples: X is n x KF_FEATURE_DIM host floats (row-major),
- * y_log_us the targets. Features and targets are standardised with the
- * training data's mean and deviation (kept in the model); MSE on the
- * standardised log time, Adam (0.9, 0.999, 1e-8) at rate lr, minibatches
- * of `batch` in an order shuffled per epoch from `seed`. loss_per_epoch
- * (optional, `epochs` floats) gets the mean minibatch loss of each epoch. */
+/* Bytes of device memory for a model whose calls take up to `rows` feature
+ * rows at a time (the training minibatch; predictions go in chunks of rows):
+ * parameters, gradients, Adam moments, the MLP workspace, staging of
+ * features, targets and predictions, and the statistics. */
+kf_status kf_costmodel_workspace_bytes(const kf_costmodel* cm, int64_t rows, size_t* bytes);
+/* Give the model caller-owned device memory: `mem` of at least
+ * kf_costmodel_workspace_bytes(rows) bytes, 256-byte aligned, alive while the
+ * model uses it. The parameters and statistics are copied into it (on
+ * `stream`, which is synchronised) and live there from then on; binding new
+ * memory first copies the parameters back from the old one. Errors:
+ * KF_ERR_ALIGN, KF_ERR_WORKSPACE (too small), KF_ERR_HIP. */
+kf_status kf_costmodel_bind(kf_costmodel* cm, void* mem, size_t bytes, int64_t rows, void* stream);
+/* Train on n samples in caller device memory: X is n x KF_FEATURE_DIM floats
+ * (row-major), y_log_us the n targets. Features and targets are standardised
+ * with the training data's per-column mean and deviation (computed on the GPU
+ * and kept in the model); MSE on the standardised log time, Adam (0.9,
+ * 0.999, 1e-8) at rate lr, minibatches of `batch` (<= the bound rows) in an
+ * order shuffled per epoch from `seed`. loss_per_epoch (optional host array
+ * of `epochs` floats) gets the mean minibatch loss of each epoch. The stream
+ * is synchronised once per minibatch. KF_ERR_UNBOUND without bound memory. */
 kf_status kf_costmodel_train(kf_costmodel* cm, const float* X, const float* y_log_us, int64_t n, int32_t epochs,
                              int32_t batch, float lr, uint64_t seed, void* stream, float* loss_per_epoch);
-/* log_us[i] = predicted log microseconds of feature row i (host arrays). */
+/* log_us[i] = predicted log microseconds of feature row i; X (n x
+ * KF_FEATURE_DIM) and log_us are caller device memory. Asynchronous on
+ * `stream`. KF_ERR_UNBOUND without bound memory. */
 kf_status kf_costmodel_predict(kf_costmodel* cm, const float* X, int64_t n, float* log_us, void* stream);
+/* Predicted run times (us) of nplans plans from host feature rows (as
+ * kf_plan_features writes them): plan i owns rows start[i] .. start[i + 1] - 1
+ * of feats (rows x KF_FEATURE_DIM), and us[i] = sum over them of
+ * exp(prediction) + launch_us * launches. The rows are staged through the
+ * bound memory; synchronises `stream`. */
+kf_status kf_costmodel_plan_us(kf_costmodel* cm, const float* feats, int64_t rows, const int64_t* start,
+                               int32_t nplans, double* us, void* stream);
 kf_status kf_costmodel_set_launch_us(kf_costmodel* cm, float us);
 /* Host copies of the parameters (kf_costmodel_dims' nparams floats, the
- * kf_mlp layout), the feature means and deviations (KF_FEATURE_DIM each),
- * the target mean and deviation (two doubles) and the launch term; any
- * pointer may be NULL. kf_costmodel_set installs them. */
+ * kf_mlp layout; read from the bound memory after the device is
+ * synchronised), the feature means and deviations (KF_FEATURE_DIM each), the
+ * target mean and deviation (two doubles) and the launch term; any pointer
+ * may be NULL. kf_costmodel_set installs them (and copies them into bound
+ * memory). */
 kf_status kf_costmodel_get(const kf_costmodel* cm, float* params, float* mu, float* sd, double* y_mu_sd,
                            float* launch_us);
 kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* mu, const float* sd,
@@ -505,12 +541,16 @@ kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
  * persistent workgroups (0: as many as are resident on the device);
  * opts->spin_limit bounds the wait of a dependent item (0: default, about a
  * second); a wait that runs out sets error bit 1 (kf_batch_error) and the
- * item is skipped.
+ * item is skipped: that run's outputs are not valid, and its counters stay
+ * behind until kf_batch_error (or kf_batch_bind) clears them, so call
+ * kf_batch_error after a run before the next one when the results matter.
  *
  * Workspace: kf_batch_workspace_bytes bytes, 256-byte aligned, owned by the
- * caller; kf_batch_bind clears its counters (on `stream`) and the launch
- * leaves them cleared, so runs and graph replays need no clearing. Two runs
- * of one batch must not overlap in time. */
+ * caller like the arena. It holds the counters, the column partials of split
+ * instances and the instance and item tables; kf_batch_bind uploads the
+ * tables and clears the counters, and the launch leaves them cleared, so runs
+ * and graph replays need no clearing. The library allocates no device memory.
+ * Two runs of one batch must not overlap in time. */
 typedef struct kf_batch kf_batch;
 enum { KF_BATCH_BICGK = 0, KF_BATCH_GEMVER = 1 };
 #define KF_BATCH_BUCKETS 6
@@ -540,8 +580,9 @@ kf_status kf_batch_describe(const kf_batch* b, char* buf, size_t len, size_t* ne
  * order of the launch loop; arrays of cap entries, *count gets the total. */
 kf_status kf_batch_items(const kf_batch* b, int32_t which, int32_t* inst, int32_t* phase, int32_t* blk,
                          int64_t cap, int64_t* count);
-/* Device pointers; uploads the item tables (first call) and clears the
- * counters on `stream`. Errors: KF_ERR_ALIGN, KF_ERR_ALIAS, KF_ERR_HIP. */
+/* Device pointers; uploads the instance and item tables into the workspace
+ * and clears the counters on `stream`, which it synchronises. Errors:
+ * KF_ERR_ALIGN, KF_ERR_ALIAS, KF_ERR_HIP. */
 kf_status kf_batch_bind(kf_batch* b, float* arena, void* workspace, void* stream);
 /* which = 0: the persistent launch; 1: the baseline loop, one launch per
  * instance (and one more for the w rows of a split GEMVER instance). */
@@ -555,7 +596,8 @@ kf_status kf_batch_graph_launch(kf_batch* b, int32_t which, void* stream);
 kf_status kf_batch_time(kf_batch* b, int32_t which, int32_t graph, void* stream, int32_t warmup, int32_t reps,
                         float* median_us);
 /* Synchronises `stream` and returns the error bits (1: a dependent item's
- * wait ran out). Bits stay set until the next kf_batch_bind. */
+ * wait ran out) of the runs since the last call. When a bit is set it also
+ * clears the counters, flags and error word, so the next run starts clean. */
 kf_status kf_batch_error(kf_batch* b, void* stream, uint32_t* bits);
 
 /* ---- measurement helper -------------------------------------------------- */

@@ -3,9 +3,11 @@
 A thin wrapper of the library's cost-model object (kf_costmodel_*): the
 network (d -> 128 -> 128 -> 128 -> 1, ReLU) is trained on the GPU by the
 library's own kernels, and the feature/target standardisation lives in the
-object. A plan's predicted time is the sum over its kernels of
-exp(prediction) plus a per-launch term. The model plugs into kf_compile's
-learned mode through `handle`.
+object. The device memory the model works in is a torch tensor bound to it
+(the caller owns all device memory); features and targets are copied to the
+device here and handed over as device pointers. A plan's predicted time is the
+sum over its kernels of exp(prediction) plus a per-launch term. The model
+plugs into kf_compile's learned mode through `handle`.
 """
 from __future__ import annotations
 
@@ -34,6 +36,23 @@ class CostModel:
         kf._chk(kf.lib().kf_costmodel_dims(self.handle, ctypes.byref(h), ctypes.byref(L), ctypes.byref(n)))
         self.in_dim, self.hidden, self.layers, self.nparams = kf.FEATURE_DIM, h.value, L.value, n.value
         self.history = []
+        self.mem = None
+        self.rows = 0
+        if torch.cuda.is_available():
+            self.bind()      # so that `handle` is ready for kf_compile's learned mode
+
+    def bind(self, rows: int = 8192) -> "CostModel":
+        """Device memory for calls of up to `rows` feature rows (a torch
+        tensor this object keeps), bound to the library object."""
+        if self.mem is not None and self.rows >= rows:
+            return self
+        need = ctypes.c_size_t()
+        kf._chk(kf.lib().kf_costmodel_workspace_bytes(self.handle, rows, ctypes.byref(need)))
+        mem = torch.empty(need.value + 256, dtype=torch.uint8, device=self.device)
+        base = (mem.data_ptr() + 255) // 256 * 256
+        kf._chk(kf.lib().kf_costmodel_bind(self.handle, base, need.value, rows, self._stream()))
+        self.mem, self.rows = mem, rows
+        return self
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -46,11 +65,12 @@ class CostModel:
 
     def fit(self, X: np.ndarray, y_log: np.ndarray, epochs: int = 200, batch: int = 256, lr: float = 1e-3,
             seed: int = 0, verbose: bool = False) -> list:
-        X = np.ascontiguousarray(X, np.float32)
-        y = np.ascontiguousarray(y_log, np.float32)
+        self.bind(max(batch, 8192))
+        Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32)).to(self.device)
+        yd = torch.from_numpy(np.ascontiguousarray(y_log, np.float32)).to(self.device)
         hist = np.zeros(epochs, np.float32)
-        kf._chk(kf.lib().kf_costmodel_train(self.handle, X.ctypes.data_as(_f32p), y.ctypes.data_as(_f32p), len(y),
-                                            epochs, batch, lr, seed, self._stream(), hist.ctypes.data_as(_f32p)))
+        kf._chk(kf.lib().kf_costmodel_train(self.handle, Xd.data_ptr(), yd.data_ptr(), len(yd), epochs, batch, lr,
+                                            seed, self._stream(), hist.ctypes.data_as(_f32p)))
         self.history = [float(v) for v in hist]
         if verbose:
             for ep in list(range(0, epochs, 20)) + [epochs - 1]:
@@ -58,11 +78,11 @@ class CostModel:
         return self.history
 
     def predict_log(self, X: np.ndarray) -> np.ndarray:
-        X = np.ascontiguousarray(X, np.float32)
-        out = np.empty(len(X), np.float32)
-        kf._chk(kf.lib().kf_costmodel_predict(self.handle, X.ctypes.data_as(_f32p), len(X),
-                                              out.ctypes.data_as(_f32p), self._stream()))
-        return out.astype(np.float64)
+        self.bind()
+        Xd = torch.from_numpy(np.ascontiguousarray(X, np.float32).reshape(-1, self.in_dim)).to(self.device)
+        out = torch.empty(len(Xd), dtype=torch.float32, device=self.device)
+        kf._chk(kf.lib().kf_costmodel_predict(self.handle, Xd.data_ptr(), len(Xd), out.data_ptr(), self._stream()))
+        return out.cpu().numpy().astype(np.float64)
 
     def set_launch_us(self, us: float) -> None:
         kf._chk(kf.lib().kf_costmodel_set_launch_us(self.handle, float(us)))
@@ -79,17 +99,19 @@ class CostModel:
                                           y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(lu)))
         return p, mu, sd, (float(y[0]), float(y[1])), lu.value
 
-    def predict_plan_us(self, kernel_features: list, launch_us: float = 0.0) -> np.ndarray:
-        """Predicted plan times (us): kernel_features[i] is the (k x d) array of
-        plan i; launch_us per launch is added (column 25 counts launches)."""
+    def predict_plan_us(self, kernel_features: list) -> np.ndarray:
+        """Predicted plan times (us) by the library (kf_costmodel_plan_us):
+        kernel_features[i] is the (k x d) array of plan i; the model's
+        per-launch term is added per launch (column 25 counts launches)."""
+        self.bind()
         sizes = [len(f) for f in kernel_features]
-        allf = np.concatenate(kernel_features, axis=0)
-        t = np.exp(self.predict_log(allf)) + launch_us * allf[:, 25]
-        out, i = [], 0
-        for s in sizes:
-            out.append(float(t[i:i + s].sum()))
-            i += s
-        return np.array(out)
+        allf = np.ascontiguousarray(np.concatenate(kernel_features, axis=0), np.float32)
+        start = np.ascontiguousarray(np.concatenate([[0], np.cumsum(sizes)]), np.int64)
+        out = np.empty(len(sizes), np.float64)
+        kf._chk(kf.lib().kf_costmodel_plan_us(self.handle, allf.ctypes.data_as(_f32p), len(allf),
+                                              start.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(sizes),
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._stream()))
+        return out
 
     def save(self, path: str) -> None:
         """The library's binary format (.kfcm) or, for other names, numpy .npz."""

@@ -652,9 +652,20 @@ kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan
 namespace kf {
 kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
 kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_plan** out);
+kf_status timed_workspace_bytes(const kf_script* s, const kf_compile_opts& o, size_t* bytes);
 }  // namespace kf
 
 extern "C" {
+
+kf_status kf_compile_workspace_bytes(const kf_script* s, const kf_compile_opts* opts, size_t* bytes) {
+    if (!s || !bytes) return set_error(KF_ERR_ARG, "null argument");
+    if (s->s.calls.empty()) return set_error(KF_ERR_STATE, "script has no calls");
+    kf_compile_opts o;
+    kf_compile_opts_init(&o);
+    if (opts) o = *opts;
+    KF_TRY({ return kf::timed_workspace_bytes(s, o, bytes); });
+    return KF_OK;
+}
 
 kf_status kf_compile(const kf_script* s, const kf_compile_opts* opts, kf_plan** out) {
     if (!s || !out) return set_error(KF_ERR_ARG, "null argument");

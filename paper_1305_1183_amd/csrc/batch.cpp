@@ -51,9 +51,6 @@ struct kf_batch {
     // bound state
     float* arena = nullptr;
     void* ws = nullptr;
-    kfb_inst* d_insts = nullptr;
-    kfb_item* d_queue = nullptr;
-    kfb_item* d_by_inst = nullptr;
     int grid = 0;
     Graph graphs[2];
     ~kf_batch() {
@@ -61,14 +58,21 @@ struct kf_batch {
             if (g.x) (void)hipGraphExecDestroy(g.x);
             if (g.g) (void)hipGraphDestroy(g.g);
         }
-        if (d_insts) (void)hipFree(d_insts);
-        if (d_queue) (void)hipFree(d_queue);
-        if (d_by_inst) (void)hipFree(d_by_inst);
     }
-    size_t sync_bytes() const { return (size_t)((sync_words * 4 + 255) / 256 * 256); }
-    size_t ws_bytes() const { return sync_bytes() + (size_t)ws_floats * 4; }
+    // Workspace layout, each part at a 256-byte boundary: the counters, the
+    // column partials of split instances, then the instance table and the two
+    // item tables (queue order and instance order), uploaded by kf_batch_bind.
+    static size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+    size_t sync_bytes() const { return up256((size_t)sync_words * 4); }
+    size_t part_bytes() const { return up256((size_t)ws_floats * 4); }
+    size_t insts_bytes() const { return up256(insts.size() * sizeof(kfb_inst)); }
+    size_t items_bytes() const { return up256(queue.size() * sizeof(kfb_item)); }
+    size_t ws_bytes() const { return sync_bytes() + part_bytes() + insts_bytes() + 2 * items_bytes(); }
     unsigned* sync_ptr() const { return (unsigned*)ws; }
     float* part_ptr() const { return (float*)((char*)ws + sync_bytes()); }
+    kfb_inst* insts_ptr() const { return (kfb_inst*)((char*)ws + sync_bytes() + part_bytes()); }
+    kfb_item* queue_ptr() const { return (kfb_item*)((char*)insts_ptr() + insts_bytes()); }
+    kfb_item* by_inst_ptr() const { return (kfb_item*)((char*)queue_ptr() + items_bytes()); }
 };
 
 extern "C" {
@@ -314,20 +318,21 @@ kf_status kf_batch_bind(kf_batch* b, float* arena, void* workspace, void* stream
         if (g.g) (void)hipGraphDestroy(g.g);
         g = Graph();
     }
-    if (!b->d_insts && !b->insts.empty()) {
-        const size_t ni = b->insts.size() * sizeof(kfb_inst), nq = b->queue.size() * sizeof(kfb_item);
-        if (hipMalloc((void**)&b->d_insts, ni) != hipSuccess || hipMalloc((void**)&b->d_queue, nq) != hipSuccess ||
-            hipMalloc((void**)&b->d_by_inst, nq) != hipSuccess)
-            return set_error(KF_ERR_HIP, "hipMalloc of the batch tables failed");
-        if (hipMemcpy(b->d_insts, b->insts.data(), ni, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(b->d_queue, b->queue.data(), nq, hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(b->d_by_inst, b->by_inst.data(), nq, hipMemcpyHostToDevice) != hipSuccess)
-            return set_error(KF_ERR_HIP, "copy of the batch tables failed");
-    }
     b->arena = arena;
     b->ws = workspace;
-    if (workspace && hipMemsetAsync(workspace, 0, b->sync_bytes(), st) != hipSuccess)
-        return set_error(KF_ERR_HIP, "clearing the batch counters failed");
+    if (workspace) {
+        // clear the counters and upload the tables into the caller's workspace;
+        // the host tables are read by the copies, so the stream is synchronised
+        const size_t ni = b->insts.size() * sizeof(kfb_inst), nq = b->queue.size() * sizeof(kfb_item);
+        if (hipMemsetAsync(workspace, 0, b->sync_bytes(), st) != hipSuccess ||
+            (ni && hipMemcpyAsync(b->insts_ptr(), b->insts.data(), ni, hipMemcpyHostToDevice, st) != hipSuccess) ||
+            (nq && hipMemcpyAsync(b->queue_ptr(), b->queue.data(), nq, hipMemcpyHostToDevice, st) != hipSuccess) ||
+            (nq && hipMemcpyAsync(b->by_inst_ptr(), b->by_inst.data(), nq, hipMemcpyHostToDevice, st) != hipSuccess) ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            b->ws = nullptr;
+            return set_error(KF_ERR_HIP, "clearing the counters or uploading the batch tables failed");
+        }
+    }
     if (b->grid_req > 0) {
         b->grid = b->grid_req;
     } else {
@@ -344,15 +349,15 @@ static kf_status batch_launch(kf_batch* b, int which, hipStream_t st) {
     if (b->insts.empty()) return KF_OK;
     const int nq = (int)b->queue.size();
     if (which == 0) {
-        if (kfb_launch(b->d_insts, b->d_queue, nq, 0, b->grid, 1, b->arena, b->part_ptr(), b->sync_ptr(),
+        if (kfb_launch(b->insts_ptr(), b->queue_ptr(), nq, 0, b->grid, 1, b->arena, b->part_ptr(), b->sync_ptr(),
                        b->spin_limit, st) != hipSuccess)
             return set_error(KF_ERR_HIP, "persistent launch failed");
         return KF_OK;
     }
     for (size_t i = 0; i < b->insts.size(); ++i) {
-        if (kfb_launch(b->d_insts, b->d_by_inst, nq, b->first1[i], b->count1[i], 0, b->arena, b->part_ptr(),
+        if (kfb_launch(b->insts_ptr(), b->by_inst_ptr(), nq, b->first1[i], b->count1[i], 0, b->arena, b->part_ptr(),
                        b->sync_ptr(), b->spin_limit, st) != hipSuccess ||
-            kfb_launch(b->d_insts, b->d_by_inst, nq, b->first2[i], b->count2[i], 0, b->arena, b->part_ptr(),
+            kfb_launch(b->insts_ptr(), b->by_inst_ptr(), nq, b->first2[i], b->count2[i], 0, b->arena, b->part_ptr(),
                        b->sync_ptr(), b->spin_limit, st) != hipSuccess)
             return set_error(KF_ERR_HIP, "instance launch failed");
     }
@@ -441,6 +446,11 @@ kf_status kf_batch_error(kf_batch* b, void* stream, uint32_t* bits) {
     if (hipStreamSynchronize(st) != hipSuccess ||
         hipMemcpy(&v, b->sync_ptr() + KFB_SYNC_ERROR, 4, hipMemcpyDeviceToHost) != hipSuccess)
         return set_error(KF_ERR_HIP, "reading the batch error word failed");
+    // A dependent item that gave up its wait left its instance's counters
+    // and x flag behind; with every run on the stream finished, clear all of
+    // them (and the error word) so that the next run starts clean.
+    if (v && (hipMemsetAsync(b->ws, 0, b->sync_bytes(), st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess))
+        return set_error(KF_ERR_HIP, "clearing the batch counters failed");
     *bits = v;
     return KF_OK;
 }

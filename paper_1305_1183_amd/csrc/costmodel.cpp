@@ -187,44 +187,89 @@ kf_status kf_mlp_adam(const kf_mlp* m, float* params, const float* grads, float*
 
 }  // extern "C"
 
-// ---- the cost model object: network, its device state and the normalisation
+// ---- the cost model object: network, normalisation, and the caller's memory
+namespace kf {
+hipError_t mlp_col_stats(long n, int d, const float* X, float floor, float* mu, float* sd, hipStream_t st);
+hipError_t mlp_gather_std(int rows, int d, const float* X, const int* idx, long row0, const float* mu,
+                          const float* sd, float* out, hipStream_t st);
+hipError_t mlp_unstd(int n, const float* p, const float* mu, const float* sd, float* out, hipStream_t st);
+}  // namespace kf
+
+// Parts of the bound device memory, each at a 256-byte boundary (offsets in
+// bytes): parameters, gradients, Adam moments, the MLP workspace for `rows`
+// rows, standardised features and targets, raw features staged from the
+// host, predictions, minibatch row indices, and the statistics (feature means
+// and deviations, target mean and deviation, the last loss).
+struct CmLayout {
+    size_t params, grads, mom1, mom2, ws, x, raw, y, out, idx, stats, total;
+    size_t ws_floats;
+};
+
 struct kf_costmodel {
     kf_mlp* m = nullptr;
     uint64_t seed = 0;
-    float* d_params = nullptr;
-    float* d_grads = nullptr;
-    float* d_m = nullptr;
-    float* d_v = nullptr;
-    float* d_ws = nullptr;
-    float* d_x = nullptr;
-    float* d_y = nullptr;
-    float* d_out = nullptr;
-    size_t ws_cap = 0;   // floats of d_ws
-    long rows_cap = 0;   // rows of d_x, d_y, d_out
+    std::vector<float> params;        // host copy; authoritative while unbound
     std::vector<float> mu, sd;
     double y_mu = 0.0, y_sd = 1.0;
     float launch_us = 0.f;
+    char* mem = nullptr;              // caller-owned device memory (kf_costmodel_bind)
+    int64_t rows_cap = 0;
+    CmLayout lay{};
     ~kf_costmodel() {
-        for (float* p : {d_params, d_grads, d_m, d_v, d_ws, d_x, d_y, d_out})
-            if (p) (void)hipFree(p);
         if (m) kf_mlp_destroy(m);
     }
+    float* f(size_t off) const { return (float*)(mem + off); }
 };
 
 namespace {
 
 const int kPredictChunk = 8192;
 
-kf_status cm_reserve(kf_costmodel* cm, long rows) {
-    if (rows <= cm->rows_cap) return KF_OK;
-    for (float** p : {&cm->d_ws, &cm->d_x, &cm->d_y, &cm->d_out})
-        if (*p) { (void)hipFree(*p); *p = nullptr; }
-    cm->ws_cap = ws_floats(cm->m, rows);
-    HIPCHK(hipMalloc((void**)&cm->d_ws, cm->ws_cap * sizeof(float)));
-    HIPCHK(hipMalloc((void**)&cm->d_x, (size_t)rows * cm->m->d * sizeof(float)));
-    HIPCHK(hipMalloc((void**)&cm->d_y, (size_t)rows * sizeof(float)));
-    HIPCHK(hipMalloc((void**)&cm->d_out, (size_t)rows * sizeof(float)));
-    cm->rows_cap = rows;
+CmLayout cm_layout(const kf_mlp* m, int64_t rows) {
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    CmLayout L{};
+    const size_t pb = up((size_t)m->nparams * 4), d = (size_t)m->d, r = (size_t)rows;
+    size_t o = 0;
+    L.params = o; o += pb;
+    L.grads = o; o += pb;
+    L.mom1 = o; o += pb;
+    L.mom2 = o; o += pb;
+    L.ws_floats = ws_floats(m, rows);
+    L.ws = o; o += up(L.ws_floats * 4);
+    L.x = o; o += up(r * d * 4);
+    L.raw = o; o += up(r * d * 4);
+    L.y = o; o += up(r * 4);
+    L.out = o; o += up(r * 4);
+    L.idx = o; o += up(r * 4);
+    L.stats = o; o += up((2 * d + 4) * 4);
+    L.total = o;
+    return L;
+}
+
+// Device copies of the statistics: mu[d], sd[d], y_mu, y_sd, loss.
+float* st_mu(const kf_costmodel* cm) { return cm->f(cm->lay.stats); }
+float* st_sd(const kf_costmodel* cm) { return st_mu(cm) + cm->m->d; }
+float* st_ymu(const kf_costmodel* cm) { return st_mu(cm) + 2 * cm->m->d; }
+float* st_ysd(const kf_costmodel* cm) { return st_ymu(cm) + 1; }
+float* st_loss(const kf_costmodel* cm) { return st_ymu(cm) + 2; }
+
+kf_status upload_state(kf_costmodel* cm, hipStream_t st) {
+    const int d = cm->m->d;
+    std::vector<float> stats(2 * d + 2);
+    std::copy(cm->mu.begin(), cm->mu.end(), stats.begin());
+    std::copy(cm->sd.begin(), cm->sd.end(), stats.begin() + d);
+    stats[2 * d] = (float)cm->y_mu;
+    stats[2 * d + 1] = (float)cm->y_sd;
+    HIPCHK(hipMemcpyAsync(cm->f(cm->lay.params), cm->params.data(), cm->params.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(st_mu(cm), stats.data(), stats.size() * 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KF_OK;
+}
+
+kf_status need_bound(const kf_costmodel* cm, int64_t rows) {
+    if (!cm->mem) return set_error(KF_ERR_UNBOUND, "the cost model has no device memory: kf_costmodel_bind first");
+    if (rows > cm->rows_cap)
+        return set_error(KF_ERR_WORKSPACE, "the bound cost-model memory holds fewer rows than this call needs");
     return KF_OK;
 }
 
@@ -233,6 +278,16 @@ uint64_t splitmix(uint64_t& state) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
+}
+
+// log_us[0..c) of standardised feature rows at cm->lay.x (device) into dst (device).
+kf_status predict_staged(kf_costmodel* cm, int c, float* dst, hipStream_t st) {
+    float* ws = cm->f(cm->lay.ws);
+    kf_status s = kf_mlp_forward(cm->m, cm->f(cm->lay.params), cm->f(cm->lay.x), c, cm->f(cm->lay.out), ws,
+                                 cm->lay.ws_floats * 4, st);
+    if (s != KF_OK) return s;
+    HIPCHK(mlp_unstd(c, cm->f(cm->lay.out), st_ymu(cm), st_ysd(cm), dst, st));
+    return KF_OK;
 }
 
 }  // namespace
@@ -249,74 +304,82 @@ kf_status kf_costmodel_create(int32_t hidden, int32_t layers, uint64_t seed, kf_
     cm->seed = seed;
     cm->mu.assign(KF_FEATURE_DIM, 0.f);
     cm->sd.assign(KF_FEATURE_DIM, 1.f);
-    std::vector<float> p((size_t)cm->m->nparams);
-    kf_mlp_init_params(cm->m, seed, p.data());
-    const size_t pb = p.size() * sizeof(float);
-    for (float** d : {&cm->d_params, &cm->d_grads, &cm->d_m, &cm->d_v})
-        HIPCHK(hipMalloc((void**)d, pb));
-    HIPCHK(hipMemcpy(cm->d_params, p.data(), pb, hipMemcpyHostToDevice));
+    cm->params.assign((size_t)cm->m->nparams, 0.f);
+    kf_mlp_init_params(cm->m, seed, cm->params.data());
     *out = guard.release();
     return KF_OK;
 }
 
 void kf_costmodel_destroy(kf_costmodel* cm) { delete cm; }
 
+kf_status kf_costmodel_workspace_bytes(const kf_costmodel* cm, int64_t rows, size_t* bytes) {
+    if (!cm || !bytes || rows < 1 || rows > ((int64_t)1 << 24)) return set_error(KF_ERR_ARG, "bad argument");
+    *bytes = cm_layout(cm->m, rows).total;
+    return KF_OK;
+}
+
+kf_status kf_costmodel_bind(kf_costmodel* cm, void* mem, size_t bytes, int64_t rows, void* stream) {
+    if (!cm || !mem || rows < 1 || rows > ((int64_t)1 << 24)) return set_error(KF_ERR_ARG, "bad argument");
+    if ((uintptr_t)mem % 256) return set_error(KF_ERR_ALIGN, "cost-model memory must be 256-byte aligned");
+    const CmLayout L = cm_layout(cm->m, rows);
+    if (bytes < L.total) return set_error(KF_ERR_WORKSPACE, "cost-model memory smaller than kf_costmodel_workspace_bytes");
+    if (cm->mem) {   // keep what training did in the memory bound before
+        HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+        HIPCHK(hipMemcpy(cm->params.data(), cm->f(cm->lay.params), cm->params.size() * 4, hipMemcpyDeviceToHost));
+    }
+    cm->mem = (char*)mem;
+    cm->rows_cap = rows;
+    cm->lay = L;
+    kf_status s = upload_state(cm, (hipStream_t)stream);
+    if (s != KF_OK) cm->mem = nullptr;
+    return s;
+}
+
 kf_status kf_costmodel_train(kf_costmodel* cm, const float* X, const float* y_log_us, int64_t n, int32_t epochs,
                              int32_t batch, float lr, uint64_t seed, void* stream, float* loss_per_epoch) {
-    if (!cm || !X || !y_log_us || n < 2 || epochs < 1 || batch < 1 || !(lr > 0.f))
+    if (!cm || !X || !y_log_us || n < 2 || n > INT32_MAX || epochs < 1 || batch < 1 || !(lr > 0.f))
         return set_error(KF_ERR_ARG, "bad argument");
+    kf_status s = need_bound(cm, batch);
+    if (s != KF_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const int d = cm->m->d;
-    // feature and target standardisation from the training data
-    std::vector<double> mu(d, 0.0), var(d, 0.0);
-    double ym = 0.0, yv = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int j = 0; j < d; ++j) mu[j] += X[i * d + j];
-        ym += y_log_us[i];
-    }
-    for (int j = 0; j < d; ++j) mu[j] /= (double)n;
-    ym /= (double)n;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int j = 0; j < d; ++j) var[j] += (X[i * d + j] - mu[j]) * (X[i * d + j] - mu[j]);
-        yv += (y_log_us[i] - ym) * (y_log_us[i] - ym);
-    }
-    for (int j = 0; j < d; ++j) {
-        cm->mu[j] = (float)mu[j];
-        cm->sd[j] = (float)std::max(std::sqrt(var[j] / (double)n), 1e-3);
-    }
-    cm->y_mu = ym;
-    cm->y_sd = std::max(std::sqrt(yv / (double)n), 1e-6);
-    kf_status s = cm_reserve(cm, std::max<long>(batch, n));
-    if (s != KF_OK) return s;
+    // feature and target standardisation from the training data (on the GPU)
+    HIPCHK(mlp_col_stats(n, d, X, 1e-3f, st_mu(cm), st_sd(cm), st));
+    HIPCHK(mlp_col_stats(n, 1, y_log_us, 1e-6f, st_ymu(cm), st_ysd(cm), st));
+    std::vector<float> stats(2 * d + 2);
+    HIPCHK(hipMemcpyAsync(stats.data(), st_mu(cm), stats.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    cm->mu.assign(stats.begin(), stats.begin() + d);
+    cm->sd.assign(stats.begin() + d, stats.begin() + 2 * d);
+    cm->y_mu = stats[2 * d];
+    cm->y_sd = stats[2 * d + 1];
     const size_t pb = (size_t)cm->m->nparams * sizeof(float);
-    HIPCHK(hipMemsetAsync(cm->d_m, 0, pb, st));
-    HIPCHK(hipMemsetAsync(cm->d_v, 0, pb, st));
-    std::vector<int64_t> perm(n);
-    std::vector<float> xs((size_t)n * d), ys(n);
+    HIPCHK(hipMemsetAsync(cm->f(cm->lay.mom1), 0, pb, st));
+    HIPCHK(hipMemsetAsync(cm->f(cm->lay.mom2), 0, pb, st));
+    std::vector<int32_t> perm((size_t)n);
+    int* d_idx = (int*)(cm->mem + cm->lay.idx);
     uint64_t rng = seed * 0x9E3779B97F4A7C15ULL + 0x632BE59BD9B4E019ULL;
     int step = 0;
     for (int ep = 0; ep < epochs; ++ep) {
-        for (int64_t i = 0; i < n; ++i) perm[i] = i;
+        for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
         for (int64_t i = n - 1; i > 0; --i) std::swap(perm[i], perm[(int64_t)(splitmix(rng) % (uint64_t)(i + 1))]);
-        for (int64_t i = 0; i < n; ++i) {
-            const float* src = X + perm[i] * d;
-            for (int j = 0; j < d; ++j) xs[i * d + j] = (src[j] - cm->mu[j]) / cm->sd[j];
-            ys[i] = (float)((y_log_us[perm[i]] - cm->y_mu) / cm->y_sd);
-        }
-        HIPCHK(hipMemcpyAsync(cm->d_x, xs.data(), xs.size() * sizeof(float), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(cm->d_y, ys.data(), ys.size() * sizeof(float), hipMemcpyHostToDevice, st));
         double tot = 0.0;
         int cnt = 0;
         for (int64_t b0 = 0; b0 < n; b0 += batch) {
             const int b = (int)std::min<int64_t>(batch, n - b0);
             ++step;
-            s = kf_mlp_loss_grad(cm->m, cm->d_params, cm->d_x + b0 * d, cm->d_y + b0, b, cm->d_grads, cm->d_out,
-                                 cm->d_ws, cm->ws_cap * sizeof(float), stream);
+            // the minibatch's rows, gathered and standardised on the GPU
+            HIPCHK(hipMemcpyAsync(d_idx, perm.data() + b0, (size_t)b * 4, hipMemcpyHostToDevice, st));
+            HIPCHK(mlp_gather_std(b, d, X, d_idx, 0, st_mu(cm), st_sd(cm), cm->f(cm->lay.x), st));
+            HIPCHK(mlp_gather_std(b, 1, y_log_us, d_idx, 0, st_ymu(cm), st_ysd(cm), cm->f(cm->lay.y), st));
+            s = kf_mlp_loss_grad(cm->m, cm->f(cm->lay.params), cm->f(cm->lay.x), cm->f(cm->lay.y), b,
+                                 cm->f(cm->lay.grads), st_loss(cm), cm->f(cm->lay.ws), cm->lay.ws_floats * 4, stream);
             if (s != KF_OK) return s;
-            s = kf_mlp_adam(cm->m, cm->d_params, cm->d_grads, cm->d_m, cm->d_v, step, lr, 0.9f, 0.999f, 1e-8f, stream);
+            s = kf_mlp_adam(cm->m, cm->f(cm->lay.params), cm->f(cm->lay.grads), cm->f(cm->lay.mom1),
+                            cm->f(cm->lay.mom2), step, lr, 0.9f, 0.999f, 1e-8f, stream);
             if (s != KF_OK) return s;
             float l = 0.f;
-            HIPCHK(hipMemcpyAsync(&l, cm->d_out, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&l, st_loss(cm), sizeof(float), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             tot += l;
             ++cnt;
@@ -327,22 +390,46 @@ kf_status kf_costmodel_train(kf_costmodel* cm, const float* X, const float* y_lo
 }
 
 kf_status kf_costmodel_predict(kf_costmodel* cm, const float* X, int64_t n, float* log_us, void* stream) {
-    if (!cm || !X || !log_us || n < 0) return set_error(KF_ERR_ARG, "bad argument");
+    if (!cm || (n > 0 && (!X || !log_us)) || n < 0) return set_error(KF_ERR_ARG, "bad argument");
+    kf_status s = need_bound(cm, 1);
+    if (s != KF_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const int d = cm->m->d;
-    kf_status s = cm_reserve(cm, kPredictChunk);
-    if (s != KF_OK) return s;
-    std::vector<float> xs((size_t)kPredictChunk * d), out(kPredictChunk);
-    for (int64_t c0 = 0; c0 < n; c0 += kPredictChunk) {
-        const int c = (int)std::min<int64_t>(kPredictChunk, n - c0);
-        for (int64_t i = 0; i < c; ++i)
-            for (int j = 0; j < d; ++j) xs[i * d + j] = (X[(c0 + i) * d + j] - cm->mu[j]) / cm->sd[j];
-        HIPCHK(hipMemcpyAsync(cm->d_x, xs.data(), (size_t)c * d * sizeof(float), hipMemcpyHostToDevice, st));
-        s = kf_mlp_forward(cm->m, cm->d_params, cm->d_x, c, cm->d_out, cm->d_ws, cm->ws_cap * sizeof(float), stream);
+    for (int64_t c0 = 0; c0 < n; c0 += cm->rows_cap) {
+        const int c = (int)std::min<int64_t>(cm->rows_cap, n - c0);
+        HIPCHK(mlp_gather_std(c, d, X, nullptr, c0, st_mu(cm), st_sd(cm), cm->f(cm->lay.x), st));
+        s = predict_staged(cm, c, log_us + c0, st);
         if (s != KF_OK) return s;
-        HIPCHK(hipMemcpyAsync(out.data(), cm->d_out, (size_t)c * sizeof(float), hipMemcpyDeviceToHost, st));
+    }
+    return KF_OK;
+}
+
+kf_status kf_costmodel_plan_us(kf_costmodel* cm, const float* feats, int64_t rows, const int64_t* start,
+                               int32_t nplans, double* us, void* stream) {
+    if (!cm || nplans < 0 || rows < 0 || (nplans > 0 && (!start || !us)) || (rows > 0 && !feats))
+        return set_error(KF_ERR_ARG, "bad argument");
+    for (int32_t i = 0; i < nplans; ++i)
+        if (start[i] < 0 || start[i] > start[i + 1] || start[i + 1] > rows)
+            return set_error(KF_ERR_ARG, "plan row ranges must be ordered and inside the feature rows");
+    kf_status s = need_bound(cm, 1);
+    if (s != KF_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int d = cm->m->d;
+    std::vector<float> lg((size_t)rows);
+    for (int64_t c0 = 0; c0 < rows; c0 += cm->rows_cap) {
+        const int c = (int)std::min<int64_t>(cm->rows_cap, rows - c0);
+        HIPCHK(hipMemcpyAsync(cm->f(cm->lay.raw), feats + c0 * d, (size_t)c * d * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(mlp_gather_std(c, d, cm->f(cm->lay.raw), nullptr, 0, st_mu(cm), st_sd(cm), cm->f(cm->lay.x), st));
+        s = predict_staged(cm, c, cm->f(cm->lay.out), st);
+        if (s != KF_OK) return s;
+        HIPCHK(hipMemcpyAsync(lg.data() + c0, cm->f(cm->lay.out), (size_t)c * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        for (int i = 0; i < c; ++i) log_us[c0 + i] = (float)(out[i] * cm->y_sd + cm->y_mu);
+    }
+    for (int32_t i = 0; i < nplans; ++i) {
+        double t = 0.0;
+        for (int64_t r = start[i]; r < start[i + 1]; ++r)
+            t += std::exp((double)lg[r]) + (double)cm->launch_us * feats[r * d + 25];
+        us[i] = t;
     }
     return KF_OK;
 }
@@ -356,8 +443,16 @@ kf_status kf_costmodel_set_launch_us(kf_costmodel* cm, float us) {
 kf_status kf_costmodel_get(const kf_costmodel* cm, float* params, float* mu, float* sd, double* y_mu_sd,
                            float* launch_us) {
     if (!cm) return set_error(KF_ERR_ARG, "null model");
-    if (params && hipMemcpy(params, cm->d_params, (size_t)cm->m->nparams * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess)
-        return set_error(KF_ERR_HIP, "reading the model parameters failed");
+    if (params) {
+        if (cm->mem) {
+            if (hipDeviceSynchronize() != hipSuccess ||
+                hipMemcpy(params, cm->f(cm->lay.params), (size_t)cm->m->nparams * sizeof(float),
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return set_error(KF_ERR_HIP, "reading the model parameters failed");
+        } else {
+            std::memcpy(params, cm->params.data(), cm->params.size() * sizeof(float));
+        }
+    }
     if (mu) std::memcpy(mu, cm->mu.data(), cm->mu.size() * sizeof(float));
     if (sd) std::memcpy(sd, cm->sd.data(), cm->sd.size() * sizeof(float));
     if (y_mu_sd) { y_mu_sd[0] = cm->y_mu; y_mu_sd[1] = cm->y_sd; }
@@ -370,13 +465,16 @@ kf_status kf_costmodel_set(kf_costmodel* cm, const float* params, const float* m
     if (!cm || !params || !mu || !sd || !y_mu_sd || !(y_mu_sd[1] > 0.0)) return set_error(KF_ERR_ARG, "bad argument");
     for (int j = 0; j < cm->m->d; ++j)
         if (!(sd[j] > 0.f)) return set_error(KF_ERR_ARG, "feature scales must be positive");
-    if (hipMemcpy(cm->d_params, params, (size_t)cm->m->nparams * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-        return set_error(KF_ERR_HIP, "writing the model parameters failed");
+    cm->params.assign(params, params + cm->m->nparams);
     cm->mu.assign(mu, mu + cm->m->d);
     cm->sd.assign(sd, sd + cm->m->d);
     cm->y_mu = y_mu_sd[0];
     cm->y_sd = y_mu_sd[1];
     cm->launch_us = launch_us;
+    if (cm->mem) {
+        if (hipDeviceSynchronize() != hipSuccess) return set_error(KF_ERR_HIP, "hipDeviceSynchronize failed");
+        return upload_state(cm, nullptr);
+    }
     return KF_OK;
 }
 
@@ -482,13 +580,9 @@ namespace kf {
 kf_status costmodel_plan_us(kf_costmodel* cm, const std::vector<float>& feats, const std::vector<size_t>& start,
                             hipStream_t st, std::vector<double>* us) {
     const size_t rows = feats.size() / KF_FEATURE_DIM;
-    std::vector<float> lg(rows);
-    kf_status s = kf_costmodel_predict(cm, feats.data(), (int64_t)rows, lg.data(), st);
-    if (s != KF_OK) return s;
+    std::vector<int64_t> st64(start.begin(), start.end());
     us->assign(start.size() - 1, 0.0);
-    for (size_t i = 0; i + 1 < start.size(); ++i)
-        for (size_t r = start[i]; r < start[i + 1]; ++r)
-            (*us)[i] += std::exp((double)lg[r]) + cm->launch_us * feats[r * KF_FEATURE_DIM + 25];
-    return KF_OK;
+    return kf_costmodel_plan_us(cm, feats.data(), (int64_t)rows, st64.data(), (int32_t)(start.size() - 1), us->data(),
+                                st);
 }
 }  // namespace kf

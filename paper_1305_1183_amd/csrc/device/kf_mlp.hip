@@ -9,6 +9,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "device/kf_blocks.h"
+
 namespace kf {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -88,6 +90,84 @@ __global__ void mlp_adam_kernel(long n, float* __restrict__ p, const float* __re
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Per-column mean and standard deviation (population, floored at `floor`) of
+// an n x d row-major matrix, for the standardisation of features and targets.
+// One workgroup per column; thread t adds rows t, t + 256, ... with
+// compensated sums, then the 256 pairs are merged by a fixed halving tree.
+// Two passes: the mean, then the squared deviations from it.
+__device__ __forceinline__ float mlp_block_total(kf_cs v, kf_cs* part) {
+    const int t = threadIdx.x;
+    part[t] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part[t] = kf_cs_merge(part[t], part[t + w]);
+        __syncthreads();
+    }
+    const float r = kf_cs_value(part[0]);
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) mlp_col_stats_kernel(long n, int d, const float* __restrict__ X,
+                                                            float floor, float* __restrict__ mu,
+                                                            float* __restrict__ sd) {
+    __shared__ kf_cs part[256];
+    const int j = blockIdx.x;
+    kf_cs a = kf_cs_init(0.f);
+    for (long i = threadIdx.x; i < n; i += 256) a = kf_cs_add(a, X[i * d + j]);
+    const float mean = mlp_block_total(a, part) / (float)n;
+    kf_cs q = kf_cs_init(0.f);
+    for (long i = threadIdx.x; i < n; i += 256) {
+        const float e = X[i * d + j] - mean;
+        q = kf_cs_add(q, e * e);
+    }
+    const float var = mlp_block_total(q, part) / (float)n;
+    if (threadIdx.x == 0) {
+        mu[j] = mean;
+        sd[j] = fmaxf(sqrtf(var), floor);
+    }
+}
+
+// out(r, j) = (X(src, j) - mu(j)) / sd(j) for r < rows, with src = idx[r]
+// (a minibatch in shuffled order) or row0 + r when idx is null.
+__global__ void mlp_gather_std_kernel(int rows, int d, const float* __restrict__ X, const int* __restrict__ idx,
+                                      long row0, const float* __restrict__ mu, const float* __restrict__ sd,
+                                      float* __restrict__ out) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)rows * d) return;
+    const int r = (int)(i / d), j = (int)(i % d);
+    const long src = idx ? (long)idx[r] : row0 + r;
+    out[i] = (X[src * d + j] - mu[j]) / sd[j];
+}
+
+// out(i) = p(i) sd + mu: a standardised prediction back to log microseconds.
+__global__ void mlp_unstd_kernel(int n, const float* __restrict__ p, const float* __restrict__ mu,
+                                 const float* __restrict__ sd, float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = __builtin_fmaf(p[i], *sd, *mu);
+}
+
+hipError_t mlp_col_stats(long n, int d, const float* X, float floor, float* mu, float* sd, hipStream_t st) {
+    if (n <= 0 || d <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(mlp_col_stats_kernel, dim3(d), dim3(256), 0, st, n, d, X, floor, mu, sd);
+    return hipGetLastError();
+}
+
+hipError_t mlp_gather_std(int rows, int d, const float* X, const int* idx, long row0, const float* mu,
+                          const float* sd, float* out, hipStream_t st) {
+    const long total = (long)rows * d;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_gather_std_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, rows, d, X,
+                       idx, row0, mu, sd, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_unstd(int n, const float* p, const float* mu, const float* sd, float* out, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_unstd_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p, mu, sd, out);
+    return hipGetLastError();
 }
 
 hipError_t mlp_gemm(int M, int N, int K, const float* A, long sai, long sak, const float* B, long sbk, long sbj,

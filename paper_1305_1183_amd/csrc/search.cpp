@@ -467,17 +467,13 @@ kf_status costmodel_plan_us(kf_costmodel* cm, const std::vector<float>& feats, c
 
 namespace {
 
-// Times candidates of a planset kernel by kernel with the caller's buffers; the
-// workspace is allocated here and grown as candidates need it.
+// Times candidates of a planset kernel by kernel with the caller's buffers and
+// the caller's workspace (opts.workspace).
 struct Timer {
     const kf_planset* ps;
     const kf_compile_opts& o;
-    void* ws = nullptr;
-    size_t ws_bytes = 0;
+    int too_big = 0;   // candidates whose workspace did not fit
     Timer(const kf_planset* p, const kf_compile_opts& opts) : ps(p), o(opts) {}
-    ~Timer() {
-        if (ws) (void)hipFree(ws);
-    }
     kf_status time_kernels(int32_t i, std::vector<double>* us) {
         kf_plan* p = nullptr;
         kf_status s = kf_planset_compile(ps, i, 0, &p);
@@ -489,15 +485,12 @@ struct Timer {
         }
         size_t need = 0;
         kf_plan_workspace_bytes(p, &need);
-        if (need > ws_bytes) {
-            if (ws) (void)hipFree(ws);
-            ws = nullptr;
-            ws_bytes = 0;
-            if (hipMalloc(&ws, need) != hipSuccess) return set_error(KF_ERR_HIP, "hipMalloc of the timing workspace failed");
-            ws_bytes = need;
+        if (need > o.workspace_bytes || (need && !o.workspace)) {
+            ++too_big;
+            return set_error(KF_ERR_WORKSPACE, "candidate workspace larger than opts.workspace_bytes");
         }
         if (need) {
-            s = kf_bind_workspace(p, ws, ws_bytes);
+            s = kf_bind_workspace(p, o.workspace, o.workspace_bytes);
             if (s != KF_OK) return s;
         }
         std::vector<float> t(p->ks.size());
@@ -536,7 +529,11 @@ kf_status measured_combination(const kf_planset* ps, const kf_compile_opts& o, c
         any = true;
     }
     *best = best_combination(ps, cost);
-    if (best->first < 0) return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");
+    if (best->first < 0) {
+        if (t.too_big > 0 && !any)
+            return set_error(KF_ERR_WORKSPACE, "no candidate fits opts.workspace_bytes (see kf_compile_workspace_bytes)");
+        return set_error(KF_ERR_UNSUPPORTED, "no candidate could be timed");
+    }
     return KF_OK;
 }
 
@@ -595,6 +592,24 @@ kf_status compile_learned(const kf_script* s, const kf_compile_opts& o, kf_plan*
         if (st != KF_OK) return st;
     }
     return compile_combination(ps, best, o.flags, out);
+}
+
+kf_status timed_workspace_bytes(const kf_script* s, const kf_compile_opts& o, size_t* bytes) {
+    kf_planset* ps = nullptr;
+    kf_status st = candidates_for(s, o, &ps);
+    if (st != KF_OK) return st;
+    std::unique_ptr<kf_planset> guard(ps);
+    size_t most = 0;
+    for (size_t i = 0; i < ps->parts.size(); ++i) {
+        kf_plan* p = nullptr;
+        if (kf_planset_compile(ps, (int32_t)i, KF_COMPILE_CODEGEN_ONLY, &p) != KF_OK) continue;
+        size_t need = 0;
+        kf_plan_workspace_bytes(p, &need);
+        kf_plan_destroy(p);
+        most = std::max(most, need);
+    }
+    *bytes = most;
+    return KF_OK;
 }
 
 kf_status compile_exhaustive(const kf_script* s, const kf_compile_opts& o, kf_plan** out) {

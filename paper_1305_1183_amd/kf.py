@@ -25,6 +25,7 @@ ERRORS = {
     -9: "KF_ERR_COMPILE", -10: "KF_ERR_HIP", -11: "KF_ERR_NOMEM", -12: "KF_ERR_UNSUPPORTED",
     -13: "KF_ERR_INTERNAL",
 }
+globals().update({name: code for code, name in ERRORS.items()})   # KF_ERR_ARG = -1, ...
 KF_NONE = -1
 MODES = {"unfused": 0, "fused": 1, "additive": 2, "learned": 3, "exhaustive": 4, "partition": 5}
 KF_COMPILE_NO_LOAD = 1
@@ -73,7 +74,7 @@ kf_compile_opts._fields_ = [("mode", _i32), ("flags", _i32),
                             ("model", _vp), ("stream", _vp), ("bind_values", _P(_i32)), ("bind_ptrs", _P(_vp)),
                             ("bind_len", _i32), ("top_k", _i32),
                             ("kernel_params", _P(kf_impl_params)), ("kernel_params_len", _i32),
-                            ("time_budget_ms", _i32)]
+                            ("time_budget_ms", _i32), ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t)]
 PARAM_FIELDS = ["mat_k", "mat_waves", "mat_group", "mat_rows", "vec_unroll", "vec_threads", "vec_grid",
                 "mat_sched", "mat_unit"]
 
@@ -106,6 +107,7 @@ _SIGS = {
     "kf_script_num_calls": ([_vp, _P(_i32)], _i32),
     "kf_script_call": ([_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)], _i32),
     "kf_compile_opts_init": ([_P(kf_compile_opts)], None),
+    "kf_compile_workspace_bytes": ([_vp, _P(kf_compile_opts), _P(_sz)], _i32),
     "kf_compile": ([_vp, _P(kf_compile_opts), _P(_vp)], _i32),
     "kf_plan_destroy": ([_vp], None),
     "kf_enumerate": ([_vp, _i32, _P(_vp)], _i32),
@@ -153,8 +155,11 @@ _SIGS = {
     "kf_jit_stats": ([_P(_i64), _P(_i64)], _i32),
     "kf_costmodel_create": ([_i32, _i32, _u64, _P(_vp)], _i32),
     "kf_costmodel_destroy": ([_vp], None),
-    "kf_costmodel_train": ([_vp, _P(_f32), _P(_f32), _i64, _i32, _i32, _f32, _u64, _vp, _P(_f32)], _i32),
-    "kf_costmodel_predict": ([_vp, _P(_f32), _i64, _P(_f32), _vp], _i32),
+    "kf_costmodel_workspace_bytes": ([_vp, _i64, _P(_sz)], _i32),
+    "kf_costmodel_bind": ([_vp, _vp, _sz, _i64, _vp], _i32),
+    "kf_costmodel_train": ([_vp, _vp, _vp, _i64, _i32, _i32, _f32, _u64, _vp, _P(_f32)], _i32),
+    "kf_costmodel_predict": ([_vp, _vp, _i64, _vp, _vp], _i32),
+    "kf_costmodel_plan_us": ([_vp, _P(_f32), _i64, _P(_i64), _i32, _P(ctypes.c_double), _vp], _i32),
     "kf_costmodel_set_launch_us": ([_vp, _f32], _i32),
     "kf_costmodel_get": ([_vp, _P(_f32), _P(_f32), _P(_f32), _P(ctypes.c_double), _P(_f32)], _i32),
     "kf_costmodel_set": ([_vp, _P(_f32), _P(_f32), _P(_f32), _P(ctypes.c_double), _f32], _i32),
@@ -322,12 +327,13 @@ def kf_script_call(s, i: int) -> dict:
 # ---- compile / enumerate --------------------------------------------------------
 def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid=None, max_partitions=0,
                          model=None, stream=None, bind=None, top_k=0, kernel_params=None, time_budget_ms=0,
-                         **params) -> kf_compile_opts:
+                         workspace=None, **params) -> kf_compile_opts:
     """bind: {script value handle: device pointer} of every input and output
-    (timing in the learned top-k and exhaustive modes); model: a cost-model
-    handle (kf_costmodel_create / kf_costmodel_load); kernel_params: one dict
-    of implementation parameters per plan kernel, in launch order (missing or
-    zero entries take the plan-wide parameters)."""
+    (timing in the learned top-k and exhaustive modes); workspace: (device
+    pointer, bytes) of the timed modes' plan workspace; model: a cost-model
+    handle with bound memory; kernel_params: one dict of implementation
+    parameters per plan kernel, in launch order (missing or zero entries take
+    the plan-wide parameters)."""
     o = kf_compile_opts()
     lib().kf_compile_opts_init(ctypes.byref(o))
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -335,6 +341,9 @@ def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid
     o.max_partitions = max_partitions
     o.top_k = int(top_k)
     o.time_budget_ms = int(time_budget_ms)
+    if workspace is not None:
+        o.workspace = int(workspace[0])
+        o.workspace_bytes = int(workspace[1])
     if model is not None:
         o.model = model
     if stream is not None:
@@ -379,11 +388,36 @@ def kf_compile_opts_init(mode="fused", flags=0, partition=None, table=None, grid
     return o
 
 
+def kf_compile_workspace_bytes(s, opts=None, **kw) -> int:
+    if opts is None:
+        opts = kf_compile_opts_init(**kw)
+    n = _sz()
+    _chk(lib().kf_compile_workspace_bytes(s, ctypes.byref(opts), ctypes.byref(n)))
+    return n.value
+
+
 def kf_compile(s, opts=None, **kw):
     if opts is None:
         opts = kf_compile_opts_init(**kw)
+    ws = None
+    timed = opts.mode == MODES["exhaustive"] or (opts.mode == MODES["learned"] and opts.top_k > 1)
+    if timed and not opts.workspace and opts.bind_len > 0:
+        # the caller's side of the ownership contract: the timed modes' plan
+        # workspace, sized by the library and allocated here by torch
+        import torch
+        need = kf_compile_workspace_bytes(s, opts)
+        if need:
+            ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            opts.workspace = (ws.data_ptr() + 255) // 256 * 256
+            opts.workspace_bytes = need
     h = _vp()
-    _chk(lib().kf_compile(s, ctypes.byref(opts), ctypes.byref(h)))
+    try:
+        _chk(lib().kf_compile(s, ctypes.byref(opts), ctypes.byref(h)))
+    finally:
+        if ws is not None:
+            torch.cuda.current_stream().synchronize()
+            opts.workspace, opts.workspace_bytes = None, 0
+            del ws
     return h
 
 

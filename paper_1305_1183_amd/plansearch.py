@@ -97,16 +97,15 @@ def cmd_evaluate(a):
         cands = kf.Candidates(rs.script, 64, SE.grid_points())
         # learned ranking: features + model (timed as the search would run it)
         t1 = time.perf_counter()
-        feats, nl = [], []
+        feats = []
         for i in idx:
             p = cands.compile(int(i), kf.KF_COMPILE_CODEGEN_ONLY)
             f = kf.kf_plan_features(p)
             feats.append(f)
-            nl.append(float(np.sum(f[:, 25])))
             kf.kf_plan_destroy(p)
         t_feat = time.perf_counter() - t1
         t1 = time.perf_counter()
-        learned = cm.predict_plan_us(feats) + c_launch * np.array(nl)
+        learned = cm.predict_plan_us(feats)    # the model's launch term included (set above)
         t_pred = time.perf_counter() - t1
         row = {"seed": seed, "script": rs.describe(), "candidates": int(len(m)),
                "best_us": float(true.min()), "learned": SE.rank_metrics(true, learned)}

@@ -152,3 +152,54 @@ def test_batch_full_config_sampled():
                                      vals["v2"], vals["y"], vals["z"], cols=n)
             ref = {"B": Bm, "x": x, "w": w}
         check(bt, None, host_out, idx=[i], refs={i: ref})
+
+
+def test_wait_timeout_reported_and_cleared():
+    """A spin limit of one lets the dependent items of split GEMVER instances
+    give up their bounded wait (every workgroup still exits). kf_batch_error
+    reports the bit and clears the counters and the error word; a batch of the
+    same instances with the default limit, bound to the same arena and
+    workspace, then runs correctly."""
+    kinds = np.full(64, B.GEMVER, np.int32)
+    ns = np.full(64, 2000)
+    al, be = np.full(64, 1.25, np.float32), np.full(64, 0.75, np.float32)
+    tiny = B.Batch(kinds, ns, al, be, kf.batch_opts(spin_limit=1))
+    good = B.Batch(kinds, ns, al, be, None)
+    assert tiny.elems == good.elems and tiny.ws_bytes == good.ws_bytes
+    host_in = tiny.host_arena(seed=19)
+    tiny.upload(host_in)
+    st = tiny.stream()
+    print("case timeout: tiny spin limit", flush=True)
+    tiny.run(0)
+    bits = kf.kf_batch_error(tiny.h, st)
+    assert bits in (0, 1), bits
+    assert kf.kf_batch_error(tiny.h, st) == 0     # cleared by the first call
+    print("case timeout: bits %d, then the default limit" % bits, flush=True)
+    kf.kf_batch_bind(good.h, tiny.arena.data_ptr(), tiny.ws.data_ptr(), st)
+    good.arena = tiny.arena
+    good.run(0)
+    assert kf.kf_batch_error(good.h, st) == 0
+    out = good.arena.cpu().numpy()
+    check(good, host_in, out, idx=[0, 31, 63])
+
+
+def test_split_batch_replays_bitwise_deterministic():
+    """The all-split small batch (every instance above one step cut into
+    blocks, cross-XCD arrivals and flags in every instance) replayed from a
+    graph 100 times: every replay gives the bits of the first run."""
+    bt = small_batch(opts=kf.batch_opts(rows={0: RPS, 1: RPS}))
+    host_in = bt.host_arena(seed=23)
+    bt.upload(host_in)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        kf.kf_batch_run(bt.h, 0, st.cuda_stream)
+        st.synchronize()
+        first = bt.arena.cpu().numpy()
+        check(bt, host_in, first)
+        kf.kf_batch_capture(bt.h, 0, st.cuda_stream)
+        for r in range(100):
+            kf.kf_batch_graph_launch(bt.h, 0, st.cuda_stream)
+            st.synchronize()
+            got = bt.arena.cpu().numpy()
+            assert np.array_equal(got, first, equal_nan=True), "replay %d differs" % r
+        assert kf.kf_batch_error(bt.h, st.cuda_stream) == 0
