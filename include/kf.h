@@ -168,8 +168,10 @@ enum {
 };
 enum {
     KF_COMPILE_NO_LOAD = 1,       /* stop after hipRTC (no GPU needed): build checks */
-    KF_COMPILE_CODEGEN_ONLY = 2   /* generate code but do not compile: features, bytes,
+    KF_COMPILE_CODEGEN_ONLY = 2,  /* generate code but do not compile: features, bytes,
                                      additive predictions (kf_run is refused) */
+    KF_COMPILE_RUNTIME_SHAPE = 4  /* kernels take rows, cols and each matrix's leading
+                                     dimension as arguments (kf_plan_set_shape) */
 };
 struct kf_routine_entry;
 /* Implementation parameters of one plan kernel (fields as in kf_compile_opts;
@@ -303,6 +305,32 @@ kf_status kf_bind(kf_plan* p, kf_value v, void* dev_ptr);
 kf_status kf_bind_workspace(kf_plan* p, void* dev_ptr, size_t bytes);
 /* Change a kf_const value without recompiling. */
 kf_status kf_set_const(kf_plan* p, kf_value v, float value);
+
+/* Runtime-shape plans (KF_COMPILE_RUNTIME_SHAPE; the same problem at many
+ * sizes without recompiling, e.g. one plan per size class of a batch). Every
+ * matrix of the script must have one storage shape rows x cols (the
+ * declared, largest shape) and every vector rows or cols entries; every call
+ * must be a BLAS-2 call, and the kernels use the strip schedule (a kernel that
+ * needs whole rows in a workgroup is KF_ERR_UNSUPPORTED). The workspace is
+ * sized for the declared shape.
+ * kf_plan_set_shape: run at rows x cols (1 .. declared; square if declared
+ * square); unbinds every buffer, since their sizes change. Vectors then hold
+ * rows or cols entries (as declared), matrices rows x ld elements.
+ * kf_bind_matrix: bind a matrix with its own leading dimension ld (in
+ * elements, >= cols of the current shape, rows of 16 bytes); kf_bind uses the
+ * declared ld. Errors: KF_ERR_STATE for a plan without runtime shape,
+ * KF_ERR_SHAPE, KF_ERR_ALIGN, KF_ERR_DTYPE, KF_ERR_ALIAS. */
+kf_status kf_plan_set_shape(kf_plan* p, int64_t rows, int64_t cols);
+kf_status kf_bind_matrix(kf_plan* p, kf_value v, void* dev_ptr, int64_t ld);
+/* Run a runtime-shape plan over `count` instances, one after another on
+ * `stream`: instance i has shape shapes[2i] x shapes[2i + 1] and binds
+ * values[j] to ptrs[i * nvals + j] (matrices with leading dimension
+ * lds[i * nvals + j], or the declared ld when lds is NULL); the workspace
+ * bound to the plan serves every instance. Same as kf_plan_set_shape, the
+ * binds and kf_run per instance, without host round trips in between.
+ * Leaves the last instance's shape and buffers bound. */
+kf_status kf_plan_run_many(kf_plan* p, int64_t count, const int64_t* shapes, int32_t nvals, const kf_value* values,
+                           void* const* ptrs, const int64_t* lds, void* stream);
 /* Launch every kernel of the plan on `stream` (a hipStream_t; NULL = the null
  * stream). Asynchronous; allocates nothing and keeps no state on the device
  * between runs, so repeated runs and graph replays need no preparation. A

@@ -182,3 +182,71 @@ def autotune(kind: int, bucket: int, count: int = 683, seed: int = 1, reps: int 
         torch.cuda.empty_cache()
     best = min(res, key=lambda t: t[1])[0]
     return best, res
+
+
+BUCKET_MAX = [b for _, b in BUCKET_RANGE]
+
+
+class PlanLoop:
+    """Baseline of the batched launch: the library's own single-instance fused
+    plans launched once per instance. One runtime-shape plan per (kind, size
+    bucket), declared at the bucket's largest n with the library's default
+    parameters for that shape, runs every instance of the bucket at its own
+    size n x n and row pitch (kf_plan_run_many), on the operands of a bound
+    Batch's arena; GEMVER's alpha and beta are per-instance device scalars."""
+
+    def __init__(self, bt: "Batch", params: dict = None):
+        from . import sequences as S
+        assert bt.arena is not None, "upload or fill the batch first"
+        self.bt = bt
+        n_inst = len(bt.kinds)
+        al = bt.alpha if bt.alpha is not None else np.ones(n_inst, np.float32)
+        be = bt.beta if bt.beta is not None else np.ones(n_inst, np.float32)
+        self.scal = torch.from_numpy(np.stack([al, be], 1).astype(np.float32).ravel()).to(bt.device)
+        base, sbase = bt.arena.data_ptr(), self.scal.data_ptr()
+        self.groups = []
+        buckets = np.searchsorted(BUCKET_MAX, bt.ns)
+        for kind in (BICGK, GEMVER):
+            for b in range(len(BUCKET_MAX)):
+                idx = np.flatnonzero((bt.kinds == kind) & (buckets == b))
+                if not len(idx):
+                    continue
+                nmax = BUCKET_MAX[b]
+                q = S.bicgk(nmax, nmax) if kind == BICGK else S.gemver_dev(nmax, nmax)
+                plan = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_RUNTIME_SHAPE, **(params or {}))
+                need = kf.kf_plan_workspace_bytes(plan)
+                ws = torch.empty(need // 4 + 64, dtype=torch.float32, device=bt.device)
+                kf.kf_bind_workspace(plan, (ws.data_ptr() + 255) // 256 * 256, need)
+                names = (["A", "p", "r", "q", "s"] if kind == BICGK else
+                         ["A", "u1", "v1", "u2", "v2", "y", "z", "alpha", "beta", "B", "x", "w"])
+                vals = [q.values[nm] for nm in names]
+                ptrs = np.zeros((len(idx), len(names)), np.uint64)
+                lds = np.zeros((len(idx), len(names)), np.int64)
+                for r, i in enumerate(idx):
+                    for j, nm in enumerate(names):
+                        if nm in ("alpha", "beta"):
+                            ptrs[r, j] = sbase + 4 * (2 * int(i) + (nm == "beta"))
+                        else:
+                            off, ld = bt.offset(int(i), nm)
+                            ptrs[r, j] = base + 4 * off
+                            lds[r, j] = ld if nm in ("A", "B") else 0
+                shapes = np.stack([bt.ns[idx], bt.ns[idx]], 1).astype(np.int64)
+                self.groups.append((q, plan, ws, shapes, vals, ptrs, lds))
+
+    def __del__(self):
+        for g in getattr(self, "groups", []):
+            if kf is not None:
+                kf.kf_plan_destroy(g[1])
+        self.groups = []
+
+    def run(self, stream: int) -> None:
+        for q, plan, ws, shapes, vals, ptrs, lds in self.groups:
+            kf.kf_plan_run_many(plan, shapes, vals, ptrs, lds, stream)
+
+    def launches(self) -> int:
+        """HIP launches of one run of the loop."""
+        tot = 0
+        for q, plan, ws, shapes, vals, ptrs, lds in self.groups:
+            per = sum(kf.kf_plan_num_launches(plan, k) for k in range(kf.kf_plan_num_kernels(plan)))
+            tot += per * len(shapes)
+        return tot

@@ -545,6 +545,31 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
     mp0.rows = o.mat_rows;
     mp0.sched = o.mat_sched;
     mp0.unit = o.mat_unit;
+    if (o.flags & KF_COMPILE_RUNTIME_SHAPE) {
+        // every matrix shares one storage shape, and every vector is a row or a
+        // column vector of it; runs may then take any smaller shape
+        int64_t M = -1, N = -1;
+        for (const Value& x : sc.values)
+            if (x.kind == VK::Mat) {
+                if (M < 0) { M = x.rows; N = x.cols; }
+                if (x.rows != M || x.cols != N)
+                    return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans need every matrix of one shape");
+            }
+        if (M < 0) return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans need BLAS-2 calls");
+        for (const Value& x : sc.values)
+            if (x.kind == VK::Vec && x.n != M && x.n != N)
+                return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans need vectors of the matrix's rows or cols");
+        for (int c = 0; c < (int)sc.calls.size(); ++c)
+            if (!call_space(sc, c).mat) return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans take BLAS-2 kernels only");
+        if (o.mat_sched == 1) return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans use the strip schedule");
+        mp0.dyn = true;
+        p->dyn = true;
+        p->decl_m = p->rt_m = M;
+        p->decl_n = p->rt_n = N;
+        p->rt_ld.assign(nv, 0);
+        for (size_t v = 0; v < nv; ++v)
+            if (sc.values[v].kind == VK::Mat) p->rt_ld[v] = sc.values[v].ld;
+    }
     VecParams vp0;
     vp0.unroll = o.vec_unroll;
     vp0.threads = o.vec_threads;
@@ -579,6 +604,8 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
         pk.mp = mp;
         pk.vp = vp;
         Space sp = call_space(sc, calls[0]);
+        if (mp0.dyn && (mp.sched == 1 || needs_rowres(sc, calls)))
+            return set_error(KF_ERR_UNSUPPORTED, "runtime-shape plans use the strip schedule (this kernel needs whole rows)");
         if (sp.mat && (mp.sched == 1 || needs_rowres(sc, calls))) {
             if (sp.b > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
             if (kernel_has_quantized(sc, calls))
@@ -710,7 +737,21 @@ static bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     return x < y + nb && y < x + na;
 }
 
-kf_status kf_bind(kf_plan* p, kf_value v, void* ptr) {
+// Bytes of value v's buffer as the plan will touch it: the declared shape, or
+// for runtime-shape plans the current shape (rows x leading dimension for a
+// matrix, rows or cols entries for a vector).
+static size_t bound_bytes(const kf_plan* p, int v) {
+    const Value& x = p->s.values[v];
+    if (!p->dyn) return value_bytes(x);
+    switch (x.kind) {
+        case VK::Vec: return (size_t)(x.n == p->decl_m ? p->rt_m : p->rt_n) * 4;
+        case VK::Mat: return (size_t)p->rt_m * (size_t)p->rt_ld[v] * (size_t)dtype_size(x.dtype);
+        case VK::DevScalar: return 4;
+        default: return 0;
+    }
+}
+
+static kf_status bind_checked(kf_plan* p, kf_value v, void* ptr) {
     if (!p) return set_error(KF_ERR_ARG, "null plan");
     if (v < 0 || v >= (kf_value)p->s.values.size()) return set_error(KF_ERR_ARG, "bad value handle");
     const Value& x = p->s.values[v];
@@ -720,17 +761,49 @@ kf_status kf_bind(kf_plan* p, kf_value v, void* ptr) {
     if (!ptr) return set_error(KF_ERR_ARG, "null device pointer");
     size_t al = x.kind == VK::DevScalar ? 4 : 16;
     if ((uintptr_t)ptr % al) return set_error(KF_ERR_ALIGN, "device pointer misaligned");
-    const size_t nb = value_bytes(x);
+    const size_t nb = bound_bytes(p, v);
     // an output must not overlap any other bound value
     for (size_t w = 0; w < p->s.values.size(); ++w) {
         if ((kf_value)w == v || !p->bind[w]) continue;
         const Value& y = p->s.values[w];
         bool vw = x.producer >= 0, ww = y.producer >= 0;
-        if ((vw || ww) && overlap(ptr, nb, p->bind[w], value_bytes(y)))
+        if ((vw || ww) && overlap(ptr, nb, p->bind[w], bound_bytes(p, (int)w)))
             return set_error(KF_ERR_ALIAS, "an output buffer overlaps another operand");
     }
     p->bind[v] = ptr;
     return KF_OK;
+}
+
+kf_status kf_bind(kf_plan* p, kf_value v, void* ptr) { return bind_checked(p, v, ptr); }
+
+kf_status kf_plan_set_shape(kf_plan* p, int64_t rows, int64_t cols) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (!p->dyn) return set_error(KF_ERR_STATE, "the plan was not compiled with KF_COMPILE_RUNTIME_SHAPE");
+    if (rows < 1 || cols < 1 || rows > p->decl_m || cols > p->decl_n)
+        return set_error(KF_ERR_SHAPE, "runtime shape outside 1 .. the declared shape");
+    if (p->decl_m == p->decl_n && rows != cols)
+        return set_error(KF_ERR_SHAPE, "a plan declared square runs square shapes only");
+    p->rt_m = rows;
+    p->rt_n = cols;
+    for (size_t v = 0; v < p->s.values.size(); ++v) {
+        if (p->inter_off[v] == SIZE_MAX) p->bind[v] = nullptr;
+        if (p->s.values[v].kind == VK::Mat) p->rt_ld[v] = p->s.values[v].ld;
+    }
+    return KF_OK;
+}
+
+kf_status kf_bind_matrix(kf_plan* p, kf_value v, void* ptr, int64_t ld) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (!p->dyn) return set_error(KF_ERR_STATE, "the plan was not compiled with KF_COMPILE_RUNTIME_SHAPE");
+    if (v < 0 || v >= (kf_value)p->s.values.size() || p->s.values[v].kind != VK::Mat)
+        return set_error(KF_ERR_DTYPE, "not a matrix value");
+    const int es = dtype_size(p->s.values[v].dtype);
+    if (ld < p->rt_n || (ld * es) % 16) return set_error(KF_ERR_ALIGN, "ld must be >= the runtime cols and make 16-byte rows");
+    const int64_t old = p->rt_ld[v];
+    p->rt_ld[v] = ld;
+    kf_status st = bind_checked(p, v, ptr);
+    if (st != KF_OK) p->rt_ld[v] = old;
+    return st;
 }
 
 kf_status kf_bind_workspace(kf_plan* p, void* ptr, size_t bytes) {
@@ -751,12 +824,15 @@ kf_status kf_set_const(kf_plan* p, kf_value v, float value) {
     return KF_OK;
 }
 
-static void* value_ptr(kf_plan* p, int v) {
-    if (p->inter_off[v] != SIZE_MAX) return (char*)p->ws + p->inter_off[v];
+// Device address of value v: a bound buffer, or its place in workspace ws.
+static void* value_ptr(kf_plan* p, int v, void* ws) {
+    if (p->inter_off[v] != SIZE_MAX) return (char*)ws + p->inter_off[v];
     return p->bind[v];
 }
 
-static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, int first = 0,
+// Launches first .. last - 1 of kernel k with workspace ws (the bound one, or
+// the static scratch of kf_run_noalloc).
+static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, void* ws, int first = 0,
                                int last = -1) {
     if (last < 0) last = (int)k.code.launches.size();
     for (size_t li = (size_t)first; li < (size_t)last; ++li) {
@@ -765,6 +841,14 @@ static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, in
         uint64_t store[64];
         void* ptrs[64];
         if (na > 64) return set_error(KF_ERR_INTERNAL, "too many kernel arguments");
+        int64_t grid = l.grid;
+        if (l.dyn_grid) {
+            const int64_t S = (p->rt_n + l.dyn_c - 1) / l.dyn_c, NB = (p->rt_m + l.dyn_r - 1) / l.dyn_r;
+            const int64_t NP = (p->rt_n + 3) / 4 * 4;
+            grid = l.dyn_grid == 1 ? S * NB
+                                   : (l.dyn_rpart ? (p->rt_m + l.dyn_fwb - 1) / l.dyn_fwb : 0) +
+                                         (l.dyn_cpart ? (NP / 4 + 63) / 64 : 0);
+        }
         for (size_t i = 0; i < na; ++i) {
             const KArg& a = l.args[i];
             store[i] = 0;
@@ -774,16 +858,22 @@ static kf_status launch_kernel(kf_plan* p, PlanKernel& k, hipStream_t stream, in
                     std::memcpy(&store[i], &f, 4);
                     break;
                 }
-                case ArgKind::Workspace: store[i] = (uint64_t)(uintptr_t)((char*)p->ws + k.ws_off); break;
+                case ArgKind::Workspace: store[i] = (uint64_t)(uintptr_t)((char*)ws + k.ws_off); break;
+                case ArgKind::ShapeM: store[i] = (uint64_t)p->rt_m; break;
+                case ArgKind::ShapeN: store[i] = (uint64_t)p->rt_n; break;
+                case ArgKind::MatLd:   // an intermediate in the workspace keeps its declared pitch
+                    store[i] = (uint64_t)(p->inter_off[a.value] != SIZE_MAX ? p->s.values[a.value].ld : p->rt_ld[a.value]);
+                    break;
                 default: {
-                    void* q = value_ptr(p, a.value);
+                    void* q = value_ptr(p, a.value, ws);
                     if (!q) return set_error(KF_ERR_UNBOUND, "value " + std::to_string(a.value) + " is not bound");
                     store[i] = (uint64_t)(uintptr_t)q;
                 }
             }
             ptrs[i] = &store[i];
         }
-        hipError_t e = hipModuleLaunchKernel((hipFunction_t)k.fns[li], (unsigned)l.grid, 1, 1, (unsigned)l.block, 1, 1, 0,
+        if (grid <= 0) continue;
+        hipError_t e = hipModuleLaunchKernel((hipFunction_t)k.fns[li], (unsigned)grid, 1, 1, (unsigned)l.block, 1, 1, 0,
                                              stream, ptrs, nullptr);
         if (e != hipSuccess) return set_error(KF_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
     }
@@ -799,7 +889,27 @@ static kf_status check_runnable(const kf_plan* p) {
 
 kf_status kf_run(kf_plan* p, void* stream) {
     CHECK(check_runnable(p));
-    for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream));
+    for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream, p->ws));
+    return KF_OK;
+}
+
+kf_status kf_plan_run_many(kf_plan* p, int64_t count, const int64_t* shapes, int32_t nvals, const kf_value* values,
+                           void* const* ptrs, const int64_t* lds, void* stream) {
+    if (!p || count < 0 || nvals < 0 || (count > 0 && (!shapes || (nvals > 0 && (!values || !ptrs)))))
+        return set_error(KF_ERR_ARG, "bad argument");
+    CHECK(check_runnable(p));
+    for (int64_t i = 0; i < count; ++i) {
+        CHECK(kf_plan_set_shape(p, shapes[2 * i], shapes[2 * i + 1]));
+        for (int32_t j = 0; j < nvals; ++j) {
+            const kf_value v = values[j];
+            void* ptr = ptrs[i * nvals + j];
+            if (v >= 0 && v < (kf_value)p->s.values.size() && p->s.values[v].kind == VK::Mat)
+                CHECK(kf_bind_matrix(p, v, ptr, lds ? lds[i * nvals + j] : p->s.values[v].ld));
+            else
+                CHECK(bind_checked(p, v, ptr));
+        }
+        for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream, p->ws));
+    }
     return KF_OK;
 }
 
@@ -814,13 +924,13 @@ kf_status kf_run_launch(kf_plan* p, int32_t k, int32_t l, void* stream) {
     CHECK(check_runnable(p));
     if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
     if (l < 0 || l >= (int32_t)p->ks[k].code.launches.size()) return set_error(KF_ERR_ARG, "launch index out of range");
-    return launch_kernel(p, p->ks[k], (hipStream_t)stream, l, l + 1);
+    return launch_kernel(p, p->ks[k], (hipStream_t)stream, p->ws, l, l + 1);
 }
 
 kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream) {
     CHECK(check_runnable(p));
     if (k < 0 || k >= (int32_t)p->ks.size()) return set_error(KF_ERR_ARG, "kernel index out of range");
-    return launch_kernel(p, p->ks[k], (hipStream_t)stream);
+    return launch_kernel(p, p->ks[k], (hipStream_t)stream, p->ws);
 }
 
 kf_status kf_time_plan(kf_plan* p, void* stream, int32_t warmup, int32_t reps, float* median_us) {
@@ -871,7 +981,7 @@ kf_status kf_time_plan_kernels(kf_plan* p, void* stream, int32_t warmup, int32_t
         for (size_t k = 0; k < nk && st_out == KF_OK; ++k) {
             const size_t at = ((size_t)i * nk + k) * 2;
             if (hipEventRecord(ev[at], st) != hipSuccess) { st_out = set_error(KF_ERR_HIP, "hipEventRecord"); break; }
-            st_out = launch_kernel(p, p->ks[k], st);
+            st_out = launch_kernel(p, p->ks[k], st, p->ws);
             if (st_out == KF_OK && hipEventRecord(ev[at + 1], st) != hipSuccess) st_out = set_error(KF_ERR_HIP, "hipEventRecord");
         }
     std::vector<std::vector<float>> t(nk);

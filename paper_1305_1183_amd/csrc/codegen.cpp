@@ -249,13 +249,28 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
     for (auto& a : kc_scalar_args) mainl.args.push_back(a);
     mainl.args.push_back({ArgKind::Workspace, -1});
     sig.push_back("float* __restrict__ ws");
+    if (p.dyn) {
+        // runtime shape: rows, cols and each matrix's leading dimension are arguments
+        mainl.args.push_back({ArgKind::ShapeM, -1});
+        mainl.args.push_back({ArgKind::ShapeN, -1});
+        sig.push_back("long M_");
+        sig.push_back("long N_");
+        for (int v : mat_in) { mainl.args.push_back({ArgKind::MatLd, v}); sig.push_back(F("long LD%d", v)); }
+        for (int v : mat_out) { mainl.args.push_back({ArgKind::MatLd, v}); sig.push_back(F("long LD%d", v)); }
+    }
 
     // ---- body
     Emitter e;
-    e.l(F("constexpr long M = %ldL, N = %ldL, C = %ldL, S = %ldL, NB = %ldL, NP = %ldL;", M, N, C, S, NB, NP));
     e.l(F("constexpr int K = %d, W = %d, G = %d, LG = %d, R = %d, NT = %d, E = %d, EG = %d;", K, W, G, LG, R, NT, E, EG));
-    for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
-    for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    if (p.dyn) {
+        e.l(F("constexpr long C = %ldL;", C));
+        e.l("const long M = M_, N = N_, S = (N + C - 1) / C, NB = (M + R - 1) / R, NP = (N + 3) / 4 * 4;");
+        e.l("(void)NB; (void)NP;");
+    } else {
+        e.l(F("constexpr long M = %ldL, N = %ldL, C = %ldL, S = %ldL, NB = %ldL, NP = %ldL;", M, N, C, S, NB, NP));
+        for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+        for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
+    }
     e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
     e.l("const long sidx = blockIdx.x % S, rb = blockIdx.x / S;");
     e.l("const long c0 = sidx * C, r0 = rb * R;");
@@ -506,7 +521,18 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         const long RBK = row_part ? (M + FWb - 1) / FWb : 0;
         const long CBK = col_part ? (NP / 4 + 63) / 64 : 0;
         const int FW = NB >= 64 ? 16 : 4;   // waves of the finishing pass that split the row blocks
-        f.l(F("constexpr long M = %ldL, N = %ldL, S = %ldL, NB = %ldL, NP = %ldL, RBK = %ldL;", M, N, S, NB, NP, RBK));
+        if (p.dyn) {
+            finl.args.push_back({ArgKind::ShapeM, -1});
+            finl.args.push_back({ArgKind::ShapeN, -1});
+            fsig.push_back("long M_");
+            fsig.push_back("long N_");
+            f.l(F("constexpr long C = %ldL, R = %dL, FWB = %dL;", C, R, FWb));
+            f.l("const long M = M_, N = N_, S = (N + C - 1) / C, NB = (M + R - 1) / R, NP = (N + 3) / 4 * 4;");
+            f.l(row_part ? "const long RBK = (M + FWB - 1) / FWB;" : "const long RBK = 0;");
+            f.l("(void)S; (void)NB; (void)NP; (void)RBK;");
+        } else {
+            f.l(F("constexpr long M = %ldL, N = %ldL, S = %ldL, NB = %ldL, NP = %ldL, RBK = %ldL;", M, N, S, NB, NP, RBK));
+        }
         f.l(F("constexpr int FW = %d; (void)FW;", FW));
         for (int v : scalars) {
             if (s.values[v].kind == VK::Const) f.l(F("const float %s = P%d;", scal_name(v).c_str(), v));
@@ -518,6 +544,7 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             f.l("const long row = (long)blockIdx.x * blockDim.x + threadIdx.x;");
             f.l("if (row < M) {");
             f.ind++;
+            // the S strip partials of a row, compensated, in strip order
             for (int c : gemv_calls) {
                 f.l(F("kf_cs cs%d = kf_cs_init(ws[%zuL + row]);", c, ws_off[c]));
                 f.l(F("for (long si = 1; si < S; ++si) cs%d = kf_cs_add(cs%d, ws[%zuL + si * M + row]);", c, c, ws_off[c]));
@@ -546,7 +573,6 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
             // all of it compensated.
             f.l("if (blockIdx.x >= RBK) {");
             f.ind++;
-            // the S strip partials of a row, compensated, in strip order
             f.l("const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;");
             f.l("const long cc = 4L * ((long)(blockIdx.x - RBK) * 64 + lane);");
             emit_colpart_finish(f, gemtv_calls, ws_off);
@@ -571,19 +597,33 @@ static KernelCode gen_mat(const Script& s, const std::vector<int>& calls,
         }
         finl.grid = (int)(RBK + CBK);
         finl.block = col_part ? 64 * FW : 256;
+        if (p.dyn) {
+            finl.dyn_grid = 2;
+            finl.dyn_c = C;
+            finl.dyn_r = R;
+            finl.dyn_fwb = FWb;
+            finl.dyn_rpart = row_part;
+            finl.dyn_cpart = col_part;
+        }
     }
     // the main pass no longer stores outputs that the finishing launch writes
     std::ostringstream head;
     std::string sigs, fsigs;
     for (size_t i = 0; i < sig.size(); ++i) sigs += (i ? ",\n    " : "    ") + sig[i];
     for (size_t i = 0; i < fsig.size(); ++i) fsigs += (i ? ",\n    " : "    ") + fsig[i];
-    std::string key = F("mat K%d W%d G%d R%d E%d M%ld N%ld|", K, W, G, R, E, M, N) + sigs + e.o.str() + fsigs + f.o.str();
+    std::string key = F("mat K%d W%d G%d R%d E%d M%ld N%ld%s|", K, W, G, R, E, M, N, p.dyn ? " dyn" : "") + sigs +
+                      e.o.str() + fsigs + f.o.str();
     kc.name = F("kf_mat_%016llx", (unsigned long long)fnv1a(key));
     head << "extern \"C\" __global__ void __launch_bounds__(" << NT << ") " << kc.name << "(\n"
          << sigs << ") {\n" << e.o.str() << "}\n";
     mainl.name = kc.name;
     mainl.grid = (int)(S * NB);
     mainl.block = NT;
+    if (p.dyn) {
+        mainl.dyn_grid = 1;
+        mainl.dyn_c = C;
+        mainl.dyn_r = R;
+    }
     kc.launches.push_back(mainl);
     if (row_part || col_part) {
         finl.name = kc.name + "_fin";
@@ -1165,8 +1205,13 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
         if (q.sched != 1) q.waves = q.group = q.rows = 0;   // strip-schedule parameters do not carry over
         kc = gen_mat_rowres(s, calls, part, q);
     } else {
-        kc = sp.mat ? gen_mat(s, calls, part, default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(s, calls, mp.unit)))
-                    : gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+        if (sp.mat) {
+            MatParams q = default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(s, calls, mp.unit));
+            q.dyn = mp.dyn;
+            kc = gen_mat(s, calls, part, q);
+        } else {
+            kc = gen_vec(s, calls, part, default_vec_params(sp.a, vp));
+        }
     }
     for (Launch& l : kc.launches) launch_bytes(s, &l);
     return kc;

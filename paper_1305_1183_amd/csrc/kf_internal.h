@@ -77,7 +77,9 @@ std::vector<int> unfused_partition(const Script& s);
 std::vector<std::vector<int>> kernels_in_order(const Script& s, const std::vector<int>& part);
 
 // ---- implementation parameters ---------------------------------------------
-struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0, unit = 0; };  // sched 1 = row-resident
+// sched 1 = row-resident; dyn: rows, cols and leading dimensions are kernel
+// arguments (a plan compiled with KF_COMPILE_RUNTIME_SHAPE), not constants
+struct MatParams { int k = 0, waves = 0, group = 0, rows = 0, sched = 0, unit = 0; bool dyn = false; };
 struct VecParams { int unroll = 0, threads = 0, grid = 0; };
 // e_per_unit: matrix elements per 16-byte load unit of the kernel (4 for FP32,
 // 8 with a BF16 matrix, 16 with an FP8 matrix).
@@ -91,7 +93,8 @@ VecParams default_vec_params(int64_t n, const VecParams& req);
 
 // ---- code generation (codegen.cpp) --------------------------------------------
 enum class ArgKind : int {
-    MatIn, MatOut, VecIn, VecOut, ConstScalar, DevScalarIn, DevScalarOut, Workspace
+    MatIn, MatOut, VecIn, VecOut, ConstScalar, DevScalarIn, DevScalarOut, Workspace,
+    ShapeM, ShapeN, MatLd      // runtime-shape plans: rows, cols, leading dimension of matrix `value`
 };
 struct KArg { ArgKind kind; int value; };   // value id (or -1 for the workspace)
 
@@ -102,6 +105,12 @@ struct Launch {
     std::vector<KArg> args;        // launch argument order
     int grid = 0, block = 0;
     uint64_t bytes_read = 0, bytes_written = 0;   // algorithmic HBM bytes of this launch
+    // Runtime-shape plans compute the grid from the shape of each run:
+    // dyn_grid 1 = strips x row blocks (S NB), 2 = finishing launch (row blocks
+    // of rows plus column groups of 64 float4).
+    int dyn_grid = 0;
+    long dyn_c = 0, dyn_r = 0, dyn_fwb = 0;
+    bool dyn_rpart = false, dyn_cpart = false;
 };
 
 struct KernelCode {
@@ -184,6 +193,11 @@ struct kf_plan {
     size_t ws_need = 0;
     bool loaded = false;
     int mode = 0;
+    // KF_COMPILE_RUNTIME_SHAPE: every matrix has the declared storage shape
+    // decl_m x decl_n; runs use rt_m x rt_n (<= declared) and per-matrix rt_ld
+    bool dyn = false;
+    int64_t decl_m = 0, decl_n = 0, rt_m = 0, rt_n = 0;
+    std::vector<int64_t> rt_ld;
 };
 
 // Opaque C handles.

@@ -30,6 +30,7 @@ KF_NONE = -1
 MODES = {"unfused": 0, "fused": 1, "additive": 2, "learned": 3, "exhaustive": 4, "partition": 5}
 KF_COMPILE_NO_LOAD = 1
 KF_COMPILE_CODEGEN_ONLY = 2
+KF_COMPILE_RUNTIME_SHAPE = 4
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -108,6 +109,9 @@ _SIGS = {
     "kf_script_call": ([_vp, _i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32)], _i32),
     "kf_compile_opts_init": ([_P(kf_compile_opts)], None),
     "kf_compile_workspace_bytes": ([_vp, _P(kf_compile_opts), _P(_sz)], _i32),
+    "kf_plan_set_shape": ([_vp, _i64, _i64], _i32),
+    "kf_bind_matrix": ([_vp, _i32, _vp, _i64], _i32),
+    "kf_plan_run_many": ([_vp, _i64, _P(_i64), _i32, _P(_i32), _P(_vp), _P(_i64), _vp], _i32),
     "kf_compile": ([_vp, _P(kf_compile_opts), _P(_vp)], _i32),
     "kf_plan_destroy": ([_vp], None),
     "kf_enumerate": ([_vp, _i32, _P(_vp)], _i32),
@@ -516,6 +520,30 @@ def kf_plan_workspace_bytes(p) -> int:
 
 def kf_bind(p, v: int, dev_ptr: int) -> None:
     _chk(lib().kf_bind(p, v, _vp(dev_ptr)))
+
+
+def kf_plan_set_shape(p, rows: int, cols: int) -> None:
+    _chk(lib().kf_plan_set_shape(p, rows, cols))
+
+
+def kf_bind_matrix(p, v: int, dev_ptr: int, ld: int) -> None:
+    _chk(lib().kf_bind_matrix(p, v, _vp(dev_ptr), ld))
+
+
+def kf_plan_run_many(p, shapes, values, ptrs, lds=None, stream: int = 0) -> None:
+    """shapes: (count, 2) int64; values: nvals value handles; ptrs: (count,
+    nvals) device pointers; lds: (count, nvals) leading dimensions or None."""
+    import numpy as np
+    shapes = np.ascontiguousarray(shapes, dtype=np.int64)
+    vals = np.ascontiguousarray(values, dtype=np.int32)
+    ptrs = np.ascontiguousarray(ptrs, dtype=np.uint64)
+    count = shapes.shape[0]
+    lp = None
+    if lds is not None:
+        lds = np.ascontiguousarray(lds, dtype=np.int64)
+        lp = lds.ctypes.data_as(_P(_i64))
+    _chk(lib().kf_plan_run_many(p, count, shapes.ctypes.data_as(_P(_i64)), len(vals), vals.ctypes.data_as(_P(_i32)),
+                                ptrs.ctypes.data_as(_P(_vp)), lp, _vp(stream)))
 
 
 def kf_bind_workspace(p, dev_ptr: int, nbytes: int) -> None:

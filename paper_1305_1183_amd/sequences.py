@@ -135,6 +135,16 @@ def _mat(q, name, rows, cols, ld=0, layout=kf.KF_ROW_MAJOR):
     return v
 
 
+def _dscalar(q, name):
+    """Input scalar in device memory (bound like a one-entry vector)."""
+    v = kf.kf_scalar(q.script)
+    kf.kf_input(q.script, v)
+    q.values[name] = v
+    q.inputs.append(name)
+    q.shapes[name] = (1,)
+    return v
+
+
 def _const(q, name, value):
     v = kf.kf_const(q.script, float(value))
     q.consts[name] = (v, float(value))
@@ -217,6 +227,26 @@ def gemver(m: int, n: int, alpha: float, beta: float, ld: int = 0,
     u2, v2 = _vec(q, "u2", m), _vec(q, "v2", n)
     y, z = _vec(q, "y", m), _vec(q, "z", n)
     a, b, one = _const(q, "alpha", alpha), _const(q, "beta", beta), _const(q, "one", 1.0)
+    B1 = kf.kf_ger(q.script, one, A, u1, v1)
+    B = kf.kf_ger(q.script, one, B1, u2, v2)
+    x = kf.kf_gemtv(q.script, b, B, y, one, z)
+    w = kf.kf_gemv(q.script, a, B, x)
+    _out(q, "B", B)
+    _out(q, "x", x)
+    _out(q, "w", w)
+    return q
+
+
+def gemver_dev(m: int, n: int) -> Sequence:
+    """GEMVER with alpha and beta in device memory (inputs "alpha", "beta"), so
+    that one plan serves instances with their own scalars."""
+    q = _seq("gemver")
+    A = _mat(q, "A", m, n)
+    u1, v1 = _vec(q, "u1", m), _vec(q, "v1", n)
+    u2, v2 = _vec(q, "u2", m), _vec(q, "v2", n)
+    y, z = _vec(q, "y", m), _vec(q, "z", n)
+    a, b = _dscalar(q, "alpha"), _dscalar(q, "beta")
+    one = _const(q, "one", 1.0)
     B1 = kf.kf_ger(q.script, one, A, u1, v1)
     B = kf.kf_ger(q.script, one, B1, u2, v2)
     x = kf.kf_gemtv(q.script, b, B, y, one, z)
