@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--only", default="", help="comma-separated subset of sequences (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-unfused", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="leave out the batched and reduced-precision results of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB streaming copy (memory-counter calibration)")
     ap.add_argument("--tune", action="store_true",
@@ -57,35 +59,83 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads() -> int:
+    """Threads for the all-core oracle run: the CPUs this process may run on,
+    capped by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    return min(n, int(cap)) if cap.isdigit() and int(cap) > 0 else n
+
+
 def cpu_baseline():
-    """The FP64 oracle (plain C, one thread) on the suite's shapes, bounded by
-    the full shapes: BLAS-2 sequences on all `rows` of the 16384 rows, BLAS-1
-    sequences on 2**26 entries. GB/s over the same FP32 algorithmic bytes as
-    the fused GPU plan of the sampled shapes."""
+    """The FP64 oracle (plain C, unfused definitions) on the suite's full
+    shapes, timed on this host: the all-core OpenMP build of the same source
+    (one warm-up, then the median of three passes) and the one-thread build
+    (one pass). GB/s over the FP32 algorithmic bytes of the unfused GPU plans
+    of the same shapes."""
+    import oracle
     from paper_1305_1183_amd import kf
     from paper_1305_1183_amd import sequences as S
     from paper_1305_1183_amd import workloads as WL
     from tests import seqcheck as SC  # the oracle: CPU-baseline leg only
 
-    n, rows, vec = WL.SUITE_N, WL.SUITE_N, 1 << 26
-    total_bytes, total_s = 0, 0.0
+    n, vec = WL.SUITE_N, WL.SUITE_VEC
+    want = oracle_threads()
+    total_bytes, t_one, t_all, used = 0, 0.0, 0.0, 1
+    per = {}
     for name in WL.ORDER:
-        m, nn = (vec, vec) if name in WL.BLAS1 else (rows, n)
+        m, nn = (vec, vec) if name in WL.BLAS1 else (n, n)
         arrays, scal = WL.make(name, m, nn, seed=WL.seed_for(2, name))
         q = S.by_name(name, m, nn, scal)
-        p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+        p = kf.kf_compile(q.script, mode="unfused", flags=kf.KF_COMPILE_NO_LOAD)
         r, w = kf.kf_plan_bytes(p)
         kf.kf_plan_destroy(p)
         t0 = time.perf_counter()
         SC.oracle_outputs(name, arrays, scal, nn)
-        dt = time.perf_counter() - t0
+        one = time.perf_counter() - t0
+        with oracle.all_cores(want) as used:
+            times = []
+            for rep in range(4):
+                t0 = time.perf_counter()
+                SC.oracle_outputs(name, arrays, scal, nn)
+                if rep:
+                    times.append(time.perf_counter() - t0)
+        allc = float(np.median(times))
+        del arrays
         total_bytes += r + w
-        total_s += dt
-        log("cpu oracle %-8s %.2f s" % (name, dt))
-    return {"value": round(total_bytes / total_s / 1e9, 3), "unit": "GB/s", "cores": 1,
+        t_one += one
+        t_all += allc
+        per[name] = {"one_thread_s": round(one, 3), "all_cores_s": round(allc, 3), "unfused_bytes": r + w}
+        log("cpu oracle %-8s one thread %.2f s, %d threads %.2f s" % (name, one, used, allc))
+    return {"value": round(total_bytes / t_all / 1e9, 3), "unit": "GB/s", "cores": used,
             "kind": "oracle",
-            "sample": "FP64 oracle, one thread: BiCGK/ATAX/GESUMMV/GEMVER on %d x %d (row sample), "
-                      "AXPYDOT/WAXPBY on 2^26 entries; %.1f s total" % (rows, n, total_s)}
+            "sample": "FP64 oracle (unfused definitions) on the full suite shapes: BiCGK/ATAX/GESUMMV/GEMVER "
+                      "on %d x %d, AXPYDOT/WAXPBY on 2^26 entries; OpenMP build on %d threads, median of 3 "
+                      "passes after one warm-up, %.1f s per pass; GB/s over the unfused GPU plans' FP32 "
+                      "algorithmic bytes" % (n, n, used, t_all),
+            "single_thread": {"value": round(total_bytes / t_one / 1e9, 3), "unit": "GB/s", "cores": 1,
+                              "seconds": round(t_one, 2)},
+            "cpu_model": cpu_model(), "affinity_cpus": len(os.sched_getaffinity(0)),
+            "bytes": total_bytes, "per_sequence": per}
 
 
 def precision_suite(args, torch, kf, S, WL, dev):
@@ -209,7 +259,15 @@ def batched_suite(args, torch, kf, WL, dev):
         del bt
         torch.cuda.empty_cache()
     loop = "loop" in res
-    best_loop = min(res["loop"]["us"], res["loop_graph"]["us"]) if loop else None
+    if loop:
+        pl = plan_loop_times(torch, kf, WL, dev, kinds, ns, al, be, reps=max(3, args.steps // 4))
+        r_, w_ = B.Batch(kinds, ns, al, be, WL.batch_opts()).bytes()
+        for key in ("plan_loop", "plan_loop_graph"):
+            res[key] = {"us": pl[key + "_us"], "gbps": round((r_ + w_) / pl[key + "_us"] / 1e3, 1)}
+        res["plan_loop"]["launches"] = pl["plan_loop_launches"]
+        log("batched plan loop: %.1f us, graph %.1f us" % (pl["plan_loop_us"], pl["plan_loop_graph_us"]))
+    best_loop = min(res["loop"]["us"], res["loop_graph"]["us"], res["plan_loop"]["us"],
+                    res["plan_loop_graph"]["us"]) if loop else None
     ach = res["persistent"]["gbps"]
     print(json.dumps({"metric": "batched uneven sizes: GB/s and speedup of one persistent launch vs per-instance "
                                 "launches (not the headline)",
@@ -224,6 +282,140 @@ def batched_suite(args, torch, kf, WL, dev):
                       "bytes": r + w, "results": res,
                       "config": {"workload": "%d BiCGK + %d GEMVER, n log-uniform on [32, 2048], FP32 uniform[-1,1)"
                                              % WL.BATCH_COUNTS}}), flush=True)
+
+
+def batched_compact(args, torch, kf, WL, dev):
+    """Batched uneven sizes (4096 BiCGK + 4096 GEMVER, n log-uniform on
+    [32, 2048]) on the benchmark's clock: the persistent launch, its graph
+    replay, and the loop of per-instance launches (graph-captured too)."""
+    from paper_1305_1183_amd import batched as B
+    kinds, ns, al, be = B.make_instances(*WL.BATCH_COUNTS, seed=WL.BATCH_SEED)
+    out = {}
+    for which, name in ((0, "persistent"), (1, "loop")):
+        bt = B.Batch(kinds, ns, al, be, WL.batch_opts(loop=which == 1))
+        bt.fill_device(seed=WL.BATCH_SEED)
+        r, w = bt.bytes()
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            reps = 5 if which == 0 else 2
+            us = kf.kf_batch_time(bt.h, which, False, st.cuda_stream, 1, reps)
+            kf.kf_batch_capture(bt.h, which, st.cuda_stream)
+            ug = kf.kf_batch_time(bt.h, which, True, st.cuda_stream, 1, reps)
+            err = kf.kf_batch_error(bt.h, st.cuda_stream)
+        if err:
+            raise RuntimeError("batched launch reported error bits %d" % err)
+        out[name + "_us"] = round(us, 1)
+        out[name + "_graph_us"] = round(ug, 1)
+        out["bytes"] = r + w
+        del bt
+        torch.cuda.empty_cache()
+    out.update(plan_loop_times(torch, kf, WL, dev, kinds, ns, al, be, reps=2))
+    best = min(out["persistent_us"], out["persistent_graph_us"])
+    out["gbps"] = round(out["bytes"] / best / 1e3, 1)
+    out["pct_peak"] = round(out["bytes"] / best / 1e3 / HBM_PEAK_GBPS * 100, 1)
+    best_loop = min(out["loop_us"], out["loop_graph_us"], out["plan_loop_us"], out["plan_loop_graph_us"])
+    out["speedup_vs_best_loop"] = round(best_loop / best, 2)
+    out["what"] = ("%d BiCGK + %d GEMVER, n log-uniform on [32, 2048], one persistent launch vs per-instance "
+                   "launches: the library's fused plans (one runtime-shape plan per kind and size bucket) and the "
+                   "batch kernel, each plain and graph-captured" % WL.BATCH_COUNTS)
+    log("batched: persistent %.1f us (graph %.1f), kernel loop %.1f us, plan loop %.1f us (graph %.1f)" %
+        (out["persistent_us"], out["persistent_graph_us"], out["loop_us"], out["plan_loop_us"],
+         out["plan_loop_graph_us"]))
+    return out
+
+
+def plan_loop_times(torch, kf, WL, dev, kinds, ns, al, be, reps=3):
+    """The per-instance loop of the library's own fused plans over the batch's
+    instances (B.PlanLoop), timed plain and as a graph replay."""
+    from paper_1305_1183_amd import batched as B
+    bt = B.Batch(kinds, ns, al, be, WL.batch_opts())
+    bt.fill_device(seed=WL.BATCH_SEED)
+    loop = B.PlanLoop(bt)
+    st = torch.cuda.Stream()
+    res = {"plan_loop_launches": loop.launches()}
+    with torch.cuda.stream(st):
+        loop.run(st.cuda_stream)          # warm-up (and module loads)
+        st.synchronize()
+
+        def timed(fn):
+            ts = []
+            for _ in range(reps):
+                a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a_.record(st)
+                fn()
+                b_.record(st)
+                st.synchronize()
+                ts.append(a_.elapsed_time(b_) * 1e3)
+            return float(np.median(ts))
+        res["plan_loop_us"] = round(timed(lambda: loop.run(st.cuda_stream)), 1)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            loop.run(st.cuda_stream)
+        g.replay()
+        st.synchronize()
+        res["plan_loop_graph_us"] = round(timed(g.replay), 1)
+    del g, loop, bt
+    torch.cuda.empty_cache()
+    return res
+
+
+def precision_compact(args, torch, kf, S, WL, dev):
+    """Reduced-precision A at n = 32768 on the benchmark's clock: fused BiCGK
+    and GEMVER per storage format (FP32, BF16, FP8-E4M3 with row scales),
+    time, GB/s and the relative L2 error of sampled outputs against the FP64
+    oracle on the float64 A and on the dequantised A."""
+    import oracle
+    from oracle import quant as OQ
+    from paper_1305_1183_amd import inputs as I
+    n = WL.PREC_N
+    rows = np.unique(np.concatenate([[0, n - 1], I.small_ints(7, 0, 24, 0, n - 1).astype(np.int64)]))
+    cols = np.unique(np.concatenate([[0, n - 1], I.small_ints(7, 1, 24, 0, n - 1).astype(np.int64)]))
+    e4m3 = OQ.decode_e4m3(np.arange(256, dtype=np.uint8))
+    res = {}
+    for name in WL.PREC_SEQ:
+        keep = {"rows": rows, "cols": cols}
+        stored, vecs, scal = WL.precision_inputs(name, n, WL.PREC_FORMATS, seed=4000 + WL.SEQ_INDEX[name], keep=keep)
+        f = {k: v.astype(np.float64) for k, v in vecs.items()}
+        for fmt in WL.PREC_FORMATS:
+            st_, sc_ = stored[fmt]
+            dec = {"f32": lambda a: a.astype(np.float64), "bf16": OQ.decode_bf16, "fp8": lambda a: e4m3[a]}[fmt]
+            Dr = dec(st_[rows, :n]) * sc_[rows].astype(np.float64)[:, None]
+            Dc = dec(st_[:, cols]) * sc_.astype(np.float64)[:, None]
+            devin = {}
+            for k, v in WL.precision_arrays(fmt, stored, vecs).items():
+                devin[k] = torch.from_numpy(np.ascontiguousarray(v.view(np.int16) if v.dtype == np.uint16 else v)).to(dev)
+            if name == "bicgk":
+                q = S.bicgk_q(n, n, fmt)
+            else:
+                q = S.gemver_q(n, n, scal["alpha"], scal["beta"], fmt)
+            prog = q.compile(mode="fused", **WL.PREC_TUNED.get((name, fmt), {})).bind(device=dev, **devin)
+            outs = prog.run()
+            torch.cuda.synchronize()
+            r, w = prog.bytes()
+            us = prog.time(3, 10)
+            row = {"us": round(us, 1), "gbps": round((r + w) / us / 1e3, 1),
+                   "pct_peak": round((r + w) / us / 1e3 / HBM_PEAK_GBPS * 100, 1)}
+            if name == "bicgk":
+                qg, sg = outs["q"].cpu().numpy(), outs["s"].cpu().numpy()
+                for key, got, deq, a64 in (("q", qg[rows], oracle.gemv(1.0, Dr, f["p"]), oracle.gemv(1.0, keep["A64_rows"], f["p"])),
+                                           ("s", sg[cols], oracle.gemtv(1.0, Dc, f["r"]), oracle.gemtv(1.0, keep["A64_cols"], f["r"]))):
+                    row["err_" + key] = {"vs_dequantised": float("%.3g" % WL.rel_l2(got, deq)),
+                                         "vs_fp64_A": float("%.3g" % WL.rel_l2(got, a64))}
+            else:
+                xg = outs["x"].cpu().numpy()[cols]
+                a, b = scal["alpha"], scal["beta"]
+                for key, A_ in (("vs_dequantised", Dc), ("vs_fp64_A", keep["A64_cols"])):
+                    Bc = oracle.ger(1.0, oracle.ger(1.0, A_, f["u1"], f["v1"][cols]), f["u2"], f["v2"][cols])
+                    row.setdefault("err_x", {})[key] = float("%.3g" % WL.rel_l2(xg, oracle.gemtv(b, Bc, f["y"], 1.0, f["z"][cols])))
+            res["%s/%s" % (name, fmt)] = row
+            log("precision %s %s: %.1f us, %.1f GB/s" % (name, fmt, us, row["gbps"]))
+            del prog, devin, outs
+            torch.cuda.empty_cache()
+        del stored
+    res["what"] = ("n = %d, A drawn N(0, 1) in float64 and stored per format with one FP32 scale per row; fused plans "
+                   "with their tuned points; errors on %d sampled rows / %d columns (GEMVER: x on the columns)"
+                   % (n, len(rows), len(cols)))
+    return res
 
 
 def main():
@@ -390,6 +582,13 @@ def main():
                 "kernel": "%s kernel %d launch %d (%s) %s" % (dk["seq"], dk["k"], dk["l"], "+".join(dk["calls"]), dk["name"]),
                 "avg_us": round(dom_us, 2), "bytes_per_launch": dk["bytes"],
                 "timing": "HIP events on the launch stream around this launch, mean over the timed steps"}
+    # the same kernel in the committed rocprofv3 --kernel-trace --stats summary
+    # of this command (None when the summary does not cover this kernel text)
+    prof = WL.kernel_stats_from_profiles(os.path.join(ROOT, "profiles"), WL.SUITE_STATS_FILE, dk["name"])
+    if prof is not None:
+        prof["frac"] = round(dk["bytes"] / (prof["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4)
+        prof["event_vs_profile"] = round(dom_us / prof["avg_us"], 4)
+    roofline["profile"] = prof
 
     # attainable-bandwidth references on this device, 1 GiB each, measured
     # right after the timed steps (same device state): the library's streaming
@@ -451,6 +650,10 @@ def main():
                                         for k, a in zip(kernels, avg_k)}}
     if stream_ref is not None:
         out["stream_reference"] = stream_ref
+    if not args.only and not args.no_extra_configs:
+        # the batched and reduced-precision configurations, on the same clock
+        out["batched"] = batched_compact(args, torch, kf, WL, dev)
+        out["precision"] = precision_compact(args, torch, kf, S, WL, dev)
     if not args.no_cpu_baseline and not args.only:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -8,6 +8,7 @@ arrays into it. ``mlp.py`` holds the FP64 reference of the learned cost model.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -16,8 +17,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
+OMP_LIB_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _SRC = os.path.join(_HERE, "kf_oracle.c")
 _lib = None
+_omp_lib = None
 
 _D = ctypes.POINTER(ctypes.c_double)
 _F = ctypes.POINTER(ctypes.c_float)
@@ -26,13 +29,19 @@ _i64 = ctypes.c_int64
 _dbl = ctypes.c_double
 
 
+def _gcc(out: str, extra) -> None:
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-fno-fast-math"] + list(extra) + ["-o", tmp, _SRC])
+    os.replace(tmp, out)
+
+
 def build(force: bool = False) -> str:
-    """Compile kf_oracle.c with gcc (strict IEEE double, no contraction)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC])
-        os.replace(tmp, LIB_PATH)
+    """Compile kf_oracle.c with gcc (strict IEEE double, no contraction): the
+    one-thread library and the all-core OpenMP build of the same source."""
+    for out, extra in ((LIB_PATH, []), (OMP_LIB_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            _gcc(out, extra)
     return LIB_PATH
 
 
@@ -61,6 +70,10 @@ def load(path: str):
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = _dbl if name == "kfo_dot" else None
+    L.kfo_threads.argtypes = []
+    L.kfo_threads.restype = ctypes.c_int
+    L.kfo_set_threads.argtypes = [ctypes.c_int]
+    L.kfo_set_threads.restype = None
     return L
 
 
@@ -71,6 +84,33 @@ def lib():
             build()
         _lib = load(LIB_PATH)
     return _lib
+
+
+def omp_lib():
+    """The all-core (OpenMP) build of the same source."""
+    global _omp_lib
+    if _omp_lib is None:
+        if not os.path.exists(OMP_LIB_PATH):
+            build()
+        _omp_lib = load(OMP_LIB_PATH)
+    return _omp_lib
+
+
+@contextlib.contextmanager
+def all_cores(threads: int):
+    """Inside the block every oracle function runs on the OpenMP build with
+    `threads` threads (bit-identical results: each output entry is still
+    summed by one thread in the plain order). Yields the thread count the
+    library reports."""
+    global _lib
+    saved = lib()
+    L = omp_lib()
+    L.kfo_set_threads(int(threads))
+    _lib = L
+    try:
+        yield L.kfo_threads()
+    finally:
+        _lib = saved
 
 
 def _f(a):

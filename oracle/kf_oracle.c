@@ -6,27 +6,62 @@
  * 3.3, equations (1) and (2)). The six sequences are those of Table 1, each
  * written as the composition of the elementary calls, with every intermediate
  * kept in double. Nothing here is blocked, fused or reordered.
+ *
+ * The same source compiled with OpenMP is the all-core build used to time the
+ * oracle on the host's cores: the outer loop of each map (over entries, over
+ * rows, and for GEMTV over columns) is split among threads, but every output
+ * entry is still computed by one thread in the order written here, so the
+ * results are bit-identical to the one-thread build. DOT, a single sum, stays
+ * serial.
  */
 #include "kf_oracle.h"
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#define KFO_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define KFO_PARALLEL_FOR
+#endif
+
+/* Threads of the all-core build (1 in the one-thread build). */
+int kfo_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void kfo_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void kfo_f2d(int64_t n, const float* src, double* dst) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) dst[i] = (double)src[i];
 }
 
 void kfo_mat_f2d(int64_t m, int64_t n, int64_t ld, const float* a, double* dst) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < n; ++j) dst[i * n + j] = (double)a[i * ld + j];
 }
 
 /* SCAL: map of x -> alpha x (Section 3.3, BLAS-1 as map). */
 void kfo_scal(int64_t n, double alpha, const double* x, double* y) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) y[i] = alpha * x[i];
 }
 
 /* AXPY: map of (x, y) -> alpha x + y. */
 void kfo_axpy(int64_t n, double alpha, const double* x, const double* y, double* z) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < n; ++i) z[i] = alpha * x[i] + y[i];
 }
 
@@ -41,6 +76,7 @@ double kfo_dot(int64_t n, const double* x, const double* y) {
  * reduction over the row (equation (2)). A is m x n, dense row-major. */
 void kfo_gemv(int64_t m, int64_t n, double alpha, const double* a, const double* x,
               double beta, const double* y0, double* y) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < m; ++i) {
         double s = 0.0;
         for (int64_t j = 0; j < n; ++j) s += a[i * n + j] * x[j];
@@ -52,6 +88,7 @@ void kfo_gemv(int64_t m, int64_t n, double alpha, const double* a, const double*
  * viewed as a list of columns (Section 3.3, last paragraph). */
 void kfo_gemtv(int64_t m, int64_t n, double alpha, const double* a, const double* x,
                double beta, const double* y0, double* y) {
+    KFO_PARALLEL_FOR
     for (int64_t j = 0; j < n; ++j) {
         double s = 0.0;
         for (int64_t i = 0; i < m; ++i) s += a[i * n + j] * x[i];
@@ -62,6 +99,7 @@ void kfo_gemtv(int64_t m, int64_t n, double alpha, const double* a, const double
 /* GER: B_ij = A_ij + alpha u_i v_j (the rank-1 update of GEMVER, Table 1). */
 void kfo_ger(int64_t m, int64_t n, double alpha, const double* a, const double* u,
              const double* v, double* b) {
+    KFO_PARALLEL_FOR
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < n; ++j) b[i * n + j] = a[i * n + j] + alpha * u[i] * v[j];
 }

@@ -18,6 +18,12 @@
 extern "C" {
 #endif
 
+/* Threads of the library: 1 in the one-thread build; the OpenMP build (the
+ * same source with -fopenmp, used to time the oracle on all host cores)
+ * reports and sets its thread count. */
+int    kfo_threads(void);
+void   kfo_set_threads(int n);
+
 /* ---- elementary calls on double operands (Section 3.3: BLAS as map/reduce) */
 void   kfo_f2d(int64_t n, const float* src, double* dst);
 void   kfo_mat_f2d(int64_t m, int64_t n, int64_t ld, const float* a, double* dst);

@@ -156,6 +156,29 @@ def traffic_from_profiles(profile_dir: str, kernel_name: str, batched: bool = Fa
     return int(round(k["fetch_bytes_scaled"] + k["write_bytes_scaled"]))
 
 
+# rocprofv3 --kernel-trace --stats summary of the default benchmark command
+SUITE_STATS_FILE = "suite_n16384_fused_kernel_stats.txt"
+
+
+def kernel_stats_from_profiles(profile_dir: str, fname: str, kernel_name: str):
+    """{file, command, calls, avg_us, min_us, max_us} of `kernel_name` in a
+    committed rocprofv3 statistics summary, or None when the summary does not
+    list this exact kernel (the name is a hash of its text)."""
+    import os
+    path = os.path.join(profile_dir, fname)
+    if not os.path.exists(path):
+        return None
+    command = ""
+    for line in open(path):
+        if line.startswith("# command:"):
+            command = line.split(":", 1)[1].strip()
+        f = line.split()
+        if len(f) >= 5 and f[0] == kernel_name:
+            return {"file": "profiles/" + fname, "command": command, "calls": int(f[1]),
+                    "avg_us": float(f[2]), "min_us": float(f[3]), "max_us": float(f[4])}
+    return None
+
+
 # ---- reduced-precision suite: A ~ N(0, 1) drawn in float64, stored per format
 PREC_N = 32768
 PREC_FORMATS = ("f32", "bf16", "fp8")
@@ -198,14 +221,20 @@ def normal_panel(seed: int, n: int, r0: int, panel: int = PREC_PANEL) -> np.ndar
     return rng.standard_normal((min(panel, n - r0), n))
 
 
-def precision_inputs(name: str, n: int, formats, seed: int, panel: int = PREC_PANEL):
+def precision_inputs(name: str, n: int, formats, seed: int, panel: int = PREC_PANEL, keep=None):
     """Operands of BiCGK or GEMVER with A (n x n) drawn N(0, 1) in float64
     (row panels, normal_panel) and stored in each of `formats` with row
     scales; vectors uniform [-1, 1). Returns ({fmt: (storage, scales)},
-    vectors, scalars)."""
+    vectors, scalars). keep = (rows, cols) index arrays: the float64 rows and
+    columns of A at those indices are also kept, in keep["A64_rows"] and
+    keep["A64_cols"] (a dict passed in), without a second draw."""
     from concurrent.futures import ThreadPoolExecutor
     from . import quant as Q
     out = {}
+    if keep is not None:
+        krows, kcols = (np.asarray(keep["rows"], np.int64), np.asarray(keep["cols"], np.int64))
+        keep["A64_rows"] = np.empty((len(krows), n))
+        keep["A64_cols"] = np.empty((n, len(kcols)))
 
     ld = {"f32": (n + 3) // 4 * 4, "bf16": (n + 7) // 8 * 8, "fp8": (n + 15) // 16 * 16}
     dt = {"f32": np.float32, "bf16": np.uint16, "fp8": np.uint8}
@@ -214,6 +243,10 @@ def precision_inputs(name: str, n: int, formats, seed: int, panel: int = PREC_PA
 
     def do_panel(r0):
         A64 = normal_panel(seed, n, r0, panel)
+        if keep is not None:
+            mine = np.flatnonzero((krows >= r0) & (krows < r0 + A64.shape[0]))
+            keep["A64_rows"][mine] = A64[krows[mine] - r0]
+            keep["A64_cols"][r0:r0 + A64.shape[0]] = A64[:, kcols]
         for c0 in range(0, A64.shape[0], 4):          # small row groups stay in cache
             blk = A64[c0:c0 + 4]
             for f in formats:

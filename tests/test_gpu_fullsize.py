@@ -61,6 +61,39 @@ def test_blas1_full(name, mode):
 
 
 @pytest.mark.parametrize("mode", ["fused", "unfused"])
+def test_blas1_full_bitwise_closed_forms(mode):
+    """At 2^26 entries with the benchmark's launch: WAXPBY with alpha = 2 and
+    beta = 0.5 rounds once (2x and y/2 are exact, their sum is one FMA), so it
+    equals the FP64 oracle rounded to FP32 bit for bit; AXPYDOT with w = 2v
+    and alpha = 2 has z = 0 and r = 0 exactly. A single wrong float4 anywhere
+    fails these, which the relative L2 bound at this length cannot see."""
+    print("case blas1 closed forms", V, mode, flush=True)
+    scal = {"alpha": 2.0, "beta": 0.5}
+    arrays, _ = WL.make("waxpby", V, V, seed=WL.seed_for(2, "waxpby"))
+    q = S.by_name("waxpby", V, V, scal)
+    prog = q.compile(mode=mode, **WL.tuned_params("waxpby", V, V, mode))
+    prog.bind(**{k: torch.from_numpy(v).cuda() for k, v in arrays.items()})
+    w = prog.run()["w"].cpu().numpy()
+    ref = oracle.waxpby(2.0, arrays["x"], 0.5, arrays["y"]).astype(np.float32)
+    bad = np.flatnonzero(w != ref)
+    assert bad.size == 0, ("waxpby", bad[:8])
+    del prog
+    arrays, _ = WL.make("axpydot", V, V, seed=WL.seed_for(2, "axpydot"))
+    arrays["w"] = (2.0 * arrays["v"]).astype(np.float32)
+    q = S.by_name("axpydot", V, V, scal)
+    prog = q.compile(mode=mode, **WL.tuned_params("axpydot", V, V, mode))
+    prog.bind(**{k: torch.from_numpy(v).cuda() for k, v in arrays.items()})
+    outs = prog.run()
+    z, r = outs["z"].cpu().numpy(), outs["r"].cpu().numpy()
+    zr, rr = oracle.axpydot(2.0, arrays["w"], arrays["v"], arrays["u"])
+    assert np.all(zr == 0.0) and rr == 0.0
+    bad = np.flatnonzero(z != 0.0)
+    assert bad.size == 0 and r[0] == 0.0, ("axpydot", bad[:8], r)
+    del prog
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("mode", ["fused", "unfused"])
 def test_bicgk_full(mode):
     print("case bicgk", N, mode, flush=True)
     arrays, scal, h = run("bicgk", N, N, mode)
