@@ -105,6 +105,26 @@ kf_status kf_matrix_layout(kf_script* s, int64_t rows, int64_t cols, int64_t ld,
  * entries). ld 0 = cols rounded up to a 16-byte row. */
 kf_status kf_matrix_q(kf_script* s, int64_t rows, int64_t cols, int64_t ld, int32_t dtype,
                       kf_value scale, kf_value* out);
+/* Fill the storage of a quantised matrix from FP32 data on the device (a
+ * caller that holds an FP32 matrix and wants BF16 or FP8-E4M3 storage for
+ * kf_matrix_q). A: rows x cols FP32, element (i, j) at A[i * lda + j]
+ * (lda >= cols). codes: rows x ldq elements of 2 bytes (KF_BF16) or 1 byte
+ * (KF_FP8_E4M3), ldq >= cols with 16-byte rows; columns cols..ldq-1 are set
+ * to code 0. scales: rows floats. Every code is the nearest value, ties to
+ * even, of the exact number it stands for:
+ *   KF_BF16      scale_i = 1 and the code is a_ij rounded to BF16 (the 16 high
+ *                bits of a binary32 value); values beyond the largest BF16
+ *                round to infinity and NaN stays a quiet NaN;
+ *   KF_FP8_E4M3  scale_i = amax_i / 448 (amax over the row's finite entries,
+ *                correctly rounded binary32 division; 1 for a row of zeros),
+ *                and the code is the exact quotient a_ij / scale_i rounded to
+ *                E4M3, saturating at +-448 (0x7e | sign); NaN gives 0x7f | sign.
+ * Element (i, j) of the stored matrix stands for scale_i * decode(code_ij).
+ * Asynchronous on `stream`; allocates nothing. KF_ERR_ARG for null pointers,
+ * sizes < 1 or an unknown dtype, KF_ERR_ALIGN for unaligned codes or rows,
+ * KF_ERR_ALIAS if codes or scales overlap A. */
+kf_status kf_quantize_rows(const float* A, int64_t rows, int64_t cols, int64_t lda, int32_t dtype, void* codes,
+                           int64_t ldq, float* scales, void* stream);
 kf_status kf_const(kf_script* s, float v, kf_value* out);
 kf_status kf_scalar(kf_script* s, kf_value* out);
 /* Listing 1 `input` and `return`. Declared values must be marked input before
@@ -391,30 +411,42 @@ enum {
     KF_ROUTINE_STORE_VEC = 6, KF_ROUTINE_COMPUTE_SCAL = 7, KF_ROUTINE_COMPUTE_AXPY = 8,
     KF_ROUTINE_COMPUTE_DOT = 9, KF_ROUTINE_FINISH = 10, KF_NUM_ROUTINES = 11
 };
-/* One entry of the routine table: the environment (BLAS-2: mat_k, mat_waves,
- * mat_group, mat_rows; BLAS-1: vec_unroll, vec_threads, vec_grid, 0) and the
- * time per unit in microseconds (per matrix element, per vector entry, or per
- * launch for FINISH). */
+/* One entry of the routine table: the environment and the time per unit in
+ * microseconds (per matrix element, per vector entry, or per launch for
+ * FINISH). Environments ("simulated fusion environments", Section 4.2):
+ *   cls 0  BLAS-1: env = (vec_unroll, vec_threads, vec_grid, 0);
+ *   cls 1  BLAS-2 column strips: env = (mat_k, mat_waves, mat_group, mat_rows);
+ *   cls 2  BLAS-2 row-resident: env = (mat_waves, mat_group, mat_rows, 0) as
+ *          requested (0 = the default for the shape);
+ * and lds_kb, the extra LDS the probe workgroup held besides its own (0, 16,
+ * 32, 64 KiB): a fused kernel's LDS use lowers how many of its workgroups a CU
+ * holds, so a kernel is priced in the environment whose lds_kb is nearest to
+ * its own LDS bytes. */
 typedef struct kf_routine_entry {
-    int32_t cls;          /* 0 = BLAS-1, 1 = BLAS-2 */
+    int32_t cls;          /* 0, 1, 2 as above */
     int32_t env[4];
     int32_t routine;      /* KF_ROUTINE_* */
+    int32_t lds_kb;
     float us_per_unit;
 } kf_routine_entry;
 /* Time routine `routine` alone on a rows x cols matrix (BLAS-2 routines; ld =
  * cols, a multiple of 4) or on a rows-entry vector (BLAS-1 routines; cols
- * ignored) with the implementation parameters of `params` (mode ignored).
- * `buf` is a device buffer of at least rows*cols*4 + 65536 bytes (vector:
- * rows*4 + 65536); its contents are overwritten. Median of `reps` runs.
- * KF_ROUTINE_FINISH is not a probe (time a finishing launch instead). */
+ * ignored) with the implementation parameters of `params` (mode ignored;
+ * mat_sched 1 gives the row-resident geometry: whole rows per workgroup, a
+ * workgroup barrier per row group for the row dot) while each workgroup holds
+ * extra_lds_kb KiB of LDS besides its own (0 .. 96). `buf` is a device buffer
+ * of at least rows*cols*4 + 65536 bytes (vector: rows*4 + 65536); its
+ * contents are overwritten. Median of `reps` runs. KF_ROUTINE_FINISH is not a
+ * probe (time a finishing launch instead). */
 kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols,
-                          const kf_compile_opts* params, void* buf, size_t buf_bytes,
+                          const kf_compile_opts* params, int32_t extra_lds_kb, void* buf, size_t buf_bytes,
                           void* stream, int32_t warmup, int32_t reps, float* median_us);
 /* Additive prediction of a plan: for each kernel, max(t_t, t_c) with t_t the
  * sum of its transfer routines (every matrix and vector it moves through HBM)
  * and t_c the sum of its compute routines (one per call), plus one FINISH per
  * finishing launch; summed over kernels. Entries are matched on class and
- * environment (row-resident kernels use the table's first BLAS-2
+ * environment, then the nearest extra LDS (row-resident kernels use the cls 2
+ * entries; a table without any prices them with its first BLAS-2
  * environment); KF_ERR_UNSUPPORTED if a needed entry is missing. */
 kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n,
                               float* us);

@@ -21,6 +21,8 @@ kf_status set_error(kf_status st, const std::string& msg) {
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_stream(int kind, void* dst, const void* src, size_t bytes, hipStream_t st);
+hipError_t launch_quantize_rows(const float* A, long rows, long cols, long lda, int fp8, void* codes, long ldq,
+                                float* scales, hipStream_t st);
 hipError_t launch_fill_uniform(float* dst, long rows, long cols, long ld, unsigned long long key, float pad,
                                hipStream_t st);
 
@@ -614,14 +616,22 @@ kf_status build_plan(const Script& sc, const std::vector<int>& part, const kf_co
                 return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_group");
             if (mp.sched == 1 && mp.waves && (int64_t)mp.waves * 256 * 8 < sp.b)
                 return set_error(KF_ERR_ARG, "row-resident schedule: mat_waves too small for the row length");
+            {   // the wave partials of a row group are merged one per lane
+                MatParams q = mp;
+                if (q.sched != 1) q.waves = q.group = q.rows = 0;   // strip parameters do not carry over
+                const RowresGeom g = rowres_geometry(sp.a, sp.b, q);
+                if (g.G * g.WP > 64)
+                    return set_error(KF_ERR_ARG, "row-resident schedule: mat_group times mat_waves (rounded up to a "
+                                                 "power of two) must be <= 64");
+            }
         } else if (sp.mat) {
             MatParams q = default_mat_params(sp.a, sp.b, mp, kernel_unit_elems(sc, calls, mp.unit));
             if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of mat_waves * mat_group");
         }
         pk.code = generate_kernel(sc, calls, part, mp, vp);
-        if (pk.code.lds_bytes > 64 * 1024)
+        if (pk.code.lds_bytes > 160 * 1024)
             return set_error(KF_ERR_ARG, "parameters need " + std::to_string(pk.code.lds_bytes) +
-                                             " bytes of LDS per workgroup (limit 65536)");
+                                             " bytes of LDS per workgroup (gfx950 limit 163840)");
         for (const Launch& l : pk.code.launches)
             for (const KArg& a : l.args) {
                 if (a.kind == ArgKind::MatIn || a.kind == ArgKind::VecIn || a.kind == ArgKind::DevScalarIn) p->is_read[a.value] = 1;
@@ -1123,6 +1133,24 @@ kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled) {
     std::lock_guard<std::mutex> lock(reg.mu);
     if (modules) *modules = (int64_t)reg.modules.size();
     if (kernels_compiled) *kernels_compiled = (int64_t)reg.compiled.size();
+    return KF_OK;
+}
+
+kf_status kf_quantize_rows(const float* A, int64_t rows, int64_t cols, int64_t lda, int32_t dtype, void* codes,
+                           int64_t ldq, float* scales, void* stream) {
+    if (!A || !codes || !scales) return set_error(KF_ERR_ARG, "null argument");
+    if (rows < 1 || cols < 1 || lda < cols || ldq < cols) return set_error(KF_ERR_ARG, "bad sizes");
+    if (rows > 0x7fffffff) return set_error(KF_ERR_ARG, "more than 2^31 - 1 rows");
+    if (dtype != KF_BF16 && dtype != KF_FP8_E4M3) return set_error(KF_ERR_ARG, "dtype must be KF_BF16 or KF_FP8_E4M3");
+    const int es = dtype_size(dtype);
+    if ((uintptr_t)codes % 16 || (ldq * es) % 16) return set_error(KF_ERR_ALIGN, "codes need 16-byte aligned rows");
+    if ((uintptr_t)A % 4 || (uintptr_t)scales % 4) return set_error(KF_ERR_ALIGN, "A and scales need 4-byte alignment");
+    const size_t abytes = (size_t)((rows - 1) * lda + cols) * 4;
+    if (overlap(A, abytes, codes, (size_t)(rows * ldq * es)) || overlap(A, abytes, scales, (size_t)rows * 4))
+        return set_error(KF_ERR_ALIAS, "codes or scales overlap A");
+    hipError_t e = launch_quantize_rows(A, rows, cols, lda, dtype == KF_FP8_E4M3, codes, ldq, scales,
+                                        (hipStream_t)stream);
+    if (e != hipSuccess) return set_error(KF_ERR_HIP, hipGetErrorString(e));
     return KF_OK;
 }
 

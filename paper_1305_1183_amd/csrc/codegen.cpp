@@ -872,6 +872,25 @@ bool needs_rowres(const Script& s, const std::vector<int>& calls) {
     return false;
 }
 
+RowresGeom rowres_geometry(int64_t rows, int64_t cols, const MatParams& p) {
+    RowresGeom g;
+    // enough waves to cover the row 256 columns each (at most 16); G rows per
+    // group: two once a lane holds four or more float4 of a row (measured best
+    // at 16384 columns), else up to four within the register budget
+    g.W = p.waves > 0 ? p.waves : (int)std::min<int64_t>(16, std::max<int64_t>(1, (cols + 255) / 256));
+    g.WP = 1;
+    while (g.WP < g.W) g.WP *= 2;
+    g.KP = (int)((cols + 256L * g.W - 1) / (256L * g.W));
+    g.G = p.group > 0 ? p.group : std::max(1, std::min(g.KP >= 4 ? 2 : 4, 16 / g.KP));
+    g.R = p.rows;
+    if (g.R <= 0) {
+        g.R = (rows + 255) / 256;
+        g.R = (g.R + g.G - 1) / g.G * g.G;
+        if (g.R < g.G) g.R = g.G;
+    }
+    return g;
+}
+
 static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
                                  const std::vector<int>& part, const MatParams& p0) {
     KernelCode kc;
@@ -880,24 +899,24 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     const int kid = part[calls[0]];
     const Space sp = call_space(s, calls[0]);
     const long M = (long)sp.a, N = (long)sp.b;
-    // defaults: enough waves to cover the row 256 columns each (at most 16), and
-    // G rows per group so that a group's loads fit the register budget
-    const int W = p0.waves > 0 ? p0.waves : (int)std::min<long>(16, std::max<long>(1, (N + 255) / 256));
-    const int KP = (int)((N + 256L * W - 1) / (256L * W));
-    const int G = p0.group > 0 ? p0.group : std::max(1, std::min(4, 16 / KP));
+    const RowresGeom geo = rowres_geometry(M, N, p0);
+    const int W = geo.W, WP = geo.WP, KP = geo.KP, G = geo.G;
     int LG = 0;
     while ((1 << LG) < G) ++LG;
     const long CW = 256L * KP;
     const int NT = 64 * W;
-    long R = p0.rows;
-    if (R <= 0) {
-        R = (M + 255) / 256;
-        R = (R + G - 1) / G * G;
-        if (R < G) R = G;
-    }
+    const long R = geo.R;
     const long NB = (M + R - 1) / R;
     const long NP = (N + 3) / 4 * 4;
     const bool edge_cols = (long)W * CW > N;
+    // a row group's elements lie within 2^30 floats of its first row: 32-bit offsets
+    long ld_max = 0;
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        ld_max = std::max<long>(ld_max, (long)s.values[k.in[0]].ld);
+        if (k.op == Op::Ger) ld_max = std::max<long>(ld_max, (long)s.values[k.out].ld);
+    }
+    const bool off32 = (long)G * ld_max + N < (1L << 30);
 
     std::vector<int> mat_in, mat_out, colv, rowv, vec_in, vec_out, gemv_calls, gemtv_calls, scalars;
     auto push_u = [](std::vector<int>& v, int x) {
@@ -924,6 +943,16 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     }
     for (int v : colv) push_u(vec_in, v);
     for (int v : rowv) push_u(vec_in, v);
+    std::vector<int> colv_lds;
+    if (!gemtv_calls.empty()) {
+        size_t b = 0;
+        for (int v : colv)
+            if (b + (size_t)W * CW * 4 <= 128 * 1024) { colv_lds.push_back(v); b += (size_t)W * CW * 4; }
+    }
+    auto cvx = [&](int v) {
+        return std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end() ? F("xs%d[(cb >> 2) + 64u * j]", v)
+                                                                                 : F("cv%d[j]", v);
+    };
     const bool col_part = !gemtv_calls.empty() && NB > 1;
     std::map<int, size_t> ws_off;
     size_t wsz = 0;
@@ -956,7 +985,7 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
 
     Emitter e;
     e.l(F("constexpr long M = %ldL, N = %ldL, NB = %ldL, NP = %ldL, CW = %ldL, R = %ldL;", M, N, NB, NP, CW, R));
-    e.l(F("constexpr int KP = %d, W = %d, G = %d, LG = %d, NT = %d;", KP, W, G, LG, NT));
+    e.l(F("constexpr int KP = %d, W = %d, WP = %d, G = %d, LG = %d, NT = %d;", KP, W, WP, G, LG, NT));
     for (int v : mat_in) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
     for (int v : mat_out) e.l(F("constexpr long LD%d = %ldL;", v, (long)s.values[v].ld));
     e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
@@ -965,18 +994,27 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     for (int v : scalars)
         e.l(s.values[v].kind == VK::Const ? F("const float %s = P%d;", scal_name(v).c_str(), v)
                                           : F("const float %s = *P%d;", scal_name(v).c_str(), v));
-    e.l("long col[KP];");
-    e.l("for (int j = 0; j < KP; ++j) col[j] = (long)wave * CW + (long)(j * 64 + lane) * 4;");
+    // column of lane's float4 j: cb + 256 j (32-bit: rows are at most 32768 columns)
+    e.l("const unsigned cb = (unsigned)(wave * CW + lane * 4);");
+    // Column-indexed vectors live in registers, KP float4 per lane each, or,
+    // in kernels that also hold gemtv accumulators in registers, in LDS (as
+    // many as fit 128 KiB; one copy per workgroup, zero past N), read at each
+    // use: that keeps the loads of a row group in registers without spills.
     for (int v : colv) {
-        e.l(F("kf_f4 cv%d[KP];", v));
-        e.l(F("for (int j = 0; j < KP; ++j) cv%d[j] = kf_ld4_tail(V%d, col[j], N);", v, v));
+        if (std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end()) {
+            e.l(F("__shared__ kf_f4 xs%d[W * KP * 64];", v));
+            e.l(F("for (int i = tid; i < W * KP * 64; i += NT) xs%d[i] = kf_ld4_tail(V%d, 4L * i, N);", v, v));
+        } else {
+            e.l(F("kf_f4 cv%d[KP];", v));
+            e.l(F("for (int j = 0; j < KP; ++j) cv%d[j] = kf_ld4_tail(V%d, (long)(cb + 256u * j), N);", v, v));
+        }
     }
     for (int v : rowv) {
         e.l(F("__shared__ float rv%d[R];", v));
         e.l(F("for (long i = tid; i < R; i += NT) rv%d[i] = (r0 + i < M) ? V%d[r0 + i] : 0.f;", v, v));
     }
     const int ngv = (int)gemv_calls.size();
-    if (ngv) e.l(F("__shared__ float kf_part[2][%d][G][W];", ngv));
+    if (ngv) e.l(F("__shared__ float kf_part[2][%d][G][WP];", ngv));
     for (int c : gemtv_calls) {
         e.l(F("kf_f4 acc%d[KP];", c));
         e.l(F("for (int j = 0; j < KP; ++j) acc%d[j] = kf_zero4();", c));
@@ -990,8 +1028,9 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         e.ind++;
         e.l("const long row = g0 + gi;");
         for (int v : mat_in) {
-            if (!edge) e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = kf_ld4_nt(M%d + row * LD%d + col[j]);", v, v, v));
-            else e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = (row < r1) ? kf_ldm_edge(M%d + row * LD%d, col[j], N) : kf_zero4();", v, v, v));
+            if (!edge && off32) e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = kf_ld4_nt_at(M%d + g0 * LD%d, (unsigned)gi * (unsigned)LD%d + cb + 256u * j);", v, v, v, v));
+            else if (!edge) e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = kf_ld4_nt(M%d + row * LD%d + (long)(cb + 256u * j));", v, v, v));
+            else e.l(F("for (int j = 0; j < KP; ++j) L%d[gi][j] = (row < r1) ? kf_ldm_edge(M%d + row * LD%d, (long)(cb + 256u * j), N) : kf_zero4();", v, v, v));
         }
         e.ind--;
         e.l("}");
@@ -1007,14 +1046,15 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
             std::string Min = mexpr(k.in[0]);
             if (k.op == Op::Ger) {
                 e.l(F("const float cu%d = %s * rv%d[rl];", c, scal_name(k.alpha).c_str(), k.in[1]));
-                e.l(F("for (int j = 0; j < KP; ++j) m%d[gi][j] = kf_fma4s(cu%d, cv%d[j], %s[j]);", k.out, c, k.in[2], Min.c_str()));
+                e.l(F("for (int j = 0; j < KP; ++j) m%d[gi][j] = kf_fma4s(cu%d, %s, %s[j]);", k.out, c, cvx(k.in[2]).c_str(), Min.c_str()));
                 if (must_store(s, part, kid, k.out)) {
-                    if (!edge) e.l(F("for (int j = 0; j < KP; ++j) kf_st4_nt(O%d + row * LD%d + col[j], m%d[gi][j]);", k.out, k.out, k.out));
-                    else e.l(F("if (row < r1) for (int j = 0; j < KP; ++j) kf_stm_edge(O%d + row * LD%d, col[j], N, m%d[gi][j]);", k.out, k.out, k.out));
+                    if (!edge && off32) e.l(F("for (int j = 0; j < KP; ++j) kf_st4_nt_at(O%d + g0 * LD%d, (unsigned)gi * (unsigned)LD%d + cb + 256u * j, m%d[gi][j]);", k.out, k.out, k.out, k.out));
+                    else if (!edge) e.l(F("for (int j = 0; j < KP; ++j) kf_st4_nt(O%d + row * LD%d + (long)(cb + 256u * j), m%d[gi][j]);", k.out, k.out, k.out));
+                    else e.l(F("if (row < r1) for (int j = 0; j < KP; ++j) kf_stm_edge(O%d + row * LD%d, (long)(cb + 256u * j), N, m%d[gi][j]);", k.out, k.out, k.out));
                 }
             } else if (k.op == Op::Gemv) {
                 e.l(F("float t%d = 0.f;", c));
-                e.l(F("for (int j = 0; j < KP; ++j) t%d = kf_dot4(%s[j], cv%d[j], t%d);", c, Min.c_str(), k.in[1], c));
+                e.l(F("for (int j = 0; j < KP; ++j) t%d = kf_dot4(%s[j], %s, t%d);", c, Min.c_str(), cvx(k.in[1]).c_str(), c));
                 e.l(F("rp%d[gi] = t%d;", c, c));
             }
         }
@@ -1026,15 +1066,21 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
             e.l(F("{ const float sw = kf_rows_reduce<LG>(rp%d); if ((lane & ((64 >> LG) - 1)) == 0) kf_part[slot][%d][lane >> (6 - LG)][wave] = sw; }", c, i));
         }
         if (ngv) e.l("__syncthreads();");
+        // lane l < G WP takes the partial of wave l % WP for row l / WP (zero
+        // for l % WP >= W; WP is W rounded up to a power of two); a TwoSum
+        // butterfly over each group of WP lanes merges them, in the same fixed
+        // order for every row, and lane gi WP then holds row gi's sum
+        for (int i = 0; i < ngv; ++i) {
+            int c = gemv_calls[i];
+            e.l(F("const float fl%d = kf_cs_value(kf_group_sum_cs<WP>(kf_cs_init((lane < G * WP && (lane & (WP - 1)) < W) ? (&kf_part[slot][%d][0][0])[lane] : 0.f)));", c, i));
+        }
         // per row: gemv epilogues, gemtv accumulation (script order)
         e.l("for (int gi = 0; gi < G; ++gi) {");
         e.ind++;
         e.l("const long row = g0 + gi; const int rl = (int)(row - r0); (void)rl;");
         for (int i = 0; i < ngv; ++i) {
             int c = gemv_calls[i];
-            e.l(F("kf_cs cs%d = kf_cs_init(kf_part[slot][%d][gi][0]);", c, i));
-            e.l(F("for (int w = 1; w < W; ++w) cs%d = kf_cs_add(cs%d, kf_part[slot][%d][gi][w]);", c, c, i));
-            e.l(F("const float sum%d = kf_cs_value(cs%d);", c, c));
+            e.l(F("const float sum%d = kf_lane_bcast(fl%d, gi * WP);", c, c));
         }
         for (int c : calls) {
             const Call& k = s.calls[c];
@@ -1079,7 +1125,7 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     if (!gemtv_calls.empty()) {
         e.l("for (int j = 0; j < KP; ++j) {");
         e.ind++;
-        e.l("const long cc = col[j];");
+        e.l("const long cc = (long)(cb + 256u * j);");
         e.l("if (cc < N) {");
         e.ind++;
         for (int c : gemtv_calls) {
@@ -1171,7 +1217,7 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
         kc.launches.push_back(finl);
     }
     kc.source = head.str();
-    kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + (size_t)ngv * 2 * G * W * 4;
+    kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + (size_t)ngv * 2 * G * WP * 4 + colv_lds.size() * (size_t)W * CW * 4;
     kc.params_json = F("{\"schedule\": \"row-resident\", \"waves\": %d, \"group\": %d, \"rows\": %ld, \"kp\": %d, \"row_blocks\": %ld}",
                        W, G, R, KP, NB);
     kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
@@ -1226,15 +1272,103 @@ namespace kf {
 // iterations of a real kernel (Section 4.2: routine times are benchmarked in a
 // simulated fusion environment and summed to predict a fusion).
 // ============================================================================
+// Extra LDS of a probe's environment: an array the workgroup holds (and
+// touches, so that it is allocated) for the whole launch.
+static void probe_extra_lds(Emitter& e, int extra_kb, int nt) {
+    if (extra_kb <= 0) return;
+    e.l(F("__shared__ float kf_xlds[%d];", extra_kb * 256));
+    e.l(F("for (int i = threadIdx.x; i < %d; i += %d) kf_xlds[i] = 0.f;", extra_kb * 256, nt));
+}
+
+// Row-resident probe: a workgroup of W waves owns R whole rows and walks them
+// G rows per group, as the row-resident kernels do; a row dot finishes inside
+// the workgroup (transposing reduction, LDS, barrier, merge over the waves).
+static std::string probe_rowres(Emitter& e, int routine, int64_t rows, int64_t cols, const MatParams& mp,
+                                int extra_kb, Launch* l, std::string* params_json) {
+    const RowresGeom g = rowres_geometry(rows, cols, mp);
+    const long M = (long)rows, N = (long)cols;
+    const int W = g.W, WP = g.WP, KP = g.KP, G = g.G, NT = 64 * W;
+    int LG = 0;
+    while ((1 << LG) < G) ++LG;
+    const long R = g.R, NB = (M + R - 1) / R, CW = 256L * KP;
+    const bool edge = (long)W * CW > N;
+    e.l(F("constexpr long M = %ldL, N = %ldL, R = %ldL, LD = %ldL, CW = %ldL;", M, N, R, N, CW));
+    e.l(F("constexpr int KP = %d, W = %d, WP = %d, G = %d, LG = %d, NT = %d;", KP, W, WP, G, LG, NT));
+    e.l("const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;");
+    e.l("const long r0 = (long)blockIdx.x * R, r1 = (r0 + R < M) ? r0 + R : M;");
+    e.l("(void)src; (void)dst;");
+    e.l("const unsigned cb = (unsigned)(wave * CW + lane * 4);");
+    e.l("kf_f4 cv[KP], acc[KP];");
+    e.l("for (int j = 0; j < KP; ++j) { cv[j] = kf_zero4() + (float)(lane + j); acc[j] = kf_zero4(); }");
+    e.l("__shared__ kf_f4 tile[8 * KP * 64];");
+    e.l("__shared__ float part[2][G][WP];");
+    e.l("for (int i = tid; i < 8 * KP * 64; i += NT) tile[i] = kf_zero4() + 1e-3f * (float)i;");
+    probe_extra_lds(e, extra_kb, NT);
+    e.l("__syncthreads();");
+    e.l("float s = 0.f; int slot = 0;");
+    e.l("for (long g0 = r0; g0 < r1; g0 += G) {");
+    e.ind++;
+    // a lane's columns cb + 256 j; with edge columns only those below N are touched
+    const std::string ok = edge ? "(long)(cb + 256u * j) + 4 <= N && g0 + gi < r1" : "g0 + gi < r1";
+    std::string tag;
+    switch (routine) {
+        case KF_ROUTINE_LOAD_MAT:
+            e.l("kf_f4 L[G][KP];");
+            e.l(F("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < KP; ++j) L[gi][j] = (%s) ? kf_ld4_nt_at(src + g0 * LD, (unsigned)gi * (unsigned)LD + cb + 256u * j) : kf_zero4();", ok.c_str()));
+            e.l("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < KP; ++j) acc[j] += L[gi][j];");
+            tag = "load_mat";
+            break;
+        case KF_ROUTINE_STORE_MAT:
+            e.l(F("for (int gi = 0; gi < G; ++gi) for (int j = 0; j < KP; ++j) if (%s) kf_st4_nt_at(dst + g0 * LD, (unsigned)gi * (unsigned)LD + cb + 256u * j, cv[j]);", ok.c_str()));
+            tag = "store_mat";
+            break;
+        case KF_ROUTINE_COMPUTE_GEMV:
+            e.l("float rp[G];");
+            e.l("for (int gi = 0; gi < G; ++gi) { float t = 0.f; for (int j = 0; j < KP; ++j) t = kf_dot4(tile[(((g0 + gi) & 7) * KP + j) * 64 + lane], cv[j], t); rp[gi] = t; }");
+            e.l("{ const float sw = kf_rows_reduce<LG>(rp); if ((lane & ((64 >> LG) - 1)) == 0) part[slot][lane >> (6 - LG)][wave] = sw; }");
+            e.l("__syncthreads();");
+            e.l("const float fl = kf_cs_value(kf_group_sum_cs<WP>(kf_cs_init((lane < G * WP && (lane & (WP - 1)) < W) ? (&part[slot][0][0])[lane] : 0.f)));");
+            e.l("for (int gi = 0; gi < G; ++gi) s += kf_lane_bcast(fl, gi * WP);");
+            e.l("slot ^= 1;");
+            tag = "gemv";
+            break;
+        case KF_ROUTINE_COMPUTE_GEMTV:
+            e.l("for (int gi = 0; gi < G; ++gi) { const float xr = 1e-7f * (float)(g0 + gi); for (int j = 0; j < KP; ++j) acc[j] = kf_fma4s(xr, tile[(((g0 + gi) & 7) * KP + j) * 64 + lane], acc[j]); }");
+            tag = "gemtv";
+            break;
+        case KF_ROUTINE_COMPUTE_GER:
+            e.l("for (int gi = 0; gi < G; ++gi) { const float cu = 1e-7f * (float)(g0 + gi); for (int j = 0; j < KP; ++j) acc[j] += kf_fma4s(cu, cv[j], tile[(((g0 + gi) & 7) * KP + j) * 64 + lane]); }");
+            tag = "ger";
+            break;
+    }
+    e.ind--;
+    e.l("}");
+    e.l("for (int j = 0; j < KP; ++j) s += (acc[j].x + acc[j].y) + (acc[j].z + acc[j].w);");
+    if (extra_kb > 0) e.l(F("s += kf_xlds[tid %% %d];", extra_kb * 256));
+    e.l("if (s == 1234.5678f) sink[tid] = s;");
+    l->grid = (int)NB;
+    l->block = NT;
+    *params_json = F("{\"schedule\": \"row-resident\", \"waves\": %d, \"group\": %d, \"rows\": %ld, \"extra_lds_kb\": %d}",
+                     W, G, R, extra_kb);
+    return F("probe rowres %s W%d G%d R%ld M%ld N%ld X%d", tag.c_str(), W, G, R, M, N, extra_kb);
+}
+
 KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatParams& mp0,
-                          const VecParams& vp0) {
+                          const VecParams& vp0, int extra_kb) {
     KernelCode kc;
     Emitter e;
     std::vector<std::string> sig = {"const float* __restrict__ src", "float* __restrict__ dst",
                                     "float* __restrict__ sink"};
     const bool mat = routine <= KF_ROUTINE_COMPUTE_GER;
     std::string tag;
-    if (mat) {
+    if (mat && mp0.sched == 1) {
+        Launch l;
+        const std::string key = probe_rowres(e, routine, rows, cols, mp0, extra_kb, &l, &kc.params_json) + e.o.str();
+        kc.name = F("kf_probe_%016llx", (unsigned long long)fnv1a(key));
+        l.name = kc.name;
+        kc.launches.push_back(l);
+        kc.mat = true;
+    } else if (mat) {
         MatParams p = default_mat_params(rows, cols, mp0);
         const long M = (long)rows, N = (long)cols;
         const int K = p.k, W = p.waves, G = p.group, R = p.rows, NT = 64 * W;
@@ -1251,6 +1385,7 @@ KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatPara
         e.l("for (int j = 0; j < K; ++j) { col[j] = c0 + (long)(j * 64 + lane) * 4; cv[j] = kf_zero4() + (float)(lane + j); acc[j] = kf_zero4(); }");
         e.l("__shared__ kf_f4 tile[8 * K * 64];");
         e.l("for (int i = tid; i < 8 * K * 64; i += NT) tile[i] = kf_zero4() + 1e-3f * (float)i;");
+        probe_extra_lds(e, extra_kb, NT);
         e.l("__syncthreads();");
         e.l("float s = 0.f;");
         e.l("for (long g0 = r0 + (long)wave * G; g0 < r1; g0 += (long)W * G) {");
@@ -1284,15 +1419,17 @@ KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatPara
         e.ind--;
         e.l("}");
         e.l("for (int j = 0; j < K; ++j) s += (acc[j].x + acc[j].y) + (acc[j].z + acc[j].w);");
+        if (extra_kb > 0) e.l(F("s += kf_xlds[tid %% %d];", extra_kb * 256));
         e.l("if (s == 1234.5678f) sink[tid] = s;");
-        std::string key = F("probe %s K%d W%d G%d R%d M%ld N%ld", tag.c_str(), K, W, G, R, M, N) + e.o.str();
+        std::string key = F("probe %s K%d W%d G%d R%d M%ld N%ld X%d", tag.c_str(), K, W, G, R, M, N, extra_kb) + e.o.str();
         kc.name = F("kf_probe_%016llx", (unsigned long long)fnv1a(key));
         Launch l;
         l.name = kc.name;
         l.grid = (int)(S * NB);
         l.block = NT;
         kc.launches.push_back(l);
-        kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d}", K, W, G, R);
+        kc.params_json = F("{\"k\": %d, \"waves\": %d, \"group\": %d, \"rows\": %d, \"extra_lds_kb\": %d}", K, W, G, R,
+                           extra_kb);
         kc.mat = true;
     } else {
         VecParams p = default_vec_params(rows, vp0);

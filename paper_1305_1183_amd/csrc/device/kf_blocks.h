@@ -27,6 +27,15 @@ __device__ __forceinline__ void kf_st4_nt(float* p, kf_f4 v) {
 __device__ __forceinline__ void kf_st4(float* p, kf_f4 v) {
     *reinterpret_cast<kf_f4*>(p) = v;
 }
+// Non-temporal 16-byte load and store at float offset `off` from a wave-uniform
+// base: a 32-bit offset keeps the address one scalar base plus one lane
+// register (off < 2^30).
+__device__ __forceinline__ kf_f4 kf_ld4_nt_at(const float* base, unsigned off) {
+    return __builtin_nontemporal_load(reinterpret_cast<const kf_f4*>(reinterpret_cast<const char*>(base) + 4u * off));
+}
+__device__ __forceinline__ void kf_st4_nt_at(float* base, unsigned off, kf_f4 v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<kf_f4*>(reinterpret_cast<char*>(base) + 4u * off));
+}
 __device__ __forceinline__ kf_f4 kf_zero4() { kf_f4 z = {0.f, 0.f, 0.f, 0.f}; return z; }
 
 // Vector entries col..col+3, entries at index >= n read as zero (the vector
@@ -207,9 +216,11 @@ __device__ __forceinline__ float kf_block_sum(float v, float* lds) {
 // ---- B7: compensated summation of partial sums ---------------------------------
 // A partial sum travels as a pair (s, c): s is the rounded running sum and c
 // collects the rounding errors of the additions that formed it. Each addition
-// is Knuth's TwoSum, which gives the exact error of fl(a + b) for any a and b
-// without a branch (six additions; it relies on strict IEEE evaluation, so no
-// reassociation -- the kernels are built without fast-math). Two pairs merge
+// is Knuth's TwoSum, which gives the exact error of fl(a + b) for any finite a
+// and b without a branch (six additions; it relies on strict IEEE evaluation,
+// so no reassociation -- the kernels are built without fast-math); a sum that
+// overflows or meets an infinity or NaN keeps error 0, so the pair's value is
+// the plain sum's infinity or NaN. Two pairs merge
 // with TwoSum of their leading parts, and the value of a pair is s + c. The
 // merge is symmetric in its arguments (the error term is exact), so a
 // butterfly leaves every lane with the same pair. Every final reduction that
@@ -221,7 +232,9 @@ struct kf_cs4 { kf_f4 s, c; };
 __device__ __forceinline__ void kf_two_sum(float a, float b, float* s, float* e) {
     const float t = a + b;
     const float z = t - a;
-    *e = (a - (t - z)) + (b - z);
+    const float err = (a - (t - z)) + (b - z);
+    // an infinite or NaN sum carries no error term (inf - inf would make it NaN)
+    *e = __builtin_fabsf(t) <= 3.40282347e38f ? err : 0.f;
     *s = t;
 }
 __device__ __forceinline__ kf_cs kf_cs_init(float x) { kf_cs r = {x, 0.f}; return r; }
@@ -272,6 +285,23 @@ __device__ __forceinline__ kf_cs kf_wave_sum_cs(kf_cs v) {
         v = kf_cs_merge(v, o);
     }
     return v;
+}
+// The same butterfly within aligned groups of NL lanes (NL a power of two,
+// at most 64): every lane of a group ends with the merge of the group's pairs.
+template <int NL>
+__device__ __forceinline__ kf_cs kf_group_sum_cs(kf_cs v) {
+#pragma unroll
+    for (int mask = NL / 2; mask >= 1; mask >>= 1) {
+        kf_cs o;
+        o.s = kf_xor(v.s, mask);
+        o.c = kf_xor(v.c, mask);
+        v = kf_cs_merge(v, o);
+    }
+    return v;
+}
+// Lane src's value of v (src wave-uniform), as a scalar in every lane.
+__device__ __forceinline__ float kf_lane_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 // Workgroup sum of one float per thread, compensated from the wave level on:
 // the wave pairs are merged in wave order by thread 0, which gets the value

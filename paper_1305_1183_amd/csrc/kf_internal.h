@@ -85,6 +85,11 @@ struct VecParams { int unroll = 0, threads = 0, grid = 0; };
 // 8 with a BF16 matrix, 16 with an FP8 matrix).
 MatParams default_mat_params(int64_t rows, int64_t cols, const MatParams& req, int e_per_unit = 4);
 int dtype_size(int dtype);
+// Geometry of a row-resident kernel on a rows x cols matrix after defaults:
+// W waves (WP: W rounded up to a power of two), KP float4 per lane per row,
+// G rows per group, R rows per workgroup.
+struct RowresGeom { int W = 0, WP = 0, KP = 0, G = 0; int64_t R = 0; };
+RowresGeom rowres_geometry(int64_t rows, int64_t cols, const MatParams& p);
 // Elements per 16-byte unit of the kernel made of `calls` (smallest element size
 // of the matrices it loads).
 int kernel_unit_elems(const Script& s, const std::vector<int>& calls, int req = 0);
@@ -130,9 +135,10 @@ KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
 // Does the call set need the row-resident schedule (a gemv result feeding a
 // gemtv of the same kernel)?
 bool needs_rowres(const Script& s, const std::vector<int>& calls);
-// Single-routine probe kernel (one launch; args: src, dst, sink).
+// Single-routine probe kernel (one launch; args: src, dst, sink): strip or
+// row-resident geometry (mp.sched), holding extra_kb KiB of LDS besides its own.
 KernelCode generate_probe(int routine, int64_t rows, int64_t cols, const MatParams& mp,
-                          const VecParams& vp);
+                          const VecParams& vp, int extra_kb);
 // KF_FEATURE_DIM features of one plan kernel.
 void kernel_features(const Script& s, const KernelCode& kc, const std::vector<int>& part,
                      const MatParams& mp, const VecParams& vp, float* f);

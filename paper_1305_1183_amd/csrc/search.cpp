@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <array>
 #include <cstring>
@@ -16,17 +17,27 @@ using namespace kf;
 
 namespace {
 
-bool env_match(const kf_routine_entry& e, bool mat, const MatParams& mp, const VecParams& vp) {
-    if (e.cls != (mat ? 1 : 0)) return false;
-    if (mat) return e.env[0] == mp.k && e.env[1] == mp.waves && e.env[2] == mp.group && e.env[3] == mp.rows;
+// Environment classes of the routine table: 0 BLAS-1, 1 BLAS-2 column strips,
+// 2 BLAS-2 row-resident (waves, group, rows as requested, 0 = default).
+bool env_match(const kf_routine_entry& e, int cls, const MatParams& mp, const VecParams& vp) {
+    if (e.cls != cls) return false;
+    if (cls == 1) return e.env[0] == mp.k && e.env[1] == mp.waves && e.env[2] == mp.group && e.env[3] == mp.rows;
+    if (cls == 2) return e.env[0] == mp.waves && e.env[1] == mp.group && e.env[2] == mp.rows;
     return e.env[0] == vp.unroll && e.env[1] == vp.threads && e.env[2] == vp.grid;
 }
 
-const kf_routine_entry* find(const kf_routine_entry* t, int n, bool mat, const MatParams& mp,
-                             const VecParams& vp, int routine) {
-    for (int i = 0; i < n; ++i)
-        if (t[i].routine == routine && env_match(t[i], mat, mp, vp)) return &t[i];
-    return nullptr;
+// The entry of `routine` in the environment whose extra LDS is nearest to the
+// kernel's own LDS use (lds_bytes); ties go to the smaller amount.
+const kf_routine_entry* find(const kf_routine_entry* t, int n, int cls, const MatParams& mp, const VecParams& vp,
+                             int routine, size_t lds_bytes) {
+    const kf_routine_entry* best = nullptr;
+    double bd = 0;
+    for (int i = 0; i < n; ++i) {
+        if (t[i].routine != routine || !env_match(t[i], cls, mp, vp)) continue;
+        const double d = std::fabs((double)t[i].lds_kb * 1024.0 - (double)lds_bytes);
+        if (!best || d < bd || (d == bd && t[i].lds_kb < best->lds_kb)) { best = &t[i]; bd = d; }
+    }
+    return best;
 }
 
 }  // namespace
@@ -34,9 +45,10 @@ const kf_routine_entry* find(const kf_routine_entry* t, int n, bool mat, const M
 extern "C" {
 
 kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols, const kf_compile_opts* params,
-                          void* buf, size_t buf_bytes, void* stream, int32_t warmup, int32_t reps,
-                          float* median_us) {
+                          int32_t extra_lds_kb, void* buf, size_t buf_bytes, void* stream, int32_t warmup,
+                          int32_t reps, float* median_us) {
     if (!buf || !median_us || reps < 1 || warmup < 0) return set_error(KF_ERR_ARG, "bad argument");
+    if (extra_lds_kb < 0 || extra_lds_kb > 96) return set_error(KF_ERR_ARG, "extra_lds_kb must be 0 .. 96");
     if (routine < 0 || routine >= KF_ROUTINE_FINISH) return set_error(KF_ERR_ARG, "routine has no probe");
     const bool mat = routine <= KF_ROUTINE_COMPUTE_GER;
     if (rows < 1 || (mat && (cols < 4 || cols % 4))) return set_error(KF_ERR_SHAPE, "probe shape");
@@ -47,15 +59,21 @@ kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols, const kf_
     VecParams vp;
     if (params) {
         mp.k = params->mat_k; mp.waves = params->mat_waves; mp.group = params->mat_group; mp.rows = params->mat_rows;
+        mp.sched = params->mat_sched;
         vp.unroll = params->vec_unroll; vp.threads = params->vec_threads; vp.grid = params->vec_grid;
     }
-    if (mat) {
+    if (mat && mp.sched == 1) {
+        if (cols > 32768) return set_error(KF_ERR_UNSUPPORTED, "row-resident schedule needs cols <= 32768");
+        const RowresGeom g = rowres_geometry(rows, cols, mp);
+        if (g.G * g.WP > 64 || g.KP > 8 || g.R % g.G)
+            return set_error(KF_ERR_ARG, "row-resident probe: bad waves, group or rows for this shape");
+    } else if (mat) {
         MatParams q = default_mat_params(rows, cols, mp);
         if (q.rows % (q.waves * q.group)) return set_error(KF_ERR_ARG, "mat_rows must be a multiple of waves*group");
     }
     KernelCode kc;
     try {
-        kc = generate_probe(routine, rows, cols, mp, vp);
+        kc = generate_probe(routine, rows, cols, mp, vp, extra_lds_kb);
     } catch (...) {
         return set_error(KF_ERR_INTERNAL, "probe generation failed");
     }
@@ -113,18 +131,23 @@ kf_status predict_kernel_additive(const kf_plan* p, const PlanKernel& pk, const 
     VecParams vp = mat ? VecParams() : default_vec_params(sp.a, pk.vp);
     if (!mat && pk.vp.grid > 0) vp.grid = pk.vp.grid;  // the environment is the requested point (grid is capped for short vectors)
     const bool rowres = mat && (pk.mp.sched == 1 || needs_rowres(p->s, kc.calls));
+    MatParams rp = pk.mp;   // row-resident environment: the requested geometry (0 = default)
+    if (rowres && rp.sched != 1) rp.waves = rp.group = rp.rows = 0;
+    bool have_rowres = false;
+    for (int i = 0; i < n && rowres && !have_rowres; ++i) have_rowres = table[i].cls == 2;
     const kf_routine_entry* first_mat = nullptr;
-    for (int i = 0; i < n && rowres && !first_mat; ++i)
+    for (int i = 0; i < n && rowres && !have_rowres && !first_mat; ++i)
         if (table[i].cls == 1) first_mat = &table[i];
     auto get = [&](int r) -> const kf_routine_entry* {
+        if (rowres && have_rowres) return find(table, n, 2, rp, vp, r, kc.lds_bytes);
         if (rowres && first_mat) {
-            // row-resident kernels have no probe geometry of their own: they are
-            // priced with the routines of the table's first BLAS-2 environment
+            // a table without row-resident probes: the routines of its first
+            // BLAS-2 environment stand in
             MatParams e;
             e.k = first_mat->env[0]; e.waves = first_mat->env[1]; e.group = first_mat->env[2]; e.rows = first_mat->env[3];
-            return find(table, n, true, e, vp, r);
+            return find(table, n, 1, e, vp, r, kc.lds_bytes);
         }
-        return find(table, n, mat, mp, vp, r);
+        return find(table, n, mat ? 1 : 0, mp, vp, r, kc.lds_bytes);
     };
     double tt = 0, tc = 0;
     // transfers: every operand the kernel's launches move through HBM
@@ -417,20 +440,26 @@ kf_status compile_additive(const kf_script* s, const kf_compile_opts& o, kf_plan
         grid.assign(o.grid, o.grid + o.grid_len);
     } else {
         // every (BLAS-2 environment, BLAS-1 environment) pair present in the table
-        std::vector<std::array<int, 4>> me, ve;
+        // (class first: 1 column strips, 2 row-resident)
+        std::vector<std::array<int, 5>> me, ve;
         for (int i = 0; i < o.table_len; ++i) {
-            std::array<int, 4> e = {o.table[i].env[0], o.table[i].env[1], o.table[i].env[2], o.table[i].env[3]};
-            auto& v = o.table[i].cls ? me : ve;
+            const kf_routine_entry& t = o.table[i];
+            std::array<int, 5> e = {t.cls, t.env[0], t.env[1], t.env[2], t.env[3]};
+            auto& v = t.cls ? me : ve;
             if (std::find(v.begin(), v.end(), e) == v.end()) v.push_back(e);
         }
-        if (me.empty()) me.push_back({0, 0, 0, 0});
-        if (ve.empty()) ve.push_back({0, 0, 0, 0});
+        if (me.empty()) me.push_back({1, 0, 0, 0, 0});
+        if (ve.empty()) ve.push_back({0, 0, 0, 0, 0});
         for (auto& m : me)
             for (auto& v : ve) {
                 kf_compile_opts g;
                 kf_compile_opts_init(&g);
-                g.mat_k = m[0]; g.mat_waves = m[1]; g.mat_group = m[2]; g.mat_rows = m[3];
-                g.vec_unroll = v[0]; g.vec_threads = v[1]; g.vec_grid = v[2];
+                if (m[0] == 2) {
+                    g.mat_sched = 1; g.mat_waves = m[1]; g.mat_group = m[2]; g.mat_rows = m[3];
+                } else {
+                    g.mat_k = m[1]; g.mat_waves = m[2]; g.mat_group = m[3]; g.mat_rows = m[4];
+                }
+                g.vec_unroll = v[1]; g.vec_threads = v[2]; g.vec_grid = v[3];
                 grid.push_back(g);
             }
     }

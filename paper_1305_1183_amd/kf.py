@@ -50,7 +50,7 @@ class KFError(RuntimeError):
 
 
 class kf_routine_entry(ctypes.Structure):
-    _fields_ = [("cls", _i32), ("env", _i32 * 4), ("routine", _i32), ("us_per_unit", _f32)]
+    _fields_ = [("cls", _i32), ("env", _i32 * 4), ("routine", _i32), ("lds_kb", _i32), ("us_per_unit", _f32)]
 
 
 class kf_compile_opts(ctypes.Structure):
@@ -143,8 +143,9 @@ _SIGS = {
     "kf_util_stream": ([_i32, _vp, _vp, _sz, _vp], _i32),
     "kf_jit_set_cache_dir": ([ctypes.c_char_p], _i32),
     "kf_util_fill_uniform": ([_vp, _i64, _i64, _i64, _u64, _f32, _vp], _i32),
+    "kf_quantize_rows": ([_vp, _i64, _i64, _i64, _i32, _vp, _i64, _vp, _vp], _i32),
     "kf_jit_release": ([], _i32),
-    "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
+    "kf_routine_time": ([_i32, _i64, _i64, _P(kf_compile_opts), _i32, _vp, _sz, _vp, _i32, _i32, _P(_f32)], _i32),
     "kf_predict_additive": ([_vp, _P(kf_routine_entry), _i32, _P(_f32)], _i32),
     "kf_plan_features": ([_vp, _P(_f32), _i32, _P(_i32)], _i32),
     "kf_mlp_create": ([_i32, _i32, _i32, _P(_vp)], _i32),
@@ -764,25 +765,33 @@ def kf_util_fill_uniform(dst: int, rows: int, cols: int, ld: int, key: int, pad:
     _chk(lib().kf_util_fill_uniform(_vp(dst), rows, cols, ld, key, pad, _vp(stream)))
 
 
+def kf_quantize_rows(A: int, rows: int, cols: int, lda: int, dtype: int, codes: int, ldq: int, scales: int,
+                     stream: int = 0) -> None:
+    """Row-scaled BF16 / FP8-E4M3 storage of an FP32 device matrix (device pointers)."""
+    _chk(lib().kf_quantize_rows(_vp(A), rows, cols, lda, dtype, _vp(codes), ldq, _vp(scales), _vp(stream)))
+
+
 # ---- plan ranking ------------------------------------------------------------------
 def kf_routine_time(routine: int, rows: int, cols: int, buf: int, buf_bytes: int, stream: int = 0,
-                    warmup: int = 2, reps: int = 10, **params) -> float:
+                    warmup: int = 2, reps: int = 10, extra_lds_kb: int = 0, **params) -> float:
     o = kf_compile_opts_init(**params)
     t = _f32()
-    _chk(lib().kf_routine_time(routine, rows, cols, ctypes.byref(o), _vp(buf), buf_bytes, _vp(stream),
-                               warmup, reps, ctypes.byref(t)))
+    _chk(lib().kf_routine_time(routine, rows, cols, ctypes.byref(o), extra_lds_kb, _vp(buf), buf_bytes,
+                               _vp(stream), warmup, reps, ctypes.byref(t)))
     return t.value
 
 
 def routine_table(entries) -> ctypes.Array:  # noqa: F811
-    """entries: iterable of (cls, (e0, e1, e2, e3), routine, us_per_unit)."""
+    """entries: iterable of (cls, (e0, e1, e2, e3), routine, us_per_unit[, lds_kb])."""
     entries = list(entries)
     arr = (kf_routine_entry * max(1, len(entries)))()
-    for i, (cls, env, r, us) in enumerate(entries):
+    for i, ent in enumerate(entries):
+        cls, env, r, us = ent[:4]
         arr[i].cls = cls
         for j in range(4):
             arr[i].env[j] = int(env[j])
         arr[i].routine = r
+        arr[i].lds_kb = int(ent[4]) if len(ent) > 4 else 0
         arr[i].us_per_unit = us
     return arr
 

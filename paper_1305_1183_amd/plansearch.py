@@ -40,8 +40,10 @@ def _range(s):
 def cmd_table(a):
     from . import search as SE
     entries = SE.measure_routine_table(reps=a.reps)
-    json.dump({"entries": [[c, list(e), r, u] for c, e, r, u in entries],
-               "note": "us per matrix element / vector entry / launch (FINISH); probes on 8192x8192 and 2^24"},
+    json.dump({"entries": [[c, list(e), r, u, x] for c, e, r, u, x in entries],
+               "note": "[class (0 BLAS-1, 1 BLAS-2 strips, 2 BLAS-2 row-resident), environment, routine, "
+                       "us per matrix element / vector entry / launch (FINISH), extra LDS KiB]; probes on "
+                       "8192x8192 and 2^24"},
               open(a.out, "w"), indent=0)
     print("routine table: %d entries -> %s" % (len(entries), a.out), flush=True)
 
@@ -68,24 +70,31 @@ def cmd_evaluate(a):
     train, evals = set(_range(a.train)), set(_range(a.eval))
     have = set(int(s) for s in data["script_seed"])
     train, evals = sorted(train & have), sorted(evals & have)
-    X, y = SE.kernel_training_set(data, train)
-    print("training on %d kernel samples from %d scripts (%d plan timings in all)" %
-          (len(y), len(train), len(data["plan_us"])), flush=True)
-    t0 = time.perf_counter()
-    cm = CostModel(seed=a.seed)
-    hist = cm.fit(X, y, epochs=a.epochs, batch=256, lr=a.lr, seed=a.seed, verbose=True)
-    train_s = time.perf_counter() - t0
-    kpred = np.exp(cm.predict_log(data["uk_feat"]))[data["kern_uk"]]
-    c_launch = SE.fit_launch_term(data, train, kpred)
-    cm.set_launch_us(c_launch)            # the per-launch term travels with the model
-    if a.model:
+    if a.model_in:
+        # a model trained earlier (its launch term stored with it); no training scripts needed
+        cm = CostModel.load(a.model_in)
+        X, y, hist, train_s = np.zeros((0, kf.FEATURE_DIM)), np.zeros(0), [float("nan")], 0.0
+        c_launch = float(cm.state()[4])
+        print("model %s (launch term %.3f us)" % (a.model_in, c_launch), flush=True)
+    else:
+        X, y = SE.kernel_training_set(data, train)
+        print("training on %d kernel samples from %d scripts (%d plan timings in all)" %
+              (len(y), len(train), len(data["plan_us"])), flush=True)
+        t0 = time.perf_counter()
+        cm = CostModel(seed=a.seed)
+        hist = cm.fit(X, y, epochs=a.epochs, batch=256, lr=a.lr, seed=a.seed, verbose=True)
+        train_s = time.perf_counter() - t0
+        kpred = np.exp(cm.predict_log(data["uk_feat"]))[data["kern_uk"]]
+        c_launch = SE.fit_launch_term(data, train, kpred)
+        cm.set_launch_us(c_launch)            # the per-launch term travels with the model
+    if a.model and not a.model_in:
         cm.save(a.model)
         if a.model.endswith(".npz"):
             cm.save(a.model[:-4] + ".kfcm")
     table = None
     if a.table:
         T = json.load(open(a.table))
-        table = kf.routine_table([(c, tuple(e), r, u) for c, e, r, u in T["entries"]])
+        table = kf.routine_table([(e[0], tuple(e[1])) + tuple(e[2:]) for e in T["entries"]])
     per, summary = [], {}
     for seed in evals:
         m = np.where(data["cand_seed"] == seed)[0]
@@ -115,6 +124,20 @@ def cmd_evaluate(a):
             t_add = time.perf_counter() - t1
             additive = add_all[idx]
             row["additive"] = SE.rank_metrics(true, additive)
+            # the additive search: predict every candidate, compile and time the first
+            j = int(np.argsort(additive, kind="stable")[0])
+            tmp = tempfile.mkdtemp(prefix="kfeval")
+            old = os.environ.get("KF_CACHE_DIR")
+            os.environ["KF_CACHE_DIR"] = tmp
+            t1 = time.perf_counter()
+            cands.precompile([int(idx[j])])
+            t_comp = time.perf_counter() - t1
+            if old is None:
+                del os.environ["KF_CACHE_DIR"]
+            else:
+                os.environ["KF_CACHE_DIR"] = old
+            shutil.rmtree(tmp, ignore_errors=True)
+            row["additive_search_s"] = t_add + t_comp + float(walls[j])
         # search time: exhaustive vs learned top-k (compile measured in a fresh cache)
         exh = float(data["script_codegen_s"][srow] + data["script_compile_s"][srow] + data["script_load_s"][srow]
                     + walls.sum())
@@ -154,6 +177,9 @@ def cmd_evaluate(a):
             "median_rank_of_best": float(np.median(agg(meth, "rank_of_best"))),
             "mean_regret_top3": float(np.mean(agg(meth, "regret_top3")))}
     exh = np.array([r["exhaustive_search_s"] for r in per])
+    if per and "additive_search_s" in per[0]:
+        at = np.array([r["additive_search_s"] for r in per])
+        summary["additive"].update({"total_search_s": float(at.sum()), "search_time_ratio": float(exh.sum() / at.sum())})
     for k in a.topk:
         lt = np.array([r["learned_top%d_search_s" % k] for r in per])
         rg = np.array([r["learned_top%d_regret" % k] for r in per])
@@ -267,6 +293,7 @@ def main(argv=None):
     e.add_argument("--eval", default="150:200")
     e.add_argument("--out", required=True)
     e.add_argument("--model", default="")
+    e.add_argument("--model-in", default="", help="use this trained model (.kfcm or .npz) instead of training one")
     e.add_argument("--epochs", type=int, default=150)
     e.add_argument("--lr", type=float, default=1e-3)
     e.add_argument("--seed", type=int, default=0)

@@ -47,7 +47,17 @@ def sample_candidates(n: int, k: int, seed: int) -> list:
 # ---------------------------------------------------------------------------
 # routine table (additive predictor)
 # ---------------------------------------------------------------------------
-def measure_routine_table(mat_shape=(8192, 8192), vec_n=1 << 24, reps=10, device="cuda"):
+# Extra LDS (KiB) of the probe environments: a fused kernel that holds more
+# LDS than the probe itself fits fewer workgroups per CU.
+LDS_AXIS = (0, 16, 32, 64)
+
+
+def measure_routine_table(mat_shape=(8192, 8192), vec_n=1 << 24, reps=10, device="cuda", lds_axis=LDS_AXIS):
+    """Routine table of the additive predictor: every BLAS-2 routine probed in
+    each environment of MAT_ENVS (column strips, class 1; the row-resident
+    schedule with its default geometry, class 2) at every extra-LDS amount of
+    lds_axis, the FINISH launch of each environment, and the BLAS-1 routines.
+    Entries are (cls, env, routine, us per unit, lds_kb)."""
     import torch
     from . import sequences as S
     rows, cols = mat_shape
@@ -55,27 +65,37 @@ def measure_routine_table(mat_shape=(8192, 8192), vec_n=1 << 24, reps=10, device
     buf = torch.empty(max(rows * cols, vec_n) + (1 << 16), dtype=torch.float32, device=device)
     entries = []
     for env in MAT_ENVS:
-        if env[0] == 0:
-            continue  # row-resident kernels are priced with the routines of their nearest strip environment
-        p = dict(mat_k=env[0], mat_waves=env[1], mat_group=env[2], mat_rows=env[3])
-        for r in range(5):
-            us = kf.kf_routine_time(r, rows, cols, buf.data_ptr(), buf.numel() * 4, st, 2, reps, **p)
-            entries.append((1, env, r, us / (rows * cols)))
-        # FINISH: the finishing launch of a single gemv in this environment
-        q = S.bicgk(rows, cols)
-        prog = q.compile(mode="unfused", **p)
-        prog.bind(A=buf[:rows * cols].view(rows, cols), p=buf[:cols].clone(), r=buf[:rows].clone())
-        entries.append((1, env, 10, _launch_us(prog, 0, 1, reps)))
+        rowres = env[0] == 0
+        p = mat_point(env)
+        cls, tenv = (2, (0, 0, 0, 0)) if rowres else (1, tuple(env))
+        for x in lds_axis:
+            for r in range(5):
+                us = kf.kf_routine_time(r, rows, cols, buf.data_ptr(), buf.numel() * 4, st, 2, reps,
+                                        extra_lds_kb=x, **p)
+                entries.append((cls, tenv, r, us / (rows * cols), x))
+        # FINISH: the finishing launch of a column reduction in this environment
+        # (the unfused gemtv for strips, single-pass ATAX's for row-resident)
+        if rowres:
+            q = S.atax(rows, cols)
+            prog = q.compile(mode="fused", **p)
+            prog.bind(A=buf[:rows * cols].view(rows, cols), x=buf[:cols].clone())
+            entries.append((cls, tenv, 10, _launch_us(prog, 0, 1, reps), 0))
+        else:
+            q = S.bicgk(rows, cols)
+            prog = q.compile(mode="unfused", **p)
+            prog.bind(A=buf[:rows * cols].view(rows, cols), p=buf[:cols].clone(), r=buf[:rows].clone())
+            entries.append((cls, tenv, 10, _launch_us(prog, 0, 1, reps), 0))
+        del prog
     for env in VEC_ENVS:
         p = dict(vec_unroll=env[0], vec_threads=env[1], vec_grid=env[2])
         for r in range(5, 10):
             us = kf.kf_routine_time(r, vec_n, 0, buf.data_ptr(), buf.numel() * 4, st, 2, reps, **p)
-            entries.append((0, tuple(env) + (0,), r, us / vec_n))
+            entries.append((0, tuple(env) + (0,), r, us / vec_n, 0))
         q = S.axpydot(vec_n, 1.5)
         prog = q.compile(mode="fused", **p)
         x = buf[:vec_n]
         prog.bind(w=x.clone(), v=x.clone(), u=x.clone())
-        entries.append((0, tuple(env) + (0,), 10, _launch_us(prog, 0, 1, reps)))
+        entries.append((0, tuple(env) + (0,), 10, _launch_us(prog, 0, 1, reps), 0))
     return entries
 
 

@@ -163,9 +163,13 @@ static std::vector<kf_routine_entry> table() {
     std::vector<kf_routine_entry> t;
     const int mat_env[][4] = {{0, 0, 0, 0}, {1, 4, 4, 1024}, {2, 8, 2, 1024}};
     for (auto& e : mat_env)
-        for (int r = 0; r <= 4; ++r) t.push_back({1, {e[0], e[1], e[2], e[3]}, r, 1e-6f * (r + 1)});
-    for (auto& e : mat_env) t.push_back({1, {e[0], e[1], e[2], e[3]}, 10, 4.f});
-    for (int r = 5; r <= 10; ++r) t.push_back({0, {0, 0, 0, 0}, r, r == 10 ? 4.f : 1e-5f});
+        for (int x : {0, 64})
+            for (int r = 0; r <= 4; ++r) t.push_back({1, {e[0], e[1], e[2], e[3]}, r, x, 1e-6f * (r + 1 + x)});
+    for (auto& e : mat_env) t.push_back({1, {e[0], e[1], e[2], e[3]}, 10, 0, 4.f});
+    for (int x : {0, 16, 64})   // row-resident environment (default geometry)
+        for (int r = 0; r <= 4; ++r) t.push_back({2, {0, 0, 0, 0}, r, x, 2e-6f * (r + 1)});
+    t.push_back({2, {0, 0, 0, 0}, 10, 0, 3.f});
+    for (int r = 5; r <= 10; ++r) t.push_back({0, {0, 0, 0, 0}, r, 0, r == 10 ? 4.f : 1e-5f});
     return t;
 }
 

@@ -265,3 +265,49 @@ def test_batched_partials_cancel():
         got = bt.outputs(out, i)[name]
         e = WL.rel_l2(got, ref)
         assert e <= tol, (i, name, e, tol)
+
+
+@pytest.mark.parametrize("params", [dict(mat_k=1, mat_waves=4, mat_group=2, mat_rows=64),
+                                    dict(mat_sched=1, mat_waves=4, mat_group=2, mat_rows=16)])
+def test_infinite_terms_give_infinity_not_nan(params):
+    """A sum with an infinite term is that infinity, as plain addition gives:
+    the compensation of an infinite partial (inf - inf) must not turn it into
+    NaN. BiCGK with one +inf entry of A and positive p, r: the row dot of that
+    row and the column sum of that column are +inf, every other result finite
+    and within tolerance of the oracle."""
+    m, n = 300, 700
+    ld = I.padded_ld(n)
+    A = (np.abs(I.uniform_pm1(5, 0, m * ld)).reshape(m, ld) + 0.5).astype(np.float32)
+    A[:, n:] = 0.0
+    A[123, 456] = np.inf
+    p = (np.abs(I.uniform_pm1(5, 1, n)) + 0.5).astype(np.float32)
+    r = (np.abs(I.uniform_pm1(5, 2, m)) + 0.5).astype(np.float32)
+    q_seq = S.bicgk(m, n, ld=ld)
+    prog = q_seq.compile(mode="fused", **params)
+    prog.bind(A=torch.from_numpy(A).cuda(), p=torch.from_numpy(p).cuda(), r=torch.from_numpy(r).cuda())
+    outs = prog.run()
+    torch.cuda.synchronize()
+    q, s = outs["q"].cpu().numpy(), outs["s"].cpu().numpy()
+    assert np.isposinf(q[123]) and np.isposinf(s[456])
+    fq, fs = np.delete(np.arange(m), 123), np.delete(np.arange(n), 456)
+    assert np.all(np.isfinite(q[fq])) and np.all(np.isfinite(s[fs]))
+    Af = A.copy()
+    Af[123, 456] = 1.0
+    qr, sr = oracle.bicgk(Af, p, r, cols=n)
+    tol = WL.tolerance("bicgk", m, n)
+    assert WL.rel_l2(q[fq], qr[fq]) <= tol and WL.rel_l2(s[fs], sr[fs]) <= tol
+
+
+def test_infinite_dot_term_gives_infinity():
+    """AXPYDOT's r = z^T u with one infinite u entry is +inf (z > 0 there)."""
+    n = (1 << 20) + 3
+    w = (np.abs(I.uniform_pm1(6, 0, n)) + 1.0).astype(np.float32)
+    v = (np.abs(I.uniform_pm1(6, 1, n)) * 0.25).astype(np.float32)
+    u = I.uniform_pm1(6, 2, n).astype(np.float32)
+    u[777777] = np.inf
+    q_seq = S.axpydot(n, 1.5)
+    prog = q_seq.compile(mode="fused")
+    prog.bind(w=torch.from_numpy(w).cuda(), v=torch.from_numpy(v).cuda(), u=torch.from_numpy(u).cuda())
+    outs = prog.run()
+    torch.cuda.synchronize()
+    assert np.isposinf(outs["r"].cpu().numpy()[0])

@@ -27,7 +27,7 @@ def test_learned_model_beats_additive_predictor():
     cm.set_launch_us(float(d["launch_us"]))   # plan time = sum of kernels + launch term per launch
     assert hist[-1] < hist[0]
     T = json.load(open(os.path.join(DATA, "routine_table.json")))
-    table = kf.routine_table([(c, tuple(e), r, u) for c, e, r, u in T["entries"]])
+    table = kf.routine_table([(e[0], tuple(e[1])) + tuple(e[2:]) for e in T["entries"]])
     reg_l, reg_a = [], []
     for seed in np.unique(d["cand_seed"]):
         m = d["cand_seed"] == seed

@@ -14,20 +14,26 @@ from tests import seqcheck as SC
 pytestmark = pytest.mark.gpu
 
 
+LDS = (0, 64)
+
+
 @pytest.fixture(scope="module")
 def table():
-    return SE.measure_routine_table(mat_shape=(2048, 2048), vec_n=1 << 20, reps=3)
+    return SE.measure_routine_table(mat_shape=(2048, 2048), vec_n=1 << 20, reps=3, lds_axis=LDS)
 
 
 def test_routine_table_is_positive_and_plausible(table):
-    strip = [e for e in SE.MAT_ENVS if e[0]]
-    assert len(table) == len(strip) * 6 + len(SE.VEC_ENVS) * 6
-    for cls, env, r, us in table:
-        assert us > 0 and np.isfinite(us), (cls, env, r)
+    # every BLAS-2 environment (strips and the row-resident one) at each extra-LDS
+    # amount, one FINISH per environment, and the BLAS-1 routines
+    assert len(table) == len(SE.MAT_ENVS) * (5 * len(LDS) + 1) + len(SE.VEC_ENVS) * 6
+    for cls, env, r, us, x in table:
+        assert us > 0 and np.isfinite(us), (cls, env, r, x)
+    assert sum(1 for e in table if e[0] == 2) == 5 * len(LDS) + 1
     # the matrix-load probe streams at more than 0.1 TB/s even at this small shape
-    for env in strip:
-        d = {r: us for c, e, r, us in table if c == 1 and tuple(e) == env}
-        assert 4.0 / d[0] / 1e6 > 0.1, env
+    for cls in (1, 2):
+        for c, e, r, us, x in table:
+            if c == cls and r == 0:
+                assert 4.0 / us / 1e6 > 0.1, (c, e, x)
 
 
 @pytest.mark.parametrize("name", ["gemver", "bicgk", "gesummv", "axpydot"])

@@ -141,3 +141,43 @@ def test_combination_gain_by_hand():
     assert r["partitions"] == 2 and r["candidates"] == 3
     assert abs(r["uniform_est_us"] - uniform) < 1e-9 and abs(r["combination_est_us"] - comb) < 1e-9
     assert abs(r["gain"] - (1 - comb / uniform)) < 1e-12
+
+
+def test_additive_prices_row_resident_kernels_in_their_own_environment():
+    """A kernel on the row-resident schedule takes the class 2 (row-resident)
+    entries, not a strip environment's, and the extra-LDS amount nearest to its
+    own LDS use (single-pass ATAX at n = 16384 stages x in 64 KiB of LDS)."""
+    import json
+    n = 16384
+    q = S.atax(n, n)
+    p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_CODEGEN_ONLY)
+    lds = json.loads(kf.kf_plan_describe(p))["kernels"][0]["lds_bytes"]
+    assert 64 * 1024 <= lds < 80 * 1024
+    env = (0, 0, 0, 0)
+
+    def rowres(load, x):
+        return [(2, env, 0, load, x), (2, env, 1, 5e-6, x), (2, env, 2, 1e-9, x), (2, env, 3, 2e-9, x),
+                (2, env, 4, 3e-9, x)]
+    strip = [(1, ENV, r, 1.0, 0) for r in range(5)] + [(1, ENV, 10, 100.0, 0)]
+    T = kf.routine_table(strip + rowres(1e-6, 0) + rowres(2e-6, 64) + [(2, env, 10, 3.0, 0)])
+    tt = (n * n + n) * 2e-6 + n * 5e-6          # A and x at the 64 KiB entries; y stored by the finishing launch
+    tc = n * n * (1e-9 + 2e-9)
+    assert abs(kf.kf_predict_additive(p, T) - (max(tt, tc) + 3.0)) < 1e-2 * max(tt, tc)
+    # a table without row-resident entries falls back to its first strip environment
+    T1 = kf.routine_table(strip)
+    assert kf.kf_predict_additive(p, T1) > 1e6
+    kf.kf_plan_destroy(p)
+
+
+def test_additive_mode_grid_takes_row_resident_environments():
+    """KF_MODE_ADDITIVE without a grid crosses every environment of the table;
+    a class 2 environment becomes the row-resident schedule."""
+    q = S.gesummv(2048, 2048, 1.5, 0.5)
+    env = (0, 0, 0, 0)
+    strip = [(1, ENV, r, 1e-3, 0) for r in range(5)] + [(1, ENV, 10, 4.0, 0)]
+    rowres = [(2, env, r, 1e-9, 0) for r in range(5)] + [(2, env, 10, 4.0, 0)]
+    vec = [(0, (4, 256, 64, 0), r, 1e-7, 0) for r in range(5, 11)]
+    p = kf.kf_compile(q.script, mode="additive", table=kf.routine_table(strip + rowres + vec),
+                      flags=kf.KF_COMPILE_CODEGEN_ONLY)
+    assert kf.kf_plan_kernel_params(p, 0).get("mat_sched") == 1
+    kf.kf_plan_destroy(p)
