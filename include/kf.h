@@ -358,6 +358,25 @@ kf_status kf_plan_run_many(kf_plan* p, int64_t count, const int64_t* shapes, int
  * pass writes partial sums to the workspace, a small second pass adds them
  * in a fixed order (the final reduction "by extra kernel", Section 3.2.2). */
 kf_status kf_run(kf_plan* p, void* stream);
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): run the plan as
+ * kf_run does, but with a fixed array of KF_NOALLOC_SCRATCH_BYTES (32 MiB)
+ * that the library holds on each GPU it runs on, until the process ends, as
+ * the workspace (partial sums of reductions and intermediates). No workspace
+ * need be bound; the caller still binds every input and output. Allocates
+ * nothing. A plan whose kf_plan_workspace_bytes exceeds the array is refused
+ * with KF_ERR_WORKSPACE: every fused plan of the Table 1 sequences on square
+ * matrices up to 32768 fits, unfused plans that keep a matrix intermediate do
+ * not. Nothing in the array has to start at zero: each run writes every
+ * partial before it reads it. All calls on one GPU share that GPU's array and
+ * it keeps the last call's contents, so calls that overlap in time on one GPU
+ * (two streams, two threads, two plans) race and give wrong results: the
+ * caller serialises them. The array used is the current device's, which must
+ * be the device the plan was loaded on. Errors: as kf_run, plus
+ * KF_ERR_WORKSPACE (too large) and KF_ERR_HIP (the array's address could not
+ * be looked up). */
+#define KF_NOALLOC_SCRATCH_BYTES (32u << 20)
+kf_status kf_run_noalloc(kf_plan* p, void* stream);
 /* Launch only kernel k of the plan (in plan order), e.g. to time one kernel.
  * Its inputs must already hold valid data. */
 kf_status kf_run_kernel(kf_plan* p, int32_t k, void* stream);

@@ -27,7 +27,7 @@ COMMON = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 HOST_SOURCES = ["api.cpp", "plan.cpp", "codegen.cpp", "jit.cpp", "search.cpp", "costmodel.cpp", "batch.cpp"]
-DEVICE_SOURCES = ["device/kf_util.hip", "device/kf_mlp.hip", "device/kf_batch.hip", "device/kf_quant.hip"]
+DEVICE_SOURCES = ["device/kf_util.hip", "device/kf_mlp.hip", "device/kf_batch.hip", "device/kf_noalloc.hip", "device/kf_quant.hip"]
 
 
 def _embed_blocks() -> None:

@@ -903,6 +903,20 @@ kf_status kf_run(kf_plan* p, void* stream) {
     return KF_OK;
 }
 
+extern "C++" kf_status kf::plan_loaded(const kf_plan* p) {
+    if (!p) return set_error(KF_ERR_ARG, "null plan");
+    if (!p->loaded) return set_error(KF_ERR_STATE, "plan compiled without loading");
+    return KF_OK;
+}
+
+extern "C++" kf_status kf::run_on_workspace(kf_plan* p, void* ws, void* stream) {
+    CHECK(plan_loaded(p));
+    if (p->ws_need && !ws) return set_error(KF_ERR_ARG, "null workspace");
+    if ((uintptr_t)ws % 256) return set_error(KF_ERR_ALIGN, "workspace must be 256-byte aligned");
+    for (auto& k : p->ks) CHECK(launch_kernel(p, k, (hipStream_t)stream, ws));
+    return KF_OK;
+}
+
 kf_status kf_plan_run_many(kf_plan* p, int64_t count, const int64_t* shapes, int32_t nvals, const kf_value* values,
                            void* const* ptrs, const int64_t* lds, void* stream) {
     if (!p || count < 0 || nvals < 0 || (count > 0 && (!shapes || (nvals > 0 && (!values || !ptrs)))))

@@ -158,6 +158,11 @@ std::string jit_cache_ident(const KernelCode& k);
 
 // ---- errors ---------------------------------------------------------------------
 kf_status set_error(kf_status st, const std::string& msg);
+// Launch every kernel of plan p on stream with ws as its workspace (at least
+// kf_plan_workspace_bytes, 256-byte aligned) instead of the bound one.
+kf_status run_on_workspace(kf_plan* p, void* ws, void* stream);
+// KF_OK if plan p is loaded (its kernels can launch), else the error.
+kf_status plan_loaded(const kf_plan* p);
 
 // ---- plans -------------------------------------------------------------------
 struct PlanKernel {

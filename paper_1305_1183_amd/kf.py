@@ -128,6 +128,7 @@ _SIGS = {
     "kf_bind_workspace": ([_vp, _vp, _sz], _i32),
     "kf_set_const": ([_vp, _i32, _f32], _i32),
     "kf_run": ([_vp, _vp], _i32),
+    "kf_run_noalloc": ([_vp, _vp], _i32),
     "kf_run_kernel": ([_vp, _i32, _vp], _i32),
     "kf_plan_num_launches": ([_vp, _i32, _P(_i32)], _i32),
     "kf_run_launch": ([_vp, _i32, _i32, _vp], _i32),
@@ -557,6 +558,15 @@ def kf_set_const(p, v: int, value: float) -> None:
 
 def kf_run(p, stream: int = 0) -> None:
     _chk(lib().kf_run(p, _vp(stream)))
+
+
+# Size of the library's fixed per-device workspace of kf_run_noalloc
+# (KF_NOALLOC_SCRATCH_BYTES in kf.h).
+KF_NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def kf_run_noalloc(p, stream: int = 0) -> None:
+    _chk(lib().kf_run_noalloc(p, _vp(stream)))
 
 
 def kf_run_kernel(p, k: int, stream: int = 0) -> None:

@@ -244,3 +244,27 @@ def test_stream_reference_checks_its_arguments():
     with pytest.raises(kf.KFError) as e:
         kf.kf_util_stream(1, a, a + 65536, 2 * 65536)  # overlapping copy
     assert e.value.name == "KF_ERR_ALIAS"
+
+
+def test_noalloc_entry_checks_before_any_gpu_call():
+    """kf_run_noalloc: the array size in kf.h and the binding agree; a null plan,
+    a plan too large for the array and a plan compiled without loading are
+    refused on the host."""
+    text = open(os.path.join(ROOT, "include", "kf.h")).read()
+    m = re.search(r"#define KF_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == kf.KF_NOALLOC_SCRATCH_BYTES
+    assert kf.lib().kf_run_noalloc(None, None) == kf.KF_ERR_ARG
+    big = S.gemver(3072, 3072, 1.5, 0.75)              # unfused: B1 (36 MiB) lives in the workspace
+    p = kf.kf_compile(big.script, mode="unfused", flags=kf.KF_COMPILE_NO_LOAD)
+    try:
+        assert kf.kf_plan_workspace_bytes(p) > kf.KF_NOALLOC_SCRATCH_BYTES
+        assert kf.lib().kf_run_noalloc(p, None) == kf.KF_ERR_WORKSPACE
+        assert "workspace" in kf.kf_last_error()
+    finally:
+        kf.kf_plan_destroy(p)
+    small = S.bicgk(1000, 1000)
+    p = kf.kf_compile(small.script, mode="fused", flags=kf.KF_COMPILE_NO_LOAD)
+    try:
+        assert kf.lib().kf_run_noalloc(p, None) == kf.KF_ERR_STATE
+    finally:
+        kf.kf_plan_destroy(p)
