@@ -944,11 +944,7 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     for (int v : colv) push_u(vec_in, v);
     for (int v : rowv) push_u(vec_in, v);
     std::vector<int> colv_lds;
-    if (!gemtv_calls.empty()) {
-        size_t b = 0;
-        for (int v : colv)
-            if (b + (size_t)W * CW * 4 <= 128 * 1024) { colv_lds.push_back(v); b += (size_t)W * CW * 4; }
-    }
+    if (!gemtv_calls.empty() && colv.size() * (size_t)W * CW * 4 <= 128 * 1024) colv_lds = colv;
     auto cvx = [&](int v) {
         return std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end() ? F("xs%d[(cb >> 2) + 64u * j]", v)
                                                                                  : F("cv%d[j]", v);
@@ -997,9 +993,11 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     // column of lane's float4 j: cb + 256 j (32-bit: rows are at most 32768 columns)
     e.l("const unsigned cb = (unsigned)(wave * CW + lane * 4);");
     // Column-indexed vectors live in registers, KP float4 per lane each, or,
-    // in kernels that also hold gemtv accumulators in registers, in LDS (as
-    // many as fit 128 KiB; one copy per workgroup, zero past N), read at each
-    // use: that keeps the loads of a row group in registers without spills.
+    // in kernels that also hold gemtv accumulators in registers, in LDS when
+    // all of them fit 128 KiB (one copy per workgroup, zero past N), read at
+    // each use: that keeps the loads of a row group in registers without
+    // spills. (Column-major GEMVER's three vectors stay in registers: with two
+    // of them staged it measured 2% slower.)
     for (int v : colv) {
         if (std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end()) {
             e.l(F("__shared__ kf_f4 xs%d[W * KP * 64];", v));

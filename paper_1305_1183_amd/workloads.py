@@ -91,24 +91,28 @@ def rel_l2(got, ref) -> float:
 # whole runs, median of 10). A "kernel_params" list gives each plan kernel its
 # own point (Section 4.2: one implementation per fused kernel), in launch order.
 _S1 = dict(mat_k=1, mat_waves=4, mat_group=2, mat_rows=1024)      # strips, 4 waves, 2 rows per step
-_R8 = dict(mat_sched=1, mat_waves=8, mat_group=2)                   # row-resident, 8 waves
+_R16 = dict(mat_sched=1, mat_waves=16, mat_group=2)                 # row-resident, 16 waves, 2 rows per group
 _LONG = dict(mat_k=2, mat_waves=4, mat_group=2, mat_rows=2048)     # 2 KiB strips down 2048 rows
+# Row-resident points: a sweep of waves 8/16 x rows per group 1/2/4 x rows per
+# workgroup 0-128 put 16 waves, two rows per group first for every
+# row-resident kernel of the suite (GEMVER's gemv 154 us, SGEMVT's 153 us,
+# GESUMMV 301 us with 32 rows per workgroup).
 TUNED = {
-    ("bicgk", "fused"): _S1, ("bicgk", "unfused"): dict(kernel_params=[_R8, _S1]),
+    ("bicgk", "fused"): _S1, ("bicgk", "unfused"): dict(kernel_params=[_R16, _S1]),
     ("atax", "fused"): {},   # row-resident (t = A x feeds A^T t in the kernel): library defaults
-    ("atax", "unfused"): dict(kernel_params=[_R8, _S1]),
-    ("gesummv", "fused"): dict(mat_sched=1, mat_waves=8, mat_group=2),
-    ("gesummv", "unfused"): dict(mat_sched=1, mat_waves=16, mat_group=4),
+    ("atax", "unfused"): dict(kernel_params=[_R16, _S1]),
+    ("gesummv", "fused"): dict(mat_sched=1, mat_waves=16, mat_group=2, mat_rows=32),
+    ("gesummv", "unfused"): _R16,
     # K1 {ger, ger, gemtv} streams A in and B out; K2 {gemv} reads B
-    ("gemver", "fused"): dict(kernel_params=[_LONG, _R8]),
+    ("gemver", "fused"): dict(kernel_params=[_LONG, _R16]),
     # one point for all four kernels: measured faster than the per-kernel choice
     ("gemver", "unfused"): dict(mat_k=2, mat_waves=8, mat_group=2, mat_rows=1024),
     ("axpydot", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("axpydot", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("waxpby", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("waxpby", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
-    ("sgemvt", "fused"): dict(kernel_params=[_S1, dict(mat_sched=1, mat_waves=16, mat_group=4)]),
-    ("sgemvt", "unfused"): dict(kernel_params=[_S1, _R8]),
+    ("sgemvt", "fused"): dict(kernel_params=[_S1, _R16]),
+    ("sgemvt", "unfused"): dict(kernel_params=[_S1, _R16]),
     ("vadd", "fused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
     ("vadd", "unfused"): dict(vec_unroll=4, vec_threads=256, vec_grid=16384),
 }
@@ -118,14 +122,14 @@ TUNED = {
 # row-major storage of A^T with gemv and gemtv swapped. BiCGK keeps its strip
 # point, and column-major ATAX takes row-major SGEMVT's two kernels. Column-major
 # SGEMVT {gemv, gemtv} and GEMVER {ger, ger, gemv, gemtv} are one row-resident
-# kernel each. Their points come from a grid search: waves 4/8/16, rows per
-# reduction 1/2/4, rows per block 0-128. At the library defaults they take
-# 191 us and 589 us.
+# kernel each. Their points come from a grid search: waves 8/16, rows per
+# reduction 1/2/4, rows per block 0-128 (16 waves and two rows per group first
+# for both, 32 rows per block for GEMVER).
 LAYOUT_TUNED = {
     "bicgk": _S1,
     "atax": TUNED[("sgemvt", "fused")],
-    "sgemvt": dict(mat_sched=1, mat_waves=8, mat_group=2),
-    "gemver": dict(mat_sched=1, mat_waves=8, mat_group=2, mat_rows=16),
+    "sgemvt": _R16,
+    "gemver": dict(mat_sched=1, mat_waves=16, mat_group=2, mat_rows=32),
 }
 LAYOUT_SEQ = ["bicgk", "atax", "sgemvt", "gemver"]
 
