@@ -458,14 +458,17 @@ def main():
         return
     if args.tune_batch:
         from paper_1305_1183_amd import batched as B
-        table = {0: [0] * 6, 1: [0] * 6}
+        rows = {0: [0] * 6, 1: [0] * 6}
+        tiles = {0: [0] * 6, 1: [0] * 6}
         for kind in (0, 1):
             for bucket in range(6):
-                best, res = B.autotune(kind, bucket, log=log)
-                table[kind][bucket] = best
-                print(json.dumps({"kind": kind, "bucket": bucket, "n": B.bucket_median(bucket), "best_rows": best,
-                                  "candidates": [[r_, round(u, 1), round(g, 1)] for r_, u, g in res]}), flush=True)
-        print(json.dumps({"batch_tuned": table}), flush=True)
+                (bt_, br_), res = B.autotune(kind, bucket, log=log)
+                tiles[kind][bucket], rows[kind][bucket] = bt_, br_
+                print(json.dumps({"kind": kind, "bucket": bucket, "n": B.bucket_median(bucket), "best_tile": bt_,
+                                  "best_rows": br_,
+                                  "candidates": [[t_, r_, round(u, 1), round(g, 1)] for t_, r_, u, g in res]}),
+                      flush=True)
+        print(json.dumps({"batch_tuned": rows, "batch_tiles": tiles}), flush=True)
         return
     if args.tune:
         from paper_1305_1183_amd import autotune

@@ -613,11 +613,16 @@ kf_status kf_jit_stats(int64_t* modules, int64_t* kernels_compiled);
  * x, w (inputs first, then outputs; each n floats).
  *
  * Tile shape: instances fall into six size buckets (n <= 64, 128, 256, 512,
- * 1024, 2048); opts->rows[kind][bucket] is the number of rows per work item
- * (a multiple of the bucket's rows per step: 64, 32, 16, 16, 8, 4), an
- * instance with n <= rows is one item. 0 takes the library default. The
- * project's autotuner fills these per bucket. opts->grid is the number of
- * persistent workgroups (0: as many as are resident on the device);
+ * 1024, 2048). opts->tile[kind][bucket] picks the lane tile from the bucket's
+ * menu (kf_batch_tile_info): entry 0 is the default, and a whole-row tile
+ * lets 2^ltpr lanes share a row with k float4 chunks each, walking
+ * 256 / 2^ltpr rows per step and reducing row sums every 2^lg steps; a wide
+ * tile (BiCGK above n = 512) lets the four waves split each row, k float4
+ * chunks per lane, 2^lg rows per step. opts->rows[kind][bucket] is the number
+ * of rows per work item, a multiple of the tile's rows per step (0: the
+ * library default rounded up to one); an instance with n <= rows is one item.
+ * The project's autotuner chooses both per kind and bucket. opts->grid is the
+ * number of persistent workgroups (0: as many as are resident on the device);
  * opts->spin_limit bounds the wait of a dependent item (0: default, about a
  * second); a wait that runs out sets error bit 1 (kf_batch_error) and the
  * item is skipped: that run's outputs are not valid, and its counters stay
@@ -637,7 +642,12 @@ typedef struct {
     int32_t rows[2][KF_BATCH_BUCKETS];
     int32_t grid;
     uint32_t spin_limit;
+    int32_t tile[2][KF_BATCH_BUCKETS];
 } kf_batch_opts;
+/* Entry t of the tile menu of (kind, bucket): *count gets the menu's length;
+ * when t < count, out[0..4] = wide (0/1), ltpr, k, lg, rows per step. Host
+ * only. KF_ERR_ARG for a bad kind, bucket or t. */
+kf_status kf_batch_tile_info(int32_t kind, int32_t bucket, int32_t t, int32_t* count, int32_t* out);
 
 /* kind[i] in {KF_BATCH_BICGK, KF_BATCH_GEMVER}, n[i] in [1, 2048];
  * alpha/beta per instance (GEMVER; may be NULL for 1.0). Host only: no GPU

@@ -149,10 +149,10 @@ def bucket_median(bucket: int, lo: int = 32, hi: int = 2048) -> int:
     return int(round(np.sqrt(a * b)))
 
 
-def row_candidates(bucket: int, n: int) -> list:
-    """Rows per item: the bucket's rows per step times powers of two, up to one
+def row_candidates(step: int, n: int) -> list:
+    """Rows per item: the tile's rows per step times powers of two, up to one
     item per instance."""
-    r = kf.BATCH_ROWS_PER_STEP[bucket]
+    r = step
     out = []
     while True:
         out.append(r)
@@ -163,25 +163,32 @@ def row_candidates(bucket: int, n: int) -> list:
 
 
 def autotune(kind: int, bucket: int, count: int = 683, seed: int = 1, reps: int = 5, log=None):
-    """Grid search of the rows per item for one kind and size bucket on `count`
-    instances of the bucket's median size; returns (best rows, [(rows, us, GB/s)])."""
+    """Grid search over the bucket's tile menu crossed with the rows per item,
+    on `count` instances of the bucket's median size; returns ((best tile,
+    best rows), [(tile, rows, us, GB/s)])."""
     n = bucket_median(bucket)
     res = []
-    for rows in row_candidates(bucket, n):
-        rt = {0: [0] * 6, 1: [0] * 6}
-        rt[kind][bucket] = rows
-        bt = Batch(np.full(count, kind, np.int32), np.full(count, n), np.full(count, 1.25, np.float32),
-                   np.full(count, 0.75, np.float32), kf.batch_opts(rows=rt))
-        bt.fill_device(seed)
-        us = kf.kf_batch_time(bt.h, 0, False, bt.stream(), 2, reps)
-        r, w = bt.bytes()
-        res.append((rows, us, (r + w) / us / 1e3))
-        if log:
-            log("tune kind %d bucket %d n %d rows %d: %.1f us %.1f GB/s" % (kind, bucket, n, rows, us, res[-1][2]))
-        del bt
-        torch.cuda.empty_cache()
-    best = min(res, key=lambda t: t[1])[0]
-    return best, res
+    ntile = kf.kf_batch_tile_info(kind, bucket, 0)[0]
+    for t in range(ntile):
+        step = kf.kf_batch_tile_info(kind, bucket, t)[1]["rows_per_step"]
+        for rows in row_candidates(step, n):
+            rt = {0: [0] * 6, 1: [0] * 6}
+            tt = {0: [0] * 6, 1: [0] * 6}
+            rt[kind][bucket] = rows
+            tt[kind][bucket] = t
+            bt = Batch(np.full(count, kind, np.int32), np.full(count, n), np.full(count, 1.25, np.float32),
+                       np.full(count, 0.75, np.float32), kf.batch_opts(rows=rt, tiles=tt))
+            bt.fill_device(seed)
+            us = kf.kf_batch_time(bt.h, 0, False, bt.stream(), 2, reps)
+            r, w = bt.bytes()
+            res.append((t, rows, us, (r + w) / us / 1e3))
+            if log:
+                log("tune kind %d bucket %d n %d tile %d rows %d: %.1f us %.1f GB/s" % (kind, bucket, n, t, rows, us,
+                                                                                     res[-1][3]))
+            del bt
+            torch.cuda.empty_cache()
+    best = min(res, key=lambda x: x[2])
+    return (best[0], best[1]), res
 
 
 BUCKET_MAX = [b for _, b in BUCKET_RANGE]

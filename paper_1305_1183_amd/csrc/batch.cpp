@@ -46,6 +46,7 @@ struct kf_batch {
     int64_t arena_elems = 0, ws_floats = 0, sync_words = 0, nsplit = 0;
     int64_t bytes_read = 0, bytes_written = 0;
     int32_t rows[2][KFB_BUCKETS];
+    int32_t tile[2][KFB_BUCKETS];   // entry of the tile menu per kind and bucket
     int32_t grid_req = 0;
     uint32_t spin_limit = 1u << 22;
     // bound state
@@ -88,15 +89,29 @@ kf_status kf_batch_create(int64_t count, const int32_t* kind, const int64_t* n, 
         return set_error(KF_ERR_NOMEM, "host allocation failed");
     }
     for (int k = 0; k < 2; ++k)
-        for (int j = 0; j < KFB_BUCKETS; ++j) b->rows[k][j] = kDefaultRows[k][j];
+        for (int j = 0; j < KFB_BUCKETS; ++j) {
+            b->rows[k][j] = kDefaultRows[k][j];
+            b->tile[k][j] = 0;
+        }
     if (opts) {
         for (int k = 0; k < 2; ++k)
             for (int j = 0; j < KFB_BUCKETS; ++j) {
-                const int r = opts->rows[k][j];
-                if (r == 0) continue;
-                if (r < 0 || r % kfb_rows_per_iter(j)) {
+                const int t = opts->tile[k][j];
+                if (t < 0 || t >= kfb_tile_count(k, j)) {
                     delete b;
-                    return set_error(KF_ERR_ARG, "rows per block must be a positive multiple of the bucket's rows per step");
+                    return set_error(KF_ERR_ARG, "tile is not on the menu of this kind and size bucket");
+                }
+                b->tile[k][j] = t;
+                const int r = opts->rows[k][j];
+                const int step = kfb_rows_per_step(k, j, t);
+                if (r == 0) {
+                    // the default rows per block, rounded up to the tile's rows per step
+                    b->rows[k][j] = (kDefaultRows[k][j] + step - 1) / step * step;
+                    continue;
+                }
+                if (r < 0 || r % step) {
+                    delete b;
+                    return set_error(KF_ERR_ARG, "rows per block must be a positive multiple of the tile's rows per step");
                 }
                 b->rows[k][j] = r;
             }
@@ -127,6 +142,7 @@ kf_status kf_batch_create(int64_t count, const int32_t* kind, const int64_t* n, 
             // the start of the next (stores of B and loads of A stay line-aligned)
             I.ld = (int32_t)((n[i] + 31) / 32 * 32);
             I.bucket = kfb_bucket(I.n);
+            I.tile = b->tile[I.kind][I.bucket];
             I.rows = b->rows[I.kind][I.bucket];
             I.nblk = (I.n + I.rows - 1) / I.rows;
             if (I.nblk == 1) I.rows = I.n;
@@ -253,6 +269,20 @@ kf_status kf_batch_bytes(const kf_batch* b, int64_t* read, int64_t* written) {
     return KF_OK;
 }
 
+kf_status kf_batch_tile_info(int32_t kind, int32_t bucket, int32_t t, int32_t* count, int32_t* out) {
+    if (kind < 0 || kind > 1 || bucket < 0 || bucket >= KFB_BUCKETS || t < 0 || !count)
+        return set_error(KF_ERR_ARG, "bad kind, bucket or tile");
+    const int c = kfb_tile_count(kind, bucket);
+    if (t < c) {
+        if (!out) return set_error(KF_ERR_ARG, "null argument");
+        const kfb_tile& x = kfb_tile_menu[kind][bucket][t];
+        out[0] = x.wide; out[1] = x.ltpr; out[2] = x.k; out[3] = x.lg;
+        out[4] = kfb_rows_per_step(kind, bucket, t);
+    }
+    *count = c;
+    return KF_OK;
+}
+
 kf_status kf_batch_describe(const kf_batch* b, char* buf, size_t len, size_t* needed) {
     if (!b) return set_error(KF_ERR_ARG, "null batch");
     int64_t per[2][KFB_BUCKETS] = {{0}}, split[2] = {0, 0}, ph1 = 0;
@@ -274,6 +304,16 @@ kf_status kf_batch_describe(const kf_batch* b, char* buf, size_t len, size_t* ne
     for (int k = 0; k < 2; ++k) {
         o << (k ? ", " : "") << "\"" << names[k] << "\": [";
         for (int j = 0; j < KFB_BUCKETS; ++j) o << (j ? ", " : "") << b->rows[k][j];
+        o << "]";
+    }
+    o << "}, \"tiles\": {";
+    for (int k = 0; k < 2; ++k) {
+        o << (k ? ", " : "") << "\"" << names[k] << "\": [";
+        for (int j = 0; j < KFB_BUCKETS; ++j) {
+            const kfb_tile& t = kfb_tile_menu[k][j][b->tile[k][j]];
+            o << (j ? ", " : "") << "\"" << (t.wide ? "wide" : "rows") << " tpr" << (t.wide ? 256 : (1 << t.ltpr))
+              << " k" << (int)t.k << " g" << (1 << t.lg) << "\"";
+        }
         o << "]";
     }
     o << "}, \"arena_elems\": " << b->arena_elems << ", \"workspace_bytes\": " << b->ws_bytes()

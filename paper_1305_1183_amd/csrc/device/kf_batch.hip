@@ -575,12 +575,45 @@ __device__ void kfb_w_bicgk(const kfb_inst& I, int blk, float* __restrict__ aren
     }
 }
 
-template <int LTPR, int K, int LG>
-__device__ __forceinline__ void kfb_item_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
+// Tile T of the menu of (KIND, B), instantiated from the shared table.
+template <int KIND, int B, int T>
+__device__ __forceinline__ void kfb_tile_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
                                              unsigned* sync, unsigned spin_limit, Shared& sh) {
-    if (phase == KFB_BICGK) kfb_bicgk<LTPR, K, LG>(I, blk, arena, ws, sync, sh);
-    else if (phase == KFB_GEMVER_K1) kfb_gemver_k1<LTPR, K, LG>(I, blk, arena, ws, sync, sh);
-    else kfb_gemver_k2<LTPR, K, LG>(I, blk, arena, sync, spin_limit, sh);
+    constexpr kfb_tile x = kfb_tile_menu[KIND][B][T];
+    if constexpr (x.k == 0) {
+        return;   // not on the menu (the host never selects it)
+    } else if constexpr (x.wide) {
+        kfb_w_bicgk<x.k, x.lg>(I, blk, arena, ws, sync, sh);
+    } else if constexpr (KIND == 0) {
+        kfb_bicgk<x.ltpr, x.k, x.lg>(I, blk, arena, ws, sync, sh);
+    } else if (phase == KFB_GEMVER_K1) {
+        kfb_gemver_k1<x.ltpr, x.k, x.lg>(I, blk, arena, ws, sync, sh);
+    } else {
+        kfb_gemver_k2<x.ltpr, x.k, x.lg>(I, blk, arena, sync, spin_limit, sh);
+    }
+}
+
+template <int KIND, int B>
+__device__ __forceinline__ void kfb_bucket_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
+                                               unsigned* sync, unsigned spin_limit, Shared& sh) {
+    switch (I.tile) {
+    case 1: kfb_tile_run<KIND, B, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    case 2: kfb_tile_run<KIND, B, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    default: kfb_tile_run<KIND, B, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    }
+}
+
+template <int KIND>
+__device__ __forceinline__ void kfb_kind_run(const kfb_inst& I, int phase, int blk, float* arena, float* ws,
+                                             unsigned* sync, unsigned spin_limit, Shared& sh) {
+    switch (I.bucket) {
+    case 0: kfb_bucket_run<KIND, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    case 1: kfb_bucket_run<KIND, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    case 2: kfb_bucket_run<KIND, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    case 3: kfb_bucket_run<KIND, 3>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    case 4: kfb_bucket_run<KIND, 4>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    default: kfb_bucket_run<KIND, 5>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
+    }
 }
 
 // Three waves per SIMD (168 VGPRs, two of them spilled): the whole-row GEMVER
@@ -604,22 +637,11 @@ kfb_kernel(const kfb_inst* __restrict__ insts, const kfb_item* __restrict__ item
         const kfb_inst I = insts[item.inst];
         const int phase = item.phase_blk >> 24;
         const int blk = item.phase_blk & 0xffffff;
-        switch (I.bucket) {
-        case 0: kfb_item_run<4, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        case 1: kfb_item_run<5, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        case 2: kfb_item_run<6, 1, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        case 3: kfb_item_run<6, 2, 2>(I, phase, blk, arena, ws, sync, spin_limit, sh); break;
-        // BiCGK takes the wide tiles above n = 512; GEMVER keeps whole rows per
-        // wave there, which stores B faster (measured per bucket)
-        case 4:
-            if (phase == KFB_BICGK) kfb_w_bicgk<1, 3>(I, blk, arena, ws, sync, sh);
-            else kfb_item_run<6, 4, 1>(I, phase, blk, arena, ws, sync, spin_limit, sh);
-            break;
-        default:
-            if (phase == KFB_BICGK) kfb_w_bicgk<2, 2>(I, blk, arena, ws, sync, sh);
-            else kfb_item_run<6, 8, 0>(I, phase, blk, arena, ws, sync, spin_limit, sh);
-            break;
-        }
+        // the instance's tile from the menu of its kind and size bucket (by
+        // default BiCGK takes the wide tiles above n = 512; GEMVER keeps whole
+        // rows per wave there, which stores B faster, measured per bucket)
+        if (I.kind == 0) kfb_kind_run<0>(I, phase, blk, arena, ws, sync, spin_limit, sh);   // BiCGK
+        else kfb_kind_run<1>(I, phase, blk, arena, ws, sync, spin_limit, sh);
         if (!persistent) break;
         __syncthreads();
     }

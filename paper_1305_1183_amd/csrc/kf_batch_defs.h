@@ -40,7 +40,7 @@ struct kfb_inst {
     int32_t rows;    // rows per block
     int32_t sync;    // index of the counters of a split instance, -1 if whole
     float alpha, beta;
-    int32_t pad;
+    int32_t tile;    // entry of the tile menu of (kind, bucket)
     int64_t a, b;    // arena offsets of A and B (floats)
     int64_t v[8];    // arena offsets of the vectors
     int64_t ws;      // workspace offset of the column partials (floats), -1 if whole
@@ -54,8 +54,42 @@ struct kfb_item {
 static inline int kfb_bucket(int n) {
     return n <= 64 ? 0 : n <= 128 ? 1 : n <= 256 ? 2 : n <= 512 ? 3 : n <= 1024 ? 4 : 5;
 }
-// rows one workgroup iteration covers in each bucket (the tile's row extent)
-static inline int kfb_rows_per_iter(int bucket) {
-    static const int r[KFB_BUCKETS] = {64, 32, 16, 16, 8, 4};
-    return r[bucket];
+// Tile menu per kind and size bucket; entry 0 is the default. A whole-row tile
+// <LTPR, K, LG> lets TPR = 2^LTPR lanes share a row, K float4 chunks per lane
+// (TPR K 4 >= the bucket's largest n), and walks 256 / TPR rows per step, G =
+// 2^LG steps per row reduction. A wide tile (BiCGK above n = 512) lets the
+// four waves split each row, K float4 chunks per lane of the workgroup, G =
+// 2^LG rows per step. Entries with k = 0 are absent.
+#define KFB_TILES 3
+struct kfb_tile {
+    int8_t wide, ltpr, k, lg;
+};
+constexpr kfb_tile kfb_tile_menu[2][KFB_BUCKETS][KFB_TILES] = {
+    {   // BiCGK
+        {{0, 4, 1, 2}, {0, 4, 1, 1}, {0, 3, 2, 2}},
+        {{0, 5, 1, 2}, {0, 5, 1, 1}, {0, 4, 2, 2}},
+        {{0, 6, 1, 2}, {0, 6, 1, 1}, {0, 5, 2, 2}},
+        {{0, 6, 2, 2}, {0, 6, 2, 1}, {0, 5, 4, 1}},
+        {{1, 0, 1, 3}, {1, 0, 1, 2}, {0, 6, 4, 1}},
+        {{1, 0, 2, 2}, {1, 0, 2, 1}, {0, 6, 8, 0}},
+    },
+    {   // GEMVER
+        {{0, 4, 1, 2}, {0, 4, 1, 1}, {0, 3, 2, 2}},
+        {{0, 5, 1, 2}, {0, 5, 1, 1}, {0, 4, 2, 2}},
+        {{0, 6, 1, 2}, {0, 6, 1, 1}, {0, 5, 2, 2}},
+        {{0, 6, 2, 2}, {0, 6, 2, 1}, {0, 5, 4, 1}},
+        {{0, 6, 4, 1}, {0, 6, 4, 0}, {0, 5, 8, 0}},
+        {{0, 6, 8, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    },
+};
+// number of tiles on the menu of (kind, bucket)
+static inline int kfb_tile_count(int kind, int bucket) {
+    int c = 0;
+    for (int t = 0; t < KFB_TILES; ++t) c += kfb_tile_menu[kind][bucket][t].k > 0;
+    return c;
+}
+// rows one workgroup step covers with tile t of (kind, bucket) (the tile's row extent)
+static inline int kfb_rows_per_step(int kind, int bucket, int t) {
+    const kfb_tile& x = kfb_tile_menu[kind][bucket][t];
+    return x.wide ? (1 << x.lg) : ((KFB_THREADS >> x.ltpr) << x.lg);
 }

@@ -28,16 +28,19 @@ def main(argv=None):
     ap.add_argument("chunks", nargs="+")
     ap.add_argument("--train", default="0:40")
     ap.add_argument("--eval", default="150:160")
-    ap.add_argument("--launch-us", type=float, default=0.41)
+    ap.add_argument("--launch-us", type=float, default=None,
+                    help="per-launch term of a plan's time (default: fitted on the training scripts' timings)")
     a = ap.parse_args(argv)
     data = SE.merge([dict(np.load(f, allow_pickle=False)) for f in a.chunks])
     X, y = SE.kernel_training_set(data, _range(a.train))
+    launch = a.launch_us if a.launch_us is not None else SE.fit_launch_term(data, _range(a.train))
     ev = [s for s in _range(a.eval) if s in set(int(v) for v in data["script_seed"])]
     m = np.isin(data["cand_seed"], ev)
     np.savez_compressed(a.out, X=X.astype(np.float32), y=y.astype(np.float32),
                         cand_seed=data["cand_seed"][m], cand_idx=data["cand_idx"][m],
-                        plan_us=data["plan_us"][m].astype(np.float32), launch_us=np.float32(a.launch_us))
-    print("train kernels %d, eval scripts %d, eval candidates %d" % (len(y), len(ev), int(m.sum())))
+                        plan_us=data["plan_us"][m].astype(np.float32), launch_us=np.float32(launch))
+    print("train kernels %d, eval scripts %d, eval candidates %d, launch term %.3f us" %
+          (len(y), len(ev), int(m.sum()), launch))
 
 
 if __name__ == "__main__":

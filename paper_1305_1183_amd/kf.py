@@ -186,6 +186,7 @@ _SIGS = {
     "kf_batch_graph_launch": ([_vp, _i32, _vp], _i32),
     "kf_batch_time": ([_vp, _i32, _i32, _vp, _i32, _i32, _P(_f32)], _i32),
     "kf_batch_error": ([_vp, _vp, _P(_u32)], _i32),
+    "kf_batch_tile_info": ([_i32, _i32, _i32, _P(_i32), _P(_i32)], _i32),
 }
 EXPORTED = sorted(_SIGS)
 
@@ -666,24 +667,39 @@ def kf_util_stream(kind: int, dst: int, src: int, nbytes: int, stream: int = 0) 
 # ---- batched uneven sizes ------------------------------------------------------------
 KF_BATCH_BICGK, KF_BATCH_GEMVER = 0, 1
 BATCH_BUCKETS = 6
-BATCH_ROWS_PER_STEP = (64, 32, 16, 16, 8, 4)
+BATCH_ROWS_PER_STEP = (64, 32, 16, 16, 8, 4)   # of each bucket's default tile (menu entry 0)
 BATCH_OPERANDS = {0: ["A", "B_unused", "p", "r", "q", "s"],
                   1: ["A", "B", "u1", "v1", "u2", "v2", "y", "z", "x", "w"]}
 
 
 class kf_batch_opts(ctypes.Structure):
-    _fields_ = [("rows", (_i32 * BATCH_BUCKETS) * 2), ("grid", _i32), ("spin_limit", _u32)]
+    _fields_ = [("rows", (_i32 * BATCH_BUCKETS) * 2), ("grid", _i32), ("spin_limit", _u32),
+                ("tile", (_i32 * BATCH_BUCKETS) * 2)]
 
 
-def batch_opts(rows=None, grid: int = 0, spin_limit: int = 0):
-    """rows: {kind: [rows per bucket]} (0 = library default)."""
+def batch_opts(rows=None, grid: int = 0, spin_limit: int = 0, tiles=None):
+    """rows: {kind: [rows per bucket]} (0 = library default); tiles: {kind:
+    [tile menu entry per bucket]} (0 = the bucket's default tile)."""
     o = kf_batch_opts()
     for k, lst in (rows or {}).items():
         for j, r in enumerate(lst):
             o.rows[k][j] = int(r)
+    for k, lst in (tiles or {}).items():
+        for j, t in enumerate(lst):
+            o.tile[k][j] = int(t)
     o.grid = int(grid)
     o.spin_limit = int(spin_limit)
     return o
+
+
+def kf_batch_tile_info(kind: int, bucket: int, t: int):
+    """(menu length, entry t as dict or None past the end)."""
+    c = _i32()
+    out = (_i32 * 5)()
+    _chk(lib().kf_batch_tile_info(kind, bucket, t, ctypes.byref(c), out))
+    if t >= c.value:
+        return c.value, None
+    return c.value, dict(wide=out[0], ltpr=out[1], k=out[2], lg=out[3], rows_per_step=out[4])
 
 
 def kf_batch_create(kinds, ns, alphas=None, betas=None, opts=None):

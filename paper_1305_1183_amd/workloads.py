@@ -279,12 +279,12 @@ def precision_arrays(fmt, stored, vecs):
 BATCH_COUNTS = (4096, 4096)
 BATCH_SEED = 3000
 # rows per work item for (BiCGK, GEMVER) x size bucket (n <= 64, 128, 256,
-# 512, 1024, 2048) (0 = library default). Alone, every bucket runs fastest as
-# whole instances (the batch autotuner's pick); in the mixed batch, halving the
-# instances above n = 1024 shortens the tail of the persistent launch, which
-# timing the mixed batch over the split choices of the two largest buckets
-# confirmed.
-BATCH_TUNED = {0: [64, 128, 256, 512, 1024, 1024], 1: [64, 128, 256, 512, 1024, 1024]}
+# 512, 1024, 2048) (0 = library default). Alone, every bucket but GEMVER's
+# n <= 1024 runs fastest as whole instances (the batch autotuner's pick); in
+# the mixed batch, halving the instances above n = 1024 shortens the tail of
+# the persistent launch, which timing the mixed batch over the split choices
+# of the two largest buckets confirmed.
+BATCH_TUNED = {0: [64, 128, 256, 512, 1024, 1024], 1: [64, 128, 256, 512, 512, 1024]}
 
 
 # The per-instance launch loop (the baseline) launches one instance at a time,
@@ -293,6 +293,17 @@ BATCH_TUNED = {0: [64, 128, 256, 512, 1024, 1024], 1: [64, 128, 256, 512, 1024, 
 BATCH_LOOP_ROWS = {0: [0] * 6, 1: [0] * 6}
 
 
+# Lane tile per kind and bucket (entries of the library's tile menus, 0 = the
+# default tile), from the same autotuner, which now crosses each bucket's tile
+# menu with the rows per item (`bench.py --tune-batch`,
+# profiles/batch_autotune_buckets.jsonl). GEMVER's n <= 1024 bucket has its
+# optimum inside the grid: tile 1 (whole rows, no row grouping) with 512-row
+# items.
+BATCH_TILES = {0: [0, 0, 2, 2, 2, 0], 1: [0, 2, 2, 2, 1, 0]}
+
+
 def batch_opts(grid: int = 0, loop: bool = False):
     from . import kf
-    return kf.batch_opts(rows=BATCH_LOOP_ROWS if loop else BATCH_TUNED, grid=grid)
+    if loop:
+        return kf.batch_opts(rows=BATCH_LOOP_ROWS, grid=grid)
+    return kf.batch_opts(rows=BATCH_TUNED, tiles=BATCH_TILES, grid=grid)

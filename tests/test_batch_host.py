@@ -102,3 +102,42 @@ def test_unbound_run_is_an_error():
     b = make(np.array([0], np.int32), np.array([10]))
     with pytest.raises(kf.KFError):
         kf.kf_batch_run(b.h, 0, 0)
+
+
+def test_tile_menu_covers_each_bucket():
+    """Every tile on a bucket's menu covers the bucket's widest rows (whole-row:
+    2^ltpr lanes x k float4 >= n; wide: 256 lanes x k float4), reduces over at
+    most its lanes, and entry 0 keeps the default rows per step."""
+    top = [64, 128, 256, 512, 1024, 2048]
+    for kind in (0, 1):
+        for b in range(6):
+            count, _ = kf.kf_batch_tile_info(kind, b, 0)
+            assert count >= 1
+            for t in range(count):
+                _, x = kf.kf_batch_tile_info(kind, b, t)
+                lanes = 256 if x["wide"] else 1 << x["ltpr"]
+                assert lanes * x["k"] * 4 >= top[b], (kind, b, t, x)
+                assert x["wide"] or x["lg"] <= x["ltpr"]
+                assert not (x["wide"] and kind == 1), "GEMVER has no wide tile"
+                step = (1 << x["lg"]) if x["wide"] else (256 >> x["ltpr"]) << x["lg"]
+                assert x["rows_per_step"] == step
+            assert kf.kf_batch_tile_info(kind, b, 0)[1]["rows_per_step"] == RPS[b]
+            assert kf.kf_batch_tile_info(kind, b, count)[1] is None
+
+
+def test_tile_choice_checks_and_describe():
+    import json
+    kinds, ns = np.array([0, 1, 0, 1], np.int32), np.array([40, 40, 1500, 700])
+    # tile 2 of bucket 0 steps 128 rows: rows per block must be a multiple of 128
+    with pytest.raises(kf.KFError) as e:
+        make(kinds, ns, rows={0: [64, 0, 0, 0, 0, 0]}, tiles={0: [2, 0, 0, 0, 0, 0]})
+    assert e.value.name == "KF_ERR_ARG"
+    with pytest.raises(kf.KFError):
+        make(kinds, ns, tiles={1: [0, 0, 0, 0, 0, 1]})          # GEMVER's bucket 5 has one tile
+    with pytest.raises(kf.KFError):
+        make(kinds, ns, tiles={0: [3, 0, 0, 0, 0, 0]})
+    b = make(kinds, ns, tiles={0: [2, 0, 0, 0, 0, 2], 1: [1, 0, 0, 0, 2, 0]})
+    d = json.loads(kf.kf_batch_describe(b.h))
+    assert d["tiles"]["bicgk"][0] == "rows tpr8 k2 g4" and d["tiles"]["bicgk"][5] == "rows tpr64 k8 g1"
+    assert d["tiles"]["gemver"][4] == "rows tpr32 k8 g1"
+    assert d["rows"]["bicgk"][0] == 128                          # default 64 rounded up to the tile's step

@@ -91,6 +91,21 @@ def test_batch_graph_replays(which):
     run_case(small_batch(), which, graph=True, reps=3)
 
 
+def _menu(kind, bucket):
+    return [kf.kf_batch_tile_info(kind, bucket, t)[1] for t in range(kf.kf_batch_tile_info(kind, bucket, 0)[0])]
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("split", [False, True])
+def test_every_tile_on_the_menus(tile, split):
+    """Each non-default tile of every bucket's menu, on whole instances and on
+    instances split into blocks of one tile step, matches the oracle."""
+    tiles = {k: [min(tile, len(_menu(k, b)) - 1) for b in range(6)] for k in (0, 1)}
+    rows = {k: [(_menu(k, b)[tiles[k][b]]["rows_per_step"] if split else 2048) for b in range(6)] for k in (0, 1)}
+    print("case batch tiles", tiles, "rows", rows, flush=True)
+    run_case(small_batch(seed=9, opts=kf.batch_opts(rows=rows, tiles=tiles)), 0, reps=2)
+
+
 @pytest.mark.parametrize("opts", [dict(rows={0: RPS, 1: RPS}), dict(rows={0: [2048] * 6, 1: [2048] * 6}),
                                   dict(grid=1), dict(grid=3, rows={0: RPS, 1: RPS})],
                          ids=["all-split", "all-whole", "grid1", "grid3-split"])
