@@ -47,7 +47,11 @@ def parse():
     ap.add_argument("--batched-no-loop", action="store_true",
                     help="with --batched: time only the persistent launch (for counter runs)")
     ap.add_argument("--tune-batch", action="store_true",
-                    help="grid-search the rows per work item of every size bucket of the batched launch")
+                    help="grid-search the lane tile and rows per work item of every size bucket of the batched "
+                         "launch, bucket by bucket on instances of the bucket's median size")
+    ap.add_argument("--tune-batch-mix", action="store_true",
+                    help="coordinate search of the lane tile and rows per work item of every size bucket on the "
+                         "mixed 4096 + 4096 batch itself")
     ap.add_argument("--layout", action="store_true",
                     help="row- vs column-major A: fused BiCGK, ATAX, SGEMVT, GEMVER at n = 16384")
     ap.add_argument("--precision", action="store_true",
@@ -455,6 +459,15 @@ def main():
         return
     if args.batched:
         batched_suite(args, torch, kf, WL, dev)
+        return
+    if args.tune_batch_mix:
+        from paper_1305_1183_amd import batched as B
+        kinds, ns, al, be = B.make_instances(*WL.BATCH_COUNTS, seed=WL.BATCH_SEED)
+        rows, tiles, best, hist = B.tune_mix(kinds, ns, al, be, WL.BATCH_SEED, WL.BATCH_TUNED, WL.BATCH_TILES,
+                                             log=log)
+        for kind, b, t, r, us in hist:
+            print(json.dumps({"kind": kind, "bucket": b, "tile": t, "rows": r, "us": round(us, 1)}), flush=True)
+        print(json.dumps({"batch_tuned": rows, "batch_tiles": tiles, "best_us": round(best, 1)}), flush=True)
         return
     if args.tune_batch:
         from paper_1305_1183_amd import batched as B

@@ -19,7 +19,8 @@ MAT_GRID = [dict(mat_k=k, mat_waves=w, mat_group=g, mat_rows=r)
            [dict(mat_k=k, mat_waves=w, mat_group=g, mat_rows=r)      # few waves, long row ranges:
             for k in (1, 2)                                          # fewer concurrent DRAM streams
             for (w, g, r) in ((4, 2, 1024), (4, 2, 2048), (2, 4, 2048), (8, 2, 2048), (4, 4, 2048), (4, 2, 4096))] + \
-           [dict(mat_sched=1, mat_waves=w, mat_group=g) for w in (8, 16) for g in (1, 2, 4)]
+           [dict(mat_sched=1, mat_waves=w, mat_group=g, mat_rows=r)                # row-resident points
+            for w in (8, 16) for g in (1, 2, 4) for r in (0, 16, 32, 64, 128)]
 VEC_GRID = [dict(vec_unroll=u, vec_threads=t, vec_grid=g)
             for u in (2, 4, 8) for t in (256, 512) for g in (1024, 2048, 4096)] + \
            [dict(vec_unroll=u, vec_threads=256, vec_grid=g) for u in (4, 8) for g in (8192, 16384)]

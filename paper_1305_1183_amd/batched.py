@@ -191,6 +191,62 @@ def autotune(kind: int, bucket: int, count: int = 683, seed: int = 1, reps: int 
     return (best[0], best[1]), res
 
 
+def tune_mix(kinds, ns, alpha, beta, seed: int, rows0: dict, tiles0: dict, reps: int = 5, tol: float = 0.003,
+             log=None):
+    """Coordinate search of (tile, rows per item) per kind and size bucket on
+    the mixed batch itself: from (rows0, tiles0), each bucket in turn (largest
+    first, GEMVER first) tries every tile of its menu with rows per item from
+    the tile's step up to the whole instance, keeping a change only when the
+    whole launch gets more than `tol` faster. The arena is filled once and
+    shared by every configuration (its layout depends on the sizes only).
+    Returns (rows, tiles, best_us, [(kind, bucket, tile, rows, us)])."""
+    rows = {k: list(v) for k, v in rows0.items()}
+    tiles = {k: list(v) for k, v in tiles0.items()}
+    base = Batch(kinds, ns, alpha, beta, kf.batch_opts(rows=rows, tiles=tiles))
+    base.fill_device(seed)
+    arena = base.arena
+    nmax = [int(max([n for n, k in zip(ns, kinds) if k == kind and bucket_of(n) == b] or [0]))
+            for kind in (0, 1) for b in range(6)]
+
+    def timed(r, t):
+        bt = Batch(kinds, ns, alpha, beta, kf.batch_opts(rows=r, tiles=t))
+        bt.arena = arena
+        bt._bind()
+        us = kf.kf_batch_time(bt.h, 0, False, bt.stream(), 2, reps)
+        del bt
+        return us
+
+    best = timed(rows, tiles)
+    hist = [(-1, -1, -1, -1, best)]
+    if log:
+        log("mix start: %.1f us" % best)
+    for kind in (1, 0):
+        for b in reversed(range(6)):
+            top = nmax[kind * 6 + b]
+            if top == 0:
+                continue
+            ntile = kf.kf_batch_tile_info(kind, b, 0)[0]
+            for t in range(ntile):
+                step = kf.kf_batch_tile_info(kind, b, t)[1]["rows_per_step"]
+                for r in row_candidates(step, top):
+                    if t == tiles[kind][b] and r == rows[kind][b]:
+                        continue
+                    rr = {k: list(v) for k, v in rows.items()}
+                    tt = {k: list(v) for k, v in tiles.items()}
+                    rr[kind][b], tt[kind][b] = r, t
+                    us = timed(rr, tt)
+                    hist.append((kind, b, t, r, us))
+                    if log:
+                        log("mix kind %d bucket %d tile %d rows %d: %.1f us (best %.1f)" % (kind, b, t, r, us, best))
+                    if us < best * (1.0 - tol):
+                        best, rows, tiles = us, rr, tt
+    return rows, tiles, best, hist
+
+
+def bucket_of(n: int) -> int:
+    return next(i for i, (a, b) in enumerate(BUCKET_RANGE) if n <= b)
+
+
 BUCKET_MAX = [b for _, b in BUCKET_RANGE]
 
 

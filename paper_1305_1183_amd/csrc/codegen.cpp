@@ -136,8 +136,16 @@ static void emit_colpart_finish(Emitter& f, const std::vector<int>& gemtv_calls,
     bool first = true;
     for (int c : gemtv_calls) {
         const size_t off = ws_off.at(c);
+        // eight partials are loaded before they are added, so their loads are in
+        // flight together rather than one latency per row block
         f.l(F("kf_cs4 pc%d = kf_cs4_init(kf_zero4());", c));
-        f.l(F("if (cc < N) for (long b = wave; b < NB; b += FW) pc%d = kf_cs4_add(pc%d, kf_ld4(ws + %zuL + b * NP + cc));", c, c, off));
+        f.l("if (cc < N) {");
+        f.l("  for (long b0 = wave; b0 < NB; b0 += 8 * FW) {");
+        f.l("    kf_f4 pv[8];");
+        f.l(F("    for (int i = 0; i < 8; ++i) { const long b = b0 + (long)i * FW; pv[i] = b < NB ? kf_ld4(ws + %zuL + b * NP + cc) : kf_zero4(); }", off));
+        f.l(F("    for (int i = 0; i < 8; ++i) if (b0 + (long)i * FW < NB) pc%d = kf_cs4_add(pc%d, pv[i]);", c, c));
+        f.l("  }");
+        f.l("}");
         if (!first) f.l("__syncthreads();");
         first = false;
         f.l(F("kf_fr[0][wave][lane] = pc%d.s; kf_fr[1][wave][lane] = pc%d.c;", c, c));

@@ -280,11 +280,14 @@ BATCH_COUNTS = (4096, 4096)
 BATCH_SEED = 3000
 # rows per work item for (BiCGK, GEMVER) x size bucket (n <= 64, 128, 256,
 # 512, 1024, 2048) (0 = library default). Alone, every bucket but GEMVER's
-# n <= 1024 runs fastest as whole instances (the batch autotuner's pick); in
-# the mixed batch, halving the instances above n = 1024 shortens the tail of
-# the persistent launch, which timing the mixed batch over the split choices
-# of the two largest buckets confirmed.
-BATCH_TUNED = {0: [64, 128, 256, 512, 1024, 1024], 1: [64, 128, 256, 512, 512, 1024]}
+# n <= 1024 runs fastest as whole instances (`bench.py --tune-batch`). The
+# mixed batch wants otherwise: the coordinate search on the mixed batch itself
+# (`bench.py --tune-batch-mix`, profiles/batch_autotune_mix.jsonl) cut GEMVER
+# instances above n = 512 into 256-row items (6.05 ms against 6.38 ms from
+# halved instances), which spreads the largest instances' work over more
+# workgroups and shortens the tail of the launch, and kept every default tile
+# (the per-bucket picks made the mix 13% slower).
+BATCH_TUNED = {0: [64, 128, 256, 512, 1024, 1024], 1: [64, 128, 256, 512, 256, 256]}
 
 
 # The per-instance launch loop (the baseline) launches one instance at a time,
@@ -294,12 +297,9 @@ BATCH_LOOP_ROWS = {0: [0] * 6, 1: [0] * 6}
 
 
 # Lane tile per kind and bucket (entries of the library's tile menus, 0 = the
-# default tile), from the same autotuner, which now crosses each bucket's tile
-# menu with the rows per item (`bench.py --tune-batch`,
-# profiles/batch_autotune_buckets.jsonl). GEMVER's n <= 1024 bucket has its
-# optimum inside the grid: tile 1 (whole rows, no row grouping) with 512-row
-# items.
-BATCH_TILES = {0: [0, 0, 2, 2, 2, 0], 1: [0, 2, 2, 2, 1, 0]}
+# default tile), from the mixed-batch search above; no other tile beat a
+# default by more than 0.3% there.
+BATCH_TILES = {0: [0] * 6, 1: [0] * 6}
 
 
 def batch_opts(grid: int = 0, loop: bool = False):
