@@ -56,6 +56,9 @@ def parse():
                     help="row- vs column-major A: fused BiCGK, ATAX, SGEMVT, GEMVER at n = 16384")
     ap.add_argument("--precision", action="store_true",
                     help="reduced-precision suite: BiCGK and GEMVER at n = 32768 with A in FP32, BF16, FP8-E4M3")
+    ap.add_argument("--wide-rows", action="store_true",
+                    help="row-resident kernels at n = 32768: the geometry the library picks against the same "
+                         "geometry requested explicitly (which the generator emits unadjusted)")
     return ap.parse_args()
 
 
@@ -195,6 +198,46 @@ def precision_suite(args, torch, kf, S, WL, dev):
         del stored
     print(json.dumps({"metric": "reduced-precision A: GB/s and speedup vs unfused (not the headline)",
                       "n": n, "results": res, "unit": "GB/s", "peak": HBM_PEAK_GBPS}), flush=True)
+
+
+def wide_rows_suite(args, torch, kf, S, WL, dev):
+    """Row-resident kernels on rows of 32768 columns (eight float4 per lane per
+    row): fused plans with the geometry the library picks (it halves the rows
+    per group and moves column vectors out of the registers when they would
+    not fit) against the same 16-wave, two-rows-per-group geometry requested
+    explicitly (one JSON line; not the headline)."""
+    n = 32768
+    asked = dict(mat_sched=1, mat_waves=16, mat_group=2, mat_rows=128)
+    cases = [("atax", kf.KF_ROW_MAJOR, {}), ("sgemvt", kf.KF_COL_MAJOR, {}), ("gemver", kf.KF_COL_MAJOR, {}),
+             ("bicgk", kf.KF_ROW_MAJOR, dict(mat_sched=1)), ("gesummv", kf.KF_ROW_MAJOR, dict(mat_sched=1)),
+             ("gemver", kf.KF_ROW_MAJOR, dict(mat_sched=1))]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    res = {}
+    for name, layout, params in cases:
+        q = S.by_name(name, n, n, {"alpha": 1.5, "beta": 0.75}, layout=layout)
+        devin = {k: torch.empty(q.shapes[k], dtype=torch.float32, device=dev).uniform_(-1, 1, generator=gen)
+                 for k in q.inputs}
+        row = {}
+        for key, opts in (("library", params), ("requested", asked)):
+            prog = q.compile(mode="fused", **opts).bind(device=dev, **devin)
+            r, w = prog.bytes()
+            us = prog.time(3, 20)
+            d = json.loads(kf.kf_plan_describe(prog.plan))
+            row[key] = {"us": round(us, 1), "gbps": round((r + w) / us / 1e3, 1),
+                        "kernels": [k["name"] for k in d["kernels"]], "params": [k["params"] for k in d["kernels"]]}
+            del prog
+        key = "%s/%s%s" % (name, "col" if layout == kf.KF_COL_MAJOR else "row", "/sched1" if params else "")
+        row["speedup"] = round(row["requested"]["us"] / row["library"]["us"], 3)
+        res[key] = row
+        log("wide rows %s: library %.1f us, requested %.1f us" % (key, row["library"]["us"], row["requested"]["us"]))
+        del devin
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "row-resident kernels at n = 32768: library geometry vs requested (not the headline)",
+                      "n": n, "requested": asked, "results": res, "unit": "us",
+                      "config": {"workload": "fused ATAX, SGEMVT (column-major), GEMVER (both layouts), BiCGK and "
+                                             "GESUMMV (row-resident schedule), A 32768 x 32768 FP32 uniform[-1, 1)"}}),
+          flush=True)
 
 
 def layout_suite(args, torch, kf, S, WL, dev):
@@ -456,6 +499,9 @@ def main():
         return
     if args.layout:
         layout_suite(args, torch, kf, S, WL, dev)
+        return
+    if args.wide_rows:
+        wide_rows_suite(args, torch, kf, S, WL, dev)
         return
     if args.batched:
         batched_suite(args, torch, kf, WL, dev)

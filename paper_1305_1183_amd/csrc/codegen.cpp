@@ -899,6 +899,17 @@ RowresGeom rowres_geometry(int64_t rows, int64_t cols, const MatParams& p) {
     return g;
 }
 
+// Register budget of a row-resident kernel, in VGPRs per lane, for the values
+// that stay live through a row group: the group's rows that a gemv or gemtv
+// reads (G kp float4 per matrix), the column vectors held in registers and the
+// gemtv accumulators (kp float4 each). Workgroups of 16 waves leave 128 VGPRs per
+// lane; the margin is for addresses, row partials and temporaries.
+static constexpr int kRowresBudgetHeld = 64;   // a gemv and a gemtv: rows held through the group's barrier
+static constexpr int kRowresBudget = 96;       // the others
+static int rowres_pressure(int KP, int G, size_t nmat, size_t ncv_reg, size_t nacc) {
+    return 4 * KP * (G * (int)nmat + (int)ncv_reg + (int)nacc);
+}
+
 static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
                                  const std::vector<int>& part, const MatParams& p0) {
     KernelCode kc;
@@ -907,24 +918,6 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     const int kid = part[calls[0]];
     const Space sp = call_space(s, calls[0]);
     const long M = (long)sp.a, N = (long)sp.b;
-    const RowresGeom geo = rowres_geometry(M, N, p0);
-    const int W = geo.W, WP = geo.WP, KP = geo.KP, G = geo.G;
-    int LG = 0;
-    while ((1 << LG) < G) ++LG;
-    const long CW = 256L * KP;
-    const int NT = 64 * W;
-    const long R = geo.R;
-    const long NB = (M + R - 1) / R;
-    const long NP = (N + 3) / 4 * 4;
-    const bool edge_cols = (long)W * CW > N;
-    // a row group's elements lie within 2^30 floats of its first row: 32-bit offsets
-    long ld_max = 0;
-    for (int c : calls) {
-        const Call& k = s.calls[c];
-        ld_max = std::max<long>(ld_max, (long)s.values[k.in[0]].ld);
-        if (k.op == Op::Ger) ld_max = std::max<long>(ld_max, (long)s.values[k.out].ld);
-    }
-    const bool off32 = (long)G * ld_max + N < (1L << 30);
 
     std::vector<int> mat_in, mat_out, colv, rowv, vec_in, vec_out, gemv_calls, gemtv_calls, scalars;
     auto push_u = [](std::vector<int>& v, int x) {
@@ -951,11 +944,75 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     }
     for (int v : colv) push_u(vec_in, v);
     for (int v : rowv) push_u(vec_in, v);
-    std::vector<int> colv_lds;
-    if (!gemtv_calls.empty() && colv.size() * (size_t)W * CW * 4 <= 128 * 1024) colv_lds = colv;
+
+    RowresGeom geo = rowres_geometry(M, N, p0);
+    const long CW = 256L * geo.KP;
+    // Column-indexed vectors live in registers, KP float4 per lane each, or,
+    // in kernels that also hold gemtv accumulators in registers, in LDS when
+    // all of them fit 128 KiB (one copy per workgroup, zero past N), read at
+    // each use: that keeps the loads of a row group in registers without
+    // spills. (Column-major GEMVER's three vectors stay in registers: with two
+    // of them staged it measured 2% slower.)
+    const size_t vec_lds = (size_t)geo.W * CW * 4;   // bytes of one staged vector
+    std::vector<int> colv_lds, colv_glob;
+    if (!gemtv_calls.empty() && colv.size() * vec_lds <= 128 * 1024) colv_lds = colv;
+    // Wider rows (more float4 per lane) or more operands than the registers
+    // hold would spill to scratch memory, private to each lane and re-read
+    // every group. Over the budget, G is halved first; then column vectors
+    // are staged in LDS while they fit 128 KiB, and the rest are loaded from
+    // global memory at each use (every workgroup reads the same vector: L2
+    // hits). A kernel with both a gemv and a gemtv holds its rows through the
+    // group's barrier, so its budget is lower.
+    // Only a geometry the library picks itself is adjusted; requested
+    // parameters are generated as asked.
+    const bool auto_geo = p0.waves <= 0 && p0.group <= 0 && p0.rows <= 0;
+    // rows a group holds: the matrices (loaded or made by ger) that a gemv or
+    // a gemtv reads, and one more array while ger results are formed from
+    // their loaded inputs
+    std::vector<int> held;
+    bool has_ger = false;
+    for (int c : calls) {
+        if (s.calls[c].op != Op::Ger) push_u(held, s.calls[c].in[0]);
+        else has_ger = true;
+    }
+    const size_t nheld = std::max<size_t>(1, held.size() + (has_ger ? 1 : 0));
+    auto ncv_reg = [&]() { return colv.size() - colv_lds.size() - colv_glob.size(); };
+    auto pressure = [&]() { return rowres_pressure(geo.KP, geo.G, nheld, ncv_reg(), gemtv_calls.size()); };
+    const int budget = !gemv_calls.empty() && !gemtv_calls.empty() ? kRowresBudgetHeld : kRowresBudget;
+    if (auto_geo && pressure() > budget) {
+        while (geo.G > 1 && pressure() > budget) {
+            MatParams q = p0;
+            q.group = geo.G / 2;
+            geo = rowres_geometry(M, N, q);
+        }
+        for (int v : colv) {
+            if (pressure() <= budget) break;
+            if (std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end()) continue;
+            if ((colv_lds.size() + 1) * vec_lds <= 128 * 1024) colv_lds.push_back(v);
+            else colv_glob.push_back(v);
+        }
+    }
+    const int W = geo.W, WP = geo.WP, KP = geo.KP, G = geo.G;
+    int LG = 0;
+    while ((1 << LG) < G) ++LG;
+    const int NT = 64 * W;
+    const long R = geo.R;
+    const long NB = (M + R - 1) / R;
+    const long NP = (N + 3) / 4 * 4;
+    const bool edge_cols = (long)W * CW > N;
+    // a row group's elements lie within 2^30 floats of its first row: 32-bit offsets
+    long ld_max = 0;
+    for (int c : calls) {
+        const Call& k = s.calls[c];
+        ld_max = std::max<long>(ld_max, (long)s.values[k.in[0]].ld);
+        if (k.op == Op::Ger) ld_max = std::max<long>(ld_max, (long)s.values[k.out].ld);
+    }
+    const bool off32 = (long)G * ld_max + N < (1L << 30);
     auto cvx = [&](int v) {
-        return std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end() ? F("xs%d[(cb >> 2) + 64u * j]", v)
-                                                                                 : F("cv%d[j]", v);
+        if (std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end()) return F("xs%d[(cb >> 2) + 64u * j]", v);
+        if (std::find(colv_glob.begin(), colv_glob.end(), v) != colv_glob.end())
+            return F("kf_ld4_tail(V%d, (long)(cbg + 256u * j), N)", v);
+        return F("cv%d[j]", v);
     };
     const bool col_part = !gemtv_calls.empty() && NB > 1;
     std::map<int, size_t> ws_off;
@@ -1000,13 +1057,8 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
                                           : F("const float %s = *P%d;", scal_name(v).c_str(), v));
     // column of lane's float4 j: cb + 256 j (32-bit: rows are at most 32768 columns)
     e.l("const unsigned cb = (unsigned)(wave * CW + lane * 4);");
-    // Column-indexed vectors live in registers, KP float4 per lane each, or,
-    // in kernels that also hold gemtv accumulators in registers, in LDS when
-    // all of them fit 128 KiB (one copy per workgroup, zero past N), read at
-    // each use: that keeps the loads of a row group in registers without
-    // spills. (Column-major GEMVER's three vectors stay in registers: with two
-    // of them staged it measured 2% slower.)
     for (int v : colv) {
+        if (std::find(colv_glob.begin(), colv_glob.end(), v) != colv_glob.end()) continue;
         if (std::find(colv_lds.begin(), colv_lds.end(), v) != colv_lds.end()) {
             e.l(F("__shared__ kf_f4 xs%d[W * KP * 64];", v));
             e.l(F("for (int i = tid; i < W * KP * 64; i += NT) xs%d[i] = kf_ld4_tail(V%d, 4L * i, N);", v, v));
@@ -1115,6 +1167,10 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     };
     e.l("for (long g0 = r0; g0 < r1; g0 += G) {");
     e.ind++;
+    // column vectors read from global memory: an offset the compiler cannot
+    // prove constant across groups, so that it does not hoist their loads out
+    // of the loop into registers (the spill this placement avoids)
+    if (!colv_glob.empty()) e.l("unsigned cbg = cb; asm volatile(\"\" : \"+v\"(cbg));");
     e.l(edge_cols ? "if (false) {" : "if (g0 + G <= r1) {");
     e.ind++;
     emit_group(false);
