@@ -2,7 +2,7 @@
 uses, from chunks collected by ``plansearch collect``:
 
     python -m paper_1305_1183_amd.data.make_plansearch_subset OUT.npz CHUNK.npz ... \\
-        --train 0:40 --eval 150:160
+        --train 0:70 --eval 150:170
 
 It keeps, for the training scripts, one feature row and the median measured
 time per unique kernel, and for the evaluation scripts the measured time of
@@ -26,8 +26,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("out")
     ap.add_argument("chunks", nargs="+")
-    ap.add_argument("--train", default="0:40")
-    ap.add_argument("--eval", default="150:160")
+    ap.add_argument("--train", default="0:70")
+    ap.add_argument("--eval", default="150:170")
     ap.add_argument("--launch-us", type=float, default=None,
                     help="per-launch term of a plan's time (default: fitted on the training scripts' timings)")
     a = ap.parse_args(argv)

@@ -94,7 +94,13 @@ def cmd_evaluate(a):
     table = None
     if a.table:
         T = json.load(open(a.table))
-        table = kf.routine_table([(e[0], tuple(e[1])) + tuple(e[2:]) for e in T["entries"]])
+        entries = T["entries"]
+        if a.strip_table:
+            # the additive predictor without the row-resident environment and the
+            # extra-LDS axis: row-resident kernels are then priced with the first
+            # strip environment's routines
+            entries = [e for e in entries if e[0] != 2 and (len(e) < 5 or e[4] == 0)]
+        table = kf.routine_table([(e[0], tuple(e[1])) + tuple(e[2:]) for e in entries])
     per, summary = [], {}
     for seed in evals:
         m = np.where(data["cand_seed"] == seed)[0]
@@ -289,6 +295,8 @@ def main(argv=None):
     e = sub.add_parser("evaluate")
     e.add_argument("--data", nargs="+", required=True)
     e.add_argument("--table", default="")
+    e.add_argument("--strip-table", action="store_true",
+                   help="keep only the table's strip and BLAS-1 environments without extra LDS (ablation)")
     e.add_argument("--train", default="0:150")
     e.add_argument("--eval", default="150:200")
     e.add_argument("--out", required=True)

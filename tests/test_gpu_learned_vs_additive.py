@@ -1,10 +1,10 @@
 """What the learned cost model gains over the paper's additive predictor.
 
 The MLP is trained on the GPU by the library's own kernels on measured
-kernel times of 40 random scripts (a stored subset of the plan-search study),
-then both predictors rank the measured candidate plans of 10 other scripts.
+kernel times of 70 random scripts (a stored subset of the plan-search study),
+then both predictors rank the measured candidate plans of 20 other scripts.
 The regret of a predictor is how much slower its top-ranked plan ran than the
-best measured plan."""
+best measured plan; the learned ranking must be better in mean and median."""
 import json
 import os
 
@@ -23,7 +23,7 @@ def test_learned_model_beats_additive_predictor():
     from paper_1305_1183_amd.costmodel import CostModel
     d = np.load(os.path.join(DATA, "plansearch_subset.npz"), allow_pickle=False)
     cm = CostModel(seed=0)
-    hist = cm.fit(d["X"], d["y"], epochs=60, batch=256, lr=1e-3, seed=0)
+    hist = cm.fit(d["X"], d["y"], epochs=150, batch=256, lr=1e-3, seed=0)
     cm.set_launch_us(float(d["launch_us"]))   # plan time = sum of kernels + launch term per launch
     assert hist[-1] < hist[0]
     T = json.load(open(os.path.join(DATA, "routine_table.json")))
@@ -45,6 +45,8 @@ def test_learned_model_beats_additive_predictor():
         reg_l.append(SE.rank_metrics(true, learned)["regret_top1"])
         reg_a.append(SE.rank_metrics(true, additive)["regret_top1"])
         print("script %d: learned regret %.3f, additive regret %.3f" % (seed, reg_l[-1], reg_a[-1]), flush=True)
-    print("mean regret: learned %.3f, additive %.3f" % (np.mean(reg_l), np.mean(reg_a)), flush=True)
+    print("mean regret: learned %.3f, additive %.3f; median: learned %.3f, additive %.3f" %
+          (np.mean(reg_l), np.mean(reg_a), np.median(reg_l), np.median(reg_a)), flush=True)
     assert np.mean(reg_l) < np.mean(reg_a)
-    assert np.mean(reg_l) <= 0.10
+    assert np.median(reg_l) < np.median(reg_a)
+    assert np.mean(reg_l) <= 0.06
