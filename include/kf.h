@@ -400,8 +400,10 @@ kf_status kf_time_plan_kernels(kf_plan* p, void* stream, int32_t warmup, int32_t
 kf_status kf_plan_kernel_params(const kf_plan* p, int32_t k, kf_impl_params* out);
 
 /* ---- introspection -------------------------------------------------------- */
-/* JSON description (kernels, calls, parameters, grid, bytes). Writes at most
- * cap bytes (NUL-terminated) and the needed size to *needed. */
+/* JSON description (kernels, calls, parameters, grid, bytes). Row-resident
+ * kernels also report "register_estimate" (VGPRs per lane a row group keeps
+ * live, as the generator estimates it) and "over_register_budget". Writes at
+ * most cap bytes (NUL-terminated) and the needed size to *needed. */
 kf_status kf_plan_describe(const kf_plan* p, char* buf, size_t cap, size_t* needed);
 /* Algorithmic HBM bytes of one run: every operand counted once per kernel
  * that reads or writes it in HBM (the paper's "really transferred" bytes,
@@ -466,7 +468,11 @@ kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols,
  * finishing launch; summed over kernels. Entries are matched on class and
  * environment, then the nearest extra LDS (row-resident kernels use the cls 2
  * entries; a table without any prices them with its first BLAS-2
- * environment); KF_ERR_UNSUPPORTED if a needed entry is missing. */
+ * environment); KF_ERR_UNSUPPORTED if a needed entry is missing. A kernel
+ * over the generator's register budget ("over_register_budget" in
+ * kf_plan_describe) gets 1e9 us added, so that it ranks after every
+ * implementation within budget (Section 4.2 prunes implementations that need
+ * more on-chip memory than another of the same fusion). */
 kf_status kf_predict_additive(const kf_plan* p, const kf_routine_entry* table, int32_t n,
                               float* us);
 

@@ -1280,8 +1280,13 @@ static KernelCode gen_mat_rowres(const Script& s, const std::vector<int>& calls,
     }
     kc.source = head.str();
     kc.lds_bytes = 16 + rowv.size() * (size_t)R * 4 + (size_t)ngv * 2 * G * WP * 4 + colv_lds.size() * (size_t)W * CW * 4;
-    kc.params_json = F("{\"schedule\": \"row-resident\", \"waves\": %d, \"group\": %d, \"rows\": %ld, \"kp\": %d, \"row_blocks\": %ld}",
-                       W, G, R, KP, NB);
+    // vectors loaded from global memory count too: the loads of a group are
+    // all in flight together
+    kc.reg_estimate = rowres_pressure(KP, G, nheld, ncv_reg() + colv_glob.size(), gemtv_calls.size());
+    kc.over_budget = kc.reg_estimate > budget;
+    kc.params_json = F("{\"schedule\": \"row-resident\", \"waves\": %d, \"group\": %d, \"rows\": %ld, \"kp\": %d, \"row_blocks\": %ld, "
+                       "\"register_estimate\": %d, \"over_register_budget\": %s}",
+                       W, G, R, KP, NB, kc.reg_estimate, kc.over_budget ? "true" : "false");
     kernel_bytes(s, calls, part, &kc.bytes_read, &kc.bytes_written);
     return kc;
 }

@@ -128,6 +128,11 @@ struct KernelCode {
     std::string params_json;
     std::vector<int> calls;
     bool mat = false;
+    // Row-resident kernels: the generator's estimate of the VGPRs per lane a row
+    // group keeps live, and whether it exceeds the register budget (such a
+    // kernel likely spills to scratch memory)
+    int reg_estimate = 0;
+    bool over_budget = false;
 };
 KernelCode generate_kernel(const Script& s, const std::vector<int>& calls,
                            const std::vector<int>& part, const MatParams& mp,

@@ -120,6 +120,10 @@ kf_status kf_routine_time(int32_t routine, int64_t rows, int64_t cols, const kf_
 
 namespace {
 
+// Added to the additive prediction of a kernel over the register budget: far
+// above any real plan time, so such implementations are effectively pruned
+constexpr double kOverBudgetUs = 1e9;
+
 // Additive prediction of one kernel of a plan: max(t_t, t_c) plus the
 // finishing launches (Section 4.2), with the kernel's own parameters.
 kf_status predict_kernel_additive(const kf_plan* p, const PlanKernel& pk, const kf_routine_entry* table, int32_t n,
@@ -188,6 +192,12 @@ kf_status predict_kernel_additive(const kf_plan* p, const PlanKernel& pk, const 
         if (!e) return set_error(KF_ERR_UNSUPPORTED, "routine table has no FINISH entry for this environment");
         t += (double)(kc.launches.size() - 1) * e->us_per_unit;
     }
+    // Section 4.2 prunes fusion implementations that need more on-chip memory
+    // than another implementation of the same fusion. On gfx950 the on-chip
+    // memory a row-resident kernel outgrows is its registers: an implementation
+    // over the register budget ranks after every one within it (the routine
+    // times, probed one routine at a time, cannot show its spills).
+    if (kc.over_budget) t += kOverBudgetUs;
     *us = t;
     return KF_OK;
 }

@@ -223,14 +223,40 @@ def kf_version() -> str:
 
 
 # ---- script recording --------------------------------------------------------
-def kf_script_create():
+class Script:
+    """Owning handle of a kf_script, passed to the C calls as its pointer. The
+    script is destroyed when the last reference to the handle goes (or by
+    kf_script_destroy), so an owner that is collected early (a temporary
+    sequence object) cannot free a script that a call is still using."""
+
+    def __init__(self, h):
+        self._as_parameter_ = h
+
+    def destroy(self) -> None:
+        h = self._as_parameter_
+        self._as_parameter_ = _vp()
+        if h.value:
+            lib().kf_script_destroy(h)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def kf_script_create() -> Script:
     h = _vp()
     _chk(lib().kf_script_create(ctypes.byref(h)))
-    return h
+    return Script(h)
 
 
 def kf_script_destroy(s) -> None:
-    lib().kf_script_destroy(s)
+    """Destroy now (later calls on the handle get a null script: KF_ERR_ARG)."""
+    if isinstance(s, Script):
+        s.destroy()
+    else:
+        lib().kf_script_destroy(s)
 
 
 def _new(fn, *args) -> int:

@@ -29,12 +29,6 @@ class RandomScript:
     outputs: dict = field(default_factory=dict)   # value id -> shape tuple
     calls: list = field(default_factory=list)     # op names in recording order
 
-    def __del__(self):
-        try:
-            kf.kf_script_destroy(self.script)
-        except Exception:
-            pass
-
     def describe(self) -> str:
         return "seed %d n=%d vec=%d calls=%s" % (self.seed, self.n_mat, self.n_vec, ",".join(self.calls))
 

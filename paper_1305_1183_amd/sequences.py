@@ -35,12 +35,8 @@ class Sequence:
     consts: dict = field(default_factory=dict)       # name -> (kf_value, float)
     shapes: dict = field(default_factory=dict)       # name -> tuple
 
-    def __del__(self):
-        try:
-            if self.script is not None:
-                kf.kf_script_destroy(self.script)
-        except Exception:
-            pass
+    # the script handle (kf.Script) destroys the script when its last
+    # reference goes, which may outlive this object
 
     def compile(self, mode="fused", **opts) -> "Program":
         plan = kf.kf_compile(self.script, mode=mode, **opts)

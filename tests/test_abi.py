@@ -268,3 +268,16 @@ def test_noalloc_entry_checks_before_any_gpu_call():
         assert kf.lib().kf_run_noalloc(p, None) == kf.KF_ERR_STATE
     finally:
         kf.kf_plan_destroy(p)
+
+
+def test_script_handle_outlives_its_sequence():
+    """The Python handle owns the script: compiling from the handle of a
+    temporary sequence object (collected before the call runs) is safe, and a
+    destroyed handle reaches the library as a null script (KF_ERR_ARG)."""
+    p = kf.kf_compile(S.bicgk(64, 96).script, mode="fused", flags=kf.KF_COMPILE_CODEGEN_ONLY)
+    assert kf.kf_plan_num_kernels(p) == 1
+    kf.kf_plan_destroy(p)
+    s = S.bicgk(64, 96).script
+    kf.kf_script_destroy(s)
+    assert err(kf.kf_compile, s) == "KF_ERR_ARG"
+    kf.kf_script_destroy(s)                      # a second destroy does nothing

@@ -181,3 +181,30 @@ def test_additive_mode_grid_takes_row_resident_environments():
                       flags=kf.KF_COMPILE_CODEGEN_ONLY)
     assert kf.kf_plan_kernel_params(p, 0).get("mat_sched") == 1
     kf.kf_plan_destroy(p)
+
+
+def test_additive_ranks_implementations_over_the_register_budget_last():
+    """Section 4.2 prunes implementations that need more on-chip memory than
+    another implementation of the same fusion. A row-resident kernel the
+    generator marks over its register budget (column-major GEMVER at 32768
+    columns) gets 1e9 us added; the same fusion within budget (16384 columns)
+    and single-pass ATAX at 32768 columns do not."""
+    import json
+    env = (0, 0, 0, 0)
+    T = kf.routine_table([(2, env, r, 1e-9, 0) for r in range(5)] + [(2, env, 10, 3.0, 0)])
+
+    def plan(name, m, n, layout):
+        q = S.by_name(name, m, n, {"alpha": 1.5, "beta": 0.75}, layout=layout)   # keeps the script alive
+        p = kf.kf_compile(q.script, mode="fused", flags=kf.KF_COMPILE_CODEGEN_ONLY)
+        (k,) = json.loads(kf.kf_plan_describe(p))["kernels"]
+        return p, k["params"]
+
+    p, prm = plan("gemver", 32768, 256, kf.KF_COL_MAJOR)
+    assert prm["over_register_budget"] and prm["register_estimate"] > 96
+    assert kf.kf_predict_additive(p, T) >= 1e9
+    kf.kf_plan_destroy(p)
+    for args in (("gemver", 16384, 256, kf.KF_COL_MAJOR), ("atax", 256, 32768, kf.KF_ROW_MAJOR)):
+        p, prm = plan(*args)
+        assert not prm["over_register_budget"]
+        assert kf.kf_predict_additive(p, T) < 1e6
+        kf.kf_plan_destroy(p)
