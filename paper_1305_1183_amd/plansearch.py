@@ -204,8 +204,9 @@ def cmd_evaluate(a):
 
 def cmd_modes(a):
     """kf_compile's ranking modes end to end on random scripts (GPU): the
-    learned mode (top-1 and timed top-k) against the exhaustive mode, both
-    combining kernel implementations; plan time and search time of each."""
+    learned mode (top-1 and timed top-k) and, given a routine table, the
+    additive mode against the exhaustive mode, all combining kernel
+    implementations; plan time and search time of each."""
     import torch
     from . import kf
     from . import randscript as R
@@ -214,16 +215,24 @@ def cmd_modes(a):
 
     cm = CostModel.load(a.model)
     cm.predict_log(np.zeros((1, kf.FEATURE_DIM), np.float32))   # device state of the model set up once
+    table = None
+    if a.table:
+        T = json.load(open(a.table))
+        table = kf.routine_table([(e[0], tuple(e[1])) + tuple(e[2:]) for e in T["entries"]])
     st = torch.cuda.current_stream().cuda_stream
     per = []
+    ranked = ["learned_top1", "learned_top%d" % a.topk] + (["additive"] if table is not None else [])
     for seed in _range(a.eval):
         rs = R.random_script(seed)
         inst = SE.Instance(rs)
         bind = {v: t.data_ptr() for v, t in inst.t.items()}
         row = {"seed": seed, "script": rs.describe()}
-        for key, kw in (("learned_top1", dict(mode="learned", model=cm.handle, top_k=0)),
-                        ("learned_top%d" % a.topk, dict(mode="learned", model=cm.handle, top_k=a.topk, bind=bind)),
-                        ("exhaustive", dict(mode="exhaustive", bind=bind))):
+        modes = [("learned_top1", dict(mode="learned", model=cm.handle, top_k=0)),
+                 ("learned_top%d" % a.topk, dict(mode="learned", model=cm.handle, top_k=a.topk, bind=bind))]
+        if table is not None:
+            modes.append(("additive", dict(mode="additive", table=table)))
+        modes.append(("exhaustive", dict(mode="exhaustive", bind=bind)))
+        for key, kw in modes:
             # every mode compiles from scratch: its own empty disk cache, no loaded modules
             os.environ["KF_CACHE_DIR"] = os.path.join(a.cache, "s%d_%s" % (seed, key))
             os.makedirs(os.environ["KF_CACHE_DIR"], exist_ok=True)
@@ -236,7 +245,7 @@ def cmd_modes(a):
             us = kf.kf_time_plan(plan, st, 3, 20)
             row[key] = {"plan_us": us, "search_s": search_s, "kernels": kf.kf_plan_num_kernels(plan)}
             kf.kf_plan_destroy(plan)
-        for key in ("learned_top1", "learned_top%d" % a.topk):
+        for key in ranked:
             row[key]["regret"] = row[key]["plan_us"] / row["exhaustive"]["plan_us"] - 1.0
         per.append(row)
         print("script %d: learned %.1f us (%.2f s), top-%d %.1f us (%.2f s), exhaustive %.1f us (%.2f s)" %
@@ -248,7 +257,7 @@ def cmd_modes(a):
         kf.kf_jit_release()
     summary = {}
     exh_s = sum(r["exhaustive"]["search_s"] for r in per)
-    for key in ("learned_top1", "learned_top%d" % a.topk):
+    for key in ranked:
         rg = np.array([r[key]["regret"] for r in per])
         summary[key] = {"mean_regret": float(rg.mean()), "median_regret": float(np.median(rg)),
                         "frac_within_5pct": float(np.mean(rg <= 0.05)),
@@ -309,6 +318,7 @@ def main(argv=None):
     md = sub.add_parser("modes")
     md.add_argument("--eval", default="150:160")
     md.add_argument("--model", required=True)
+    md.add_argument("--table", default="", help="routine table: also run the additive mode")
     md.add_argument("--out", required=True)
     md.add_argument("--topk", type=int, default=3)
     md.add_argument("--max-partitions", type=int, default=16)
