@@ -80,3 +80,18 @@ def test_requested_geometry_is_kept():
     (params, src), = _row_kernels(prog)
     assert params["group"] == 2 and "cbg" not in src
     SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))
+
+
+@pytest.mark.parametrize("name", ["gemver", "atax"])
+def test_wide_rows_with_padded_leading_dimension(name):
+    """Rows of 32760 columns stored 32776 floats apart, the padding NaN (a
+    read of it would reach the results): the adjusted geometry's loads and
+    column-vector reads stay within each row's columns."""
+    m, n, ld = 67, 32760, 32776
+    arrays, scal = WL.make(name, m, n, seed=WL.seed_for(43, name), ld=ld)
+    params = dict(mat_sched=1) if name == "gemver" else {}
+    q, prog, host = SC.run_gpu(name, m, n, arrays, scal, mode="fused", ld=ld, **params)
+    assert "g1" in _markers(prog)
+    if name == "gemver":
+        assert "global" in _markers(prog)
+    SC.check_against_oracle(name, m, n, host, SC.oracle_outputs(name, arrays, scal, n))
