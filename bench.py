@@ -438,6 +438,12 @@ def precision_compact(args, torch, kf, S, WL, dev):
             prog = q.compile(mode="fused", **WL.PREC_TUNED.get((name, fmt), {})).bind(device=dev, **devin)
             outs = prog.run()
             torch.cuda.synchronize()
+            # about 0.3 s of the plan before timing, as in --precision: right after
+            # the input upload the first timings run up to 8% slow
+            t_end = time.time() + 0.3
+            while time.time() < t_end:
+                prog.run()
+                torch.cuda.synchronize()
             r, w = prog.bytes()
             us = prog.time(3, 10)
             row = {"us": round(us, 1), "gbps": round((r + w) / us / 1e3, 1),
