@@ -208,3 +208,24 @@ def test_additive_ranks_implementations_over_the_register_budget_last():
         assert not prm["over_register_budget"]
         assert kf.kf_predict_additive(p, T) < 1e6
         kf.kf_plan_destroy(p)
+
+
+def test_additive_mode_avoids_a_kernel_over_the_register_budget():
+    """KF_MODE_ADDITIVE with row-resident routines far cheaper than the strip
+    ones: column-major GEMVER at 32768 columns still does not take its
+    one-kernel plan (a row-resident kernel over the register budget) but a
+    plan whose kernels are all within budget; at 16384 columns the one-kernel
+    plan is within budget and is taken."""
+    import json
+    env = (0, 0, 0, 0)
+    strip = [(1, ENV, r, 1e-3, 0) for r in range(5)] + [(1, ENV, 10, 4.0, 0)]
+    rowres = [(2, env, r, 1e-9, 0) for r in range(5)] + [(2, env, 10, 4.0, 0)]
+    vec = [(0, (4, 256, 64, 0), r, 1e-7, 0) for r in range(5, 11)]
+    T = kf.routine_table(strip + rowres + vec)
+    for m, one_kernel in ((32768, False), (16384, True)):
+        q = S.by_name("gemver", m, 256, {"alpha": 1.5, "beta": 0.75}, layout=kf.KF_COL_MAJOR)
+        p = kf.kf_compile(q.script, mode="additive", table=T, flags=kf.KF_COMPILE_CODEGEN_ONLY)
+        ks = json.loads(kf.kf_plan_describe(p))["kernels"]
+        assert all(not k["params"].get("over_register_budget", False) for k in ks), ks
+        assert (len(ks) == 1) == one_kernel, [k["params"] for k in ks]
+        kf.kf_plan_destroy(p)
